@@ -1,0 +1,164 @@
+/*
+ * slimvdb.h -- C ABI of the MI355X (gfx950) semantic TSDF integrator.
+ *
+ * The library fuses posed, semantically labelled point clouds into a sparse
+ * voxel map of 8x8x8-voxel leaves, as the SLIM-VDB method does (arXiv
+ * 2512.12945): per point, a voxel walk over the truncation band around the
+ * point along its sensor ray (Sec. III-A), the running weighted TSDF mean and
+ * weight (Eq. (1)-(2), weight 1), and the conjugate Bayesian semantic update,
+ * closed set (Dirichlet concentrations, Thm. 1 / Eq. (6)) or open set
+ * (Normal-Inverse-Gamma statistics with lambda = 2 nu = W and a diagonal beta,
+ * Thm. 2 / Eqs. (11)-(14) and Sec. III-D).  All compute runs in HIP kernels on
+ * the map's GPU; this header needs no HIP or torch include.
+ *
+ * Conventions shared by every call
+ *   - Every function returns a slim_status: SLIM_OK (0) or a negative error.
+ *     A failing call leaves a message for slim_last_error() (thread-local)
+ *     and never throws.
+ *   - "dev" pointers are device memory on the map's GPU; "host" pointers are
+ *     ordinary CPU memory.  The caller owns every buffer it passes and keeps
+ *     it valid until the work queued on `stream` has finished.  The library
+ *     owns the map's own device memory.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *     Work is queued asynchronously unless the description says the call
+ *     synchronises.  One map must be used from one stream at a time.
+ *   - Voxel keys are integer voxel coordinates k = floor(x / voxel_size) per
+ *     axis, valid for |k| < 2^20.  A voxel's centre is (k + 1/2) voxel_size.
+ *     Its leaf is floor(k / 8) per axis; its offset in the leaf is k mod 8.
+ */
+#ifndef SLIMVDB_H
+#define SLIMVDB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t slim_status;
+#define SLIM_OK 0
+#define SLIM_ERR_INVALID (-1)     /* bad argument or configuration; nothing queued */
+#define SLIM_ERR_CAPACITY (-2)    /* a frame needed more leaves or voxels than configured */
+#define SLIM_ERR_DEVICE (-3)      /* a HIP runtime call failed */
+#define SLIM_ERR_UNSUPPORTED (-4) /* valid request this build does not handle */
+
+/* semantic model of a map */
+#define SLIM_SEM_NONE 0   /* geometry only: D and W */
+#define SLIM_SEM_CLOSED 1 /* K Dirichlet class counts per voxel (Sec. III-C) */
+#define SLIM_SEM_OPEN 2   /* L-dim NIG mean m and diagonal beta per voxel (Sec. III-D) */
+
+/* layout of the per-point semantic input of slim_integrate */
+#define SLIM_IN_NONE 0      /* no semantics (SLIM_SEM_NONE maps) */
+#define SLIM_IN_LABEL_I32 1 /* int32[N]: class index; a one-hot observation (Eq. (6)) */
+#define SLIM_IN_PROB_F32 2  /* float[N x K] row-major: class probabilities, added as expected counts */
+#define SLIM_IN_LOGIT_F32 3 /* float[N x K] row-major: logits, softmax taken per point (K <= 64) */
+#define SLIM_IN_EMB_BF16 4  /* uint16[N x L] row-major bfloat16 embedding (open set) */
+#define SLIM_IN_EMB_F32 5   /* float[N x L] row-major embedding (open set) */
+
+typedef struct slim_map slim_map; /* opaque */
+
+typedef struct slim_map_config {
+    float voxel_size;   /* edge of a voxel in metres, > 0 */
+    float sdf_trunc;    /* truncation distance tau in metres, >= voxel_size */
+    float min_range;    /* points closer than this to the sensor are rejected, >= 0 */
+    float max_range;    /* points farther than this are rejected, > min_range */
+    int32_t sem_mode;   /* SLIM_SEM_* */
+    int32_t num_classes;/* K, 1..256, closed set only */
+    int32_t embed_dim;  /* L, 1..1024, open set only */
+    int32_t device;     /* HIP device ordinal that holds the map */
+    int64_t max_leaves; /* capacity in 8^3 leaves, 1 .. 2^26 */
+    int64_t max_voxels; /* capacity in voxel records, 1 .. 2^31 - 1 */
+} slim_map_config;
+
+typedef struct slim_stats {
+    int64_t leaves;              /* leaves allocated */
+    int64_t voxels;              /* voxels with W > 0 */
+    int64_t points_last;         /* points passed to the last slim_integrate */
+    int64_t rejected_last;       /* of those, rejected (non-finite, out of range, bad label, key range) */
+    int64_t pairs_last;          /* voxel updates (point, voxel) of the last frame */
+    int64_t touched_leaves_last; /* leaves the last frame touched */
+    int64_t new_leaves_last;     /* leaves it created */
+    int64_t voxels_old_last;     /* voxels it updated that already existed */
+    int64_t voxels_new_last;     /* voxels it created */
+    int32_t status_last;         /* SLIM_OK, or the error the last frame hit on the GPU */
+    int32_t reserved;
+} slim_stats;
+
+/* Creates an empty map on config->device.  Allocates every device buffer the
+ * configured capacity needs (leaf table, leaf index, voxel records).  *out
+ * receives the handle.  SLIM_ERR_INVALID on a bad configuration,
+ * SLIM_ERR_DEVICE if allocation fails. */
+slim_status slim_map_create(const slim_map_config *config, slim_map **out);
+
+/* Frees the map after waiting for all work on its device.  NULL is a no-op. */
+slim_status slim_map_destroy(slim_map *map);
+
+/* Empties the map (no leaves, no voxels) and keeps its capacity.  Queued on
+ * `stream`. */
+slim_status slim_map_reset(slim_map *map, void *stream);
+
+/* Integrates one frame (Sec. III-A to III-D): for each of the n points,
+ * points_dev[3 i .. 3 i + 2] (float, sensor frame, metres), the band walk of
+ * the ray from the sensor origin, the TSDF update of every voxel on it whose
+ * signed distance exceeds -sdf_trunc, and the semantic update of the same
+ * voxels with the same unit weight.  pose_host is map_T_sensor, 4x4 row-major
+ * double; the sensor origin is its translation.  sem_dev holds the per-point
+ * semantics in the layout sem_kind names (NULL for SLIM_IN_NONE).
+ * Per-voxel results equal one batch update per voxel with all of the frame's
+ * observations of that voxel, which is what the paper's per-point recursion
+ * reaches (Thm. 1 and 2 are stated for sets); observations are combined in
+ * point order, so repeated runs are bitwise identical.
+ * Rejected points (non-finite, range outside [min_range, max_range], label
+ * outside [0, K), a walk leaving |k| < 2^20) contribute nothing and are
+ * counted.  Requires n < 2^23.  Queued on `stream`; the frame is applied
+ * entirely or not at all: if it needs more leaves or voxels than configured,
+ * the map is left unchanged and the next slim_map_stats reports
+ * SLIM_ERR_CAPACITY.  Synchronous validation errors return SLIM_ERR_INVALID
+ * with nothing queued. */
+slim_status slim_integrate(slim_map *map, const float *points_dev, int64_t n, const double *pose_host,
+                           const void *sem_dev, int32_t sem_kind, void *stream);
+
+/* Synchronises `stream` and copies the map's counters to *out_host.  Returns
+ * the first asynchronous error since the previous call (then cleared), else
+ * SLIM_OK. */
+slim_status slim_map_stats(slim_map *map, slim_stats *out_host, void *stream);
+
+/* Exports every voxel with W > 0, ordered by leaf coordinate (x, then y, then
+ * z) and, inside a leaf, by offset (x, then y, then z).  Synchronises
+ * `stream`.  *count_host receives the voxel count M.  With capacity == 0 only
+ * the count is returned.  Otherwise capacity must be >= M, and the call
+ * writes keys_dev (int32 [M x 3] voxel coordinates), d_dev and w_dev (float
+ * [M] TSDF and weight) and, unless NULL, sem_dev (float [M x S]: the K class
+ * counts, or the L means followed by the L betas; S = 0 for geometry-only
+ * maps).  Counts c are stored without prior: the Dirichlet posterior is
+ * alpha0 + c and its predictive is (alpha0 + c_i) / (K alpha0 + sum c)
+ * (Eq. (7)).  Any async error pending on the map is returned first. */
+slim_status slim_extract(slim_map *map, int64_t capacity, int32_t *keys_dev, float *d_dev, float *w_dev,
+                         float *sem_dev, int64_t *count_host, void *stream);
+
+/* Looks up the voxels holding m world points xyz_dev (float [m x 3]) and
+ * writes their state: d_dev, w_dev (float [m]) and, unless NULL, sem_dev
+ * (float [m x S]).  Unobserved voxels, and points with non-finite or
+ * out-of-range coordinates, read as all zeros (W = 0).  Queued on `stream`. */
+slim_status slim_query(slim_map *map, const float *xyz_dev, int64_t m, float *d_dev, float *w_dev, float *sem_dev,
+                       void *stream);
+
+/* Kernel timing.  While enabled, slim_integrate brackets each of its kernels
+ * with HIP events on the stream it launches on; slim_profile_read returns the
+ * accumulated per-kernel time in milliseconds and launch counts (index 0 ray
+ * walk and emission, 1 leaf planning, 2 pair bucketing, 3 leaf sort, reduce
+ * and combine) and resets them.  Reading synchronises `stream`.  n_kernels
+ * is the length of ms_host and launches_host; the call writes
+ * min(n_kernels, 4) entries. */
+slim_status slim_profile_enable(slim_map *map, int32_t enable);
+slim_status slim_profile_read(slim_map *map, double *ms_host, int64_t *launches_host, int32_t n_kernels,
+                              void *stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *slim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLIMVDB_H */

@@ -1,0 +1,162 @@
+"""Python binding of libslimvdb (include/slimvdb.h): argument marshalling only.
+
+Every step of integration, extraction and lookup runs in the library's HIP
+kernels.  torch provides device memory and the current stream; nothing here
+computes on the data.  If the library is not built, using this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libslimvdb.so")
+
+OK, ERR_INVALID, ERR_CAPACITY, ERR_DEVICE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+SEM_NONE, SEM_CLOSED, SEM_OPEN = 0, 1, 2
+IN_NONE, IN_LABEL_I32, IN_PROB_F32, IN_LOGIT_F32, IN_EMB_BF16, IN_EMB_F32 = range(6)
+KERNELS = ("ray_walk_emit", "leaf_plan", "pair_bucket", "leaf_apply")
+
+EXPORTS = ("slim_map_create", "slim_map_destroy", "slim_map_reset", "slim_integrate", "slim_map_stats",
+           "slim_extract", "slim_query", "slim_profile_enable", "slim_profile_read", "slim_last_error")
+
+
+class MapConfig(ctypes.Structure):
+    _fields_ = [("voxel_size", ctypes.c_float), ("sdf_trunc", ctypes.c_float), ("min_range", ctypes.c_float),
+                ("max_range", ctypes.c_float), ("sem_mode", ctypes.c_int32), ("num_classes", ctypes.c_int32),
+                ("embed_dim", ctypes.c_int32), ("device", ctypes.c_int32), ("max_leaves", ctypes.c_int64),
+                ("max_voxels", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("leaves", ctypes.c_int64), ("voxels", ctypes.c_int64), ("points_last", ctypes.c_int64),
+                ("rejected_last", ctypes.c_int64), ("pairs_last", ctypes.c_int64),
+                ("touched_leaves_last", ctypes.c_int64), ("new_leaves_last", ctypes.c_int64),
+                ("voxels_old_last", ctypes.c_int64), ("voxels_new_last", ctypes.c_int64),
+                ("status_last", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class SlimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"slimvdb error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libslimvdb.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2512_12945_amd.build`")
+        L = ctypes.CDLL(path)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.slim_map_create.argtypes = [ctypes.POINTER(MapConfig), ctypes.POINTER(vp)]
+        L.slim_map_destroy.argtypes = [vp]
+        L.slim_map_reset.argtypes = [vp, vp]
+        L.slim_integrate.argtypes = [vp, vp, i64, vp, vp, i32, vp]
+        L.slim_map_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
+        L.slim_extract.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
+        L.slim_query.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+        L.slim_profile_enable.argtypes = [vp, i32]
+        L.slim_profile_read.argtypes = [vp, vp, vp, i32, vp]
+        L.slim_last_error.restype = ctypes.c_char_p
+        for f in EXPORTS[:-1]:
+            getattr(L, f).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != OK:
+        raise SlimError(code, _lib.slim_last_error().decode())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else None
+
+
+class Map:
+    """A sparse semantic TSDF map living on one GPU (see include/slimvdb.h)."""
+
+    def __init__(self, voxel_size, sdf_trunc, min_range=0.0, max_range=100.0, sem_mode=SEM_NONE, num_classes=0,
+                 embed_dim=0, device=0, max_leaves=1 << 18, max_voxels=1 << 24):
+        self._L = load()
+        self.device = torch.device("cuda", device)
+        self.cfg = MapConfig(voxel_size, sdf_trunc, min_range, max_range, sem_mode, num_classes, embed_dim, device,
+                             max_leaves, max_voxels)
+        self.sem_mode = sem_mode
+        self.nsem = num_classes if sem_mode == SEM_CLOSED else (2 * embed_dim if sem_mode == SEM_OPEN else 0)
+        h = ctypes.c_void_p()
+        _check(self._L.slim_map_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+        self.h = h
+        self._pose = np.zeros(16, np.float64)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.slim_map_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def reset(self):
+        _check(self._L.slim_map_reset(self.h, _stream(self.device)))
+
+    def integrate(self, points, pose, sem=None, kind=IN_NONE):
+        """points: (N, 3) float32 cuda tensor; pose: 4x4 map_T_sensor; sem: cuda tensor in `kind` layout."""
+        self._pose[:] = np.asarray(pose, np.float64).reshape(16)
+        n = points.shape[0] if points is not None else 0
+        _check(self._L.slim_integrate(self.h, _ptr(points), n, self._pose.ctypes.data_as(ctypes.c_void_p),
+                                      _ptr(sem), kind, _stream(self.device)))
+
+    def stats(self):
+        st = Stats()
+        _check(self._L.slim_map_stats(self.h, ctypes.byref(st), _stream(self.device)))
+        return st.as_dict()
+
+    def extract(self):
+        """All voxels with W > 0 as cuda tensors: keys (M, 3) int32, D, W (M,), sem (M, S)."""
+        cnt = ctypes.c_int64()
+        s = _stream(self.device)
+        _check(self._L.slim_extract(self.h, 0, None, None, None, None, ctypes.byref(cnt), s))
+        M = cnt.value
+        keys = torch.empty((max(M, 1), 3), dtype=torch.int32, device=self.device)
+        d = torch.empty(max(M, 1), dtype=torch.float32, device=self.device)
+        w = torch.empty(max(M, 1), dtype=torch.float32, device=self.device)
+        sem = torch.empty((max(M, 1), max(self.nsem, 1)), dtype=torch.float32, device=self.device)
+        _check(self._L.slim_extract(self.h, max(M, 1), _ptr(keys), _ptr(d), _ptr(w),
+                                    _ptr(sem) if self.nsem else None, ctypes.byref(cnt), s))
+        M = cnt.value
+        return dict(keys=keys[:M], D=d[:M], W=w[:M], sem=sem[:M, : self.nsem])
+
+    def query(self, xyz):
+        m = xyz.shape[0]
+        d = torch.empty(max(m, 1), dtype=torch.float32, device=self.device)
+        w = torch.empty(max(m, 1), dtype=torch.float32, device=self.device)
+        sem = torch.empty((max(m, 1), max(self.nsem, 1)), dtype=torch.float32, device=self.device)
+        _check(self._L.slim_query(self.h, _ptr(xyz), m, _ptr(d), _ptr(w), _ptr(sem) if self.nsem else None,
+                                  _stream(self.device)))
+        return dict(D=d[:m], W=w[:m], sem=sem[:m, : self.nsem])
+
+    def profile(self, enable=True):
+        _check(self._L.slim_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        ms = np.zeros(len(KERNELS), np.float64)
+        n = np.zeros(len(KERNELS), np.int64)
+        _check(self._L.slim_profile_read(self.h, ms.ctypes.data_as(ctypes.c_void_p),
+                                         n.ctypes.data_as(ctypes.c_void_p), len(KERNELS), _stream(self.device)))
+        return {k: (float(a), int(b)) for k, a, b in zip(KERNELS, ms, n)}
