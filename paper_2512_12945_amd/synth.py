@@ -263,6 +263,17 @@ class StreetScene:
         cls = np.where(which == 2, self.cyl_class[np.maximum(ic, 0)], cls)
         return t, cls
 
+    def sweeps(self, ts, workers=8):
+        """Several sweeps, generated in worker processes."""
+        ts = list(ts)
+        if workers <= 1 or len(ts) < 4:
+            return [self.sweep(t) for t in ts]
+        import concurrent.futures as cf
+        import multiprocessing as mp
+
+        with cf.ProcessPoolExecutor(max_workers=min(workers, len(ts)), mp_context=mp.get_context("fork")) as ex:
+            return list(ex.map(self.sweep, ts))
+
     def sweep(self, t, nrays=None):
         """Sweep number t: points (NaN where no return within range), pose, labels (with flicker)."""
         pose = self.pose(t)
