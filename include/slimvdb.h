@@ -146,10 +146,10 @@ slim_status slim_query(slim_map *map, const float *xyz_dev, int64_t m, float *d_
 /* Kernel timing.  While enabled, slim_integrate brackets each of its kernels
  * with HIP events on the stream it launches on; slim_profile_read returns the
  * accumulated per-kernel time in milliseconds and launch counts (index 0 ray
- * walk and emission, 1 leaf planning, 2 pair bucketing, 3 leaf sort, reduce
- * and combine) and resets them.  Reading synchronises `stream`.  n_kernels
- * is the length of ms_host and launches_host; the call writes
- * min(n_kernels, 4) entries. */
+ * walk and pair emission, 1 leaf planning, 2 pair bucketing, 3 per-leaf sort,
+ * 4 allocation and commit, 5 per-voxel reduce and combine) and resets them.
+ * Reading synchronises `stream`.  n_kernels is the length of ms_host and
+ * launches_host; the call writes min(n_kernels, 6) entries. */
 slim_status slim_profile_enable(slim_map *map, int32_t enable);
 slim_status slim_profile_read(slim_map *map, double *ms_host, int64_t *launches_host, int32_t n_kernels,
                               void *stream);

@@ -59,7 +59,7 @@ struct slim_map {
     slim_map_config cfg;
     int nsem = 0;
     int maxsteps = 0;
-    int apply_blocks = 1024;
+    int cus = 256;
     MapDev md = {};
     size_t hcap = 0;
     size_t pair_cap = 0;
@@ -72,8 +72,8 @@ struct slim_map {
     bool prof = false;
     std::vector<hipEvent_t> ev;  // kProfRing * 2 * kNumProfiled
     int prof_head = 0, prof_count = 0;
-    double prof_ms[kNumProfiled] = {0, 0, 0, 0};
-    long long prof_n[kNumProfiled] = {0, 0, 0, 0};
+    double prof_ms[kNumProfiled] = {};
+    long long prof_n[kNumProfiled] = {};
     std::vector<void *> allocs;
 };
 
@@ -141,24 +141,30 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s)
     HIP_OK(hipStreamSynchronize(s));
     size_t cap = std::max<size_t>(need, m->pair_cap + m->pair_cap / 2);
     cap = std::min<size_t>(cap, 0xFFFFFFF0ull);
-    void *ptrs[6] = {m->md.pair_pos, m->md.pair_rank, m->md.pair_key, m->md.pair_tsdf, m->md.srt_key, m->md.srt_tsdf};
+    MapDev &md = m->md;
+    void *ptrs[10] = {md.pair_pos, md.pair_rank, md.pair_key, md.pair_tsdf, md.srt_key,
+                      md.srt_tsdf, md.tmp_key,   md.tmp_tsdf, md.seg_desc, md.chunk_leaf};
     for (void *p : ptrs) {
         if (!p) continue;
         (void)hipFree(p);
         m->allocs.erase(std::remove(m->allocs.begin(), m->allocs.end(), p), m->allocs.end());
     }
-    m->md.pair_pos = m->md.pair_rank = m->md.pair_key = m->md.srt_key = nullptr;
-    m->md.pair_tsdf = m->md.srt_tsdf = nullptr;
+    md.pair_pos = md.pair_rank = md.pair_key = md.srt_key = md.tmp_key = nullptr;
+    md.pair_tsdf = md.srt_tsdf = md.tmp_tsdf = nullptr;
+    md.seg_desc = nullptr;
+    md.chunk_leaf = nullptr;
     slim_status r;
-    if ((r = dalloc(m, &m->md.pair_pos, cap)) || (r = dalloc(m, &m->md.pair_rank, cap)) ||
-        (r = dalloc(m, &m->md.pair_key, cap)) || (r = dalloc(m, &m->md.pair_tsdf, cap)) ||
-        (r = dalloc(m, &m->md.srt_key, cap)) || (r = dalloc(m, &m->md.srt_tsdf, cap))) {
+    if ((r = dalloc(m, &md.pair_pos, cap)) || (r = dalloc(m, &md.pair_rank, cap)) ||
+        (r = dalloc(m, &md.pair_key, cap)) || (r = dalloc(m, &md.pair_tsdf, cap)) ||
+        (r = dalloc(m, &md.srt_key, cap)) || (r = dalloc(m, &md.srt_tsdf, cap)) ||
+        (r = dalloc(m, &md.tmp_key, cap)) || (r = dalloc(m, &md.tmp_tsdf, cap)) ||
+        (r = dalloc(m, &md.seg_desc, cap)) || (r = dalloc(m, &md.chunk_leaf, cap / kSegChunk + 2))) {
         m->pair_cap = 0;
-        m->md.pair_cap = 0;
+        md.pair_cap = 0;
         return r;
     }
     m->pair_cap = cap;
-    m->md.pair_cap = (uint32_t)cap;
+    md.pair_cap = (uint32_t)cap;
     return SLIM_OK;
 }
 
@@ -211,19 +217,22 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
     m->hcap = cap;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, config->device) == hipSuccess && prop.multiProcessorCount > 0)
-        m->apply_blocks = prop.multiProcessorCount * 4;
+        m->cus = prop.multiProcessorCount;
 
     MapDev &md = m->md;
     md.hmask = (uint32_t)(cap - 1);
     md.max_leaves = config->max_leaves;
     md.max_voxels = config->max_voxels;
+    md.rec_stride = record_stride(m->nsem);
     const size_t L = (size_t)config->max_leaves, V = (size_t)config->max_voxels;
     if ((r = dalloc(m, &md.hkeys, cap)) || (r = dalloc(m, &md.hvals, cap)) || (r = dalloc(m, &md.skeys, cap)) ||
         (r = dalloc(m, &md.touched, cap)) || (r = dalloc(m, &md.pos_count, cap)) ||
-        (r = dalloc(m, &md.pos_mask, cap * kMaskWords)) || (r = dalloc(m, &md.pos_plan, cap)) ||
+        (r = dalloc(m, &md.pos_occ, cap * kMaskWords)) || (r = dalloc(m, &md.pos_plan, cap)) ||
+        (r = dalloc(m, &md.leaf_cnt, cap)) || (r = dalloc(m, &md.leaf_base, cap)) ||
+        (r = dalloc(m, &md.leaf_info, cap)) ||
         (r = dalloc(m, &md.leaf_key, L)) || (r = dalloc(m, &md.leaf_index, L * kLeafVoxels)) ||
-        (r = dalloc(m, &md.leaf_occ, L * kMaskWords)) || (r = dalloc(m, &md.vox_dw, V)) ||
-        (r = dalloc(m, &md.vox_sem, V * (size_t)m->nsem)) || (r = dalloc(m, &md.st, 1))) {
+        (r = dalloc(m, &md.leaf_occ, L * kMaskWords)) || (r = dalloc(m, &md.vox, V * (size_t)md.rec_stride)) ||
+        (r = dalloc(m, &md.st, 1))) {
         free_all(m);
         delete m;
         return r;
@@ -328,7 +337,7 @@ slim_status slim_integrate(slim_map *m, const float *points, int64_t n, const do
         m->prof_head = (m->prof_head + 1) % kProfRing;
         m->prof_count++;
     }
-    HIP_OK(launch_integrate(fp, m->md, m->apply_blocks, s, ev));
+    HIP_OK(launch_integrate(fp, m->md, m->cus, s, ev));
     return SLIM_OK;
 }
 

@@ -1,24 +1,28 @@
 // HIP kernels of the semantic TSDF integrator (gfx950, wave64).
 //
-// One frame runs as four kernels on the map's stream:
+// One frame runs as five kernels on the map's stream:
 //   1. ray_walk_emit  one lane per point: pose application, ray, band, voxel
-//                     walk (Sec. III-A), truncation gate; leaf runs of each
-//                     ray are staged (frame-local leaf table) and every kept
+//                     walk (Sec. III-A), truncation gate; the leaf runs of each
+//                     ray are staged in a frame-local leaf table and every kept
 //                     (voxel, point) observation is written as a pair.
-//   2. leaf_plan      one lane per touched leaf: find it in the map, count
-//                     its new voxels, allocate its pair bucket.
+//   2. leaf_plan      one lane per touched leaf: find it in the map (or number
+//                     it as new) and allocate its pair bucket.
 //   3. pair_bucket    one lane per pair: scatter into its leaf's bucket.
-//   4. leaf_apply     one workgroup per touched leaf: sort the bucket by
-//                     (voxel offset, point index) in LDS, reduce each voxel's
-//                     observations in point order, and combine them with the
-//                     stored state: Eq. (1)-(2) for D and W, Eq. (6) for the
-//                     class counts, Eqs. (11)-(14) with lambda = 2 nu = W for
-//                     the open-set mean and beta.  Its last workgroup commits
-//                     the frame's counters.
-// Capacity is checked in leaf_apply before any map write, so a frame that does
-// not fit changes nothing.  No floating-point atomics are used: each voxel's
-// sums are formed by one lane in point order, so results are bitwise
-// repeatable and independent of launch shapes.
+//   4. leaf_sort      one workgroup per touched leaf: counting sort of the
+//                     bucket by voxel offset in LDS, then by point index inside
+//                     each voxel; one segment descriptor per touched voxel
+//                     (record of an existing voxel, or a new record numbered in
+//                     offset order).
+//   5. segment_apply  one lane (closed set, K <= 32) or one wave (open set,
+//                     wider K) per voxel segment: reduce its observations in
+//                     point order and combine them with the stored state --
+//                     Eq. (1)-(2) for D and W, Eq. (6) for the class counts,
+//                     Eqs. (11)-(14) with lambda = 2 nu = W for the open-set
+//                     mean and beta.  Its last workgroup commits the frame.
+// Kernels 1-4 only read the map; the capacity check at the start of kernel 5
+// precedes every map write, so a frame that does not fit changes nothing.  No
+// floating-point atomics are used: each voxel's sums are formed in point order,
+// so results are bitwise repeatable and independent of launch shapes.
 //
 // The geometric decision path (pose, ray, walk, gate) is a fixed sequence of
 // binary32 operations; build with -ffp-contract=off so that only the fmaf()
@@ -78,9 +82,11 @@ __device__ void map_insert(const MapDev &md, unsigned long long key, int32_t slo
 }
 
 // Staging-table position of a leaf touched by this frame, inserting it on
-// first sight.  kNoPos if the table is full.
-__device__ uint32_t stage_leaf(const MapDev &md, unsigned long long key)
+// first sight (*fresh = true for the inserting caller).  kNoPos if the table
+// is full.
+__device__ uint32_t stage_leaf(const MapDev &md, unsigned long long key, bool *fresh)
 {
+    *fresh = false;
     uint32_t h = leaf_hash(key, md.hmask);
     for (uint32_t probe = 0; probe <= md.hmask; ++probe) {
         unsigned long long cur = load_key(&md.skeys[h]);
@@ -88,8 +94,7 @@ __device__ uint32_t stage_leaf(const MapDev &md, unsigned long long key)
         if (cur == kEmptyKey) {
             unsigned long long prev = atomicCAS(&md.skeys[h], kEmptyKey, key);
             if (prev == kEmptyKey) {
-                uint32_t j = atomicAdd(&md.st->n_touched, 1u);
-                md.touched[j] = h;
+                *fresh = true;
                 return h;
             }
             if (prev == key) return h;
@@ -112,8 +117,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
     return v;
 }
 
-// Wave-aggregated atomicAdd: every lane of the wave must call it.  Returns
-// the lane's exclusive offset into the reserved range.
+// Wave-aggregated atomicAdd (one atomic per wave): every lane of the wave must
+// call it.  Returns the lane's exclusive offset into the reserved range.
 __device__ __forceinline__ uint32_t wave_reserve(unsigned int *counter, uint32_t v)
 {
     uint32_t incl = wave_incl_scan(v);
@@ -205,14 +210,61 @@ __device__ __forceinline__ float cell_sdf(const FrameParams &fp, const Ray &ry, 
 __device__ __forceinline__ bool key_ok(int k) { return k > -kKeyLimit && k < kKeyLimit; }
 
 // ---------------------------------------------------------------------------
+// block-wide helpers (blockDim.x = 256)
+// ---------------------------------------------------------------------------
+
+// Exclusive prefix sum over the block of one value per thread; *total gets
+// the block sum.  Uses wsum[4] of LDS.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, uint32_t *total)
+{
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q < w) before += wsum[q];
+        tot += wsum[q];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + incl - v;
+}
+
+// ---------------------------------------------------------------------------
 // 1. ray walk and pair emission
 // ---------------------------------------------------------------------------
 
-constexpr int kMaxRuns = 8;  // leaf runs per ray; sdf_trunc <= 8 voxel_size keeps a ray within this
+constexpr int kMaxRuns = 8;  // leaf runs per ray; sdf_trunc <= 6 voxel_size keeps a ray within this
 
-__global__ __launch_bounds__(256) void k_ray_walk_emit(FrameParams fp, MapDev md)
+__device__ __forceinline__ uint32_t lds_hash(unsigned long long k)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    return (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 40) & (kWalkTable - 1);
+}
+
+__global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, MapDev md)
+{
+    // block-local table of the leaves this block's rays touch
+    __shared__ unsigned long long t_key[kWalkTable];
+    __shared__ uint32_t t_cnt[kWalkTable];   // pairs of this block in the leaf, then their first bucket rank
+    __shared__ uint32_t t_pos[kWalkTable];   // staging position
+    __shared__ uint32_t t_list[kWalkTable];  // occupied entries
+    __shared__ uint32_t t_fresh[kWalkTable]; // staging positions this block inserted
+    __shared__ uint32_t s_n, s_nfresh, s_fresh_base, s_pair_base, wsum[4];
+
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kWalkTable; e += blockDim.x) {
+        t_key[e] = kEmptyKey;
+        t_cnt[e] = 0;
+    }
+    if (tid == 0) {
+        s_n = 0;
+        s_nfresh = 0;
+    }
+    __syncthreads();
+
+    const int i = blockIdx.x * blockDim.x + tid;
     Ray ry;
     bool valid = false;
     if (i < fp.n) {
@@ -230,13 +282,19 @@ __global__ __launch_bounds__(256) void k_ray_walk_emit(FrameParams fp, MapDev md
     unsigned long long rkey[kMaxRuns];
     uint32_t rlen[kMaxRuns];
 #pragma unroll
-    for (int q = 0; q < kMaxRuns; ++q) { rkey[q] = kEmptyKey; rlen[q] = 0; }
+    for (int q = 0; q < kMaxRuns; ++q) {
+        rkey[q] = kEmptyKey;
+        rlen[q] = 0;
+    }
     if (valid) {
         bool inrange = true;
         unsigned long long cur = kEmptyKey;
         band_walk(fp, ry, [&](int cx, int cy, int cz) {
             const int kx = fp.a[0] + cx, ky = fp.a[1] + cy, kz = fp.a[2] + cz;
-            if (!(key_ok(kx) && key_ok(ky) && key_ok(kz))) { inrange = false; return; }
+            if (!(key_ok(kx) && key_ok(ky) && key_ok(kz))) {
+                inrange = false;
+                return;
+            }
             if (!(cell_sdf(fp, ry, cx, cy, cz) > -fp.tau)) return;
             const unsigned long long lk = pack_leaf(kx >> 3, ky >> 3, kz >> 3);
             if (lk != cur) {
@@ -253,31 +311,76 @@ __global__ __launch_bounds__(256) void k_ray_walk_emit(FrameParams fp, MapDev md
         });
         if (!inrange || nruns > kMaxRuns) valid = false;
     }
-    if (!valid) { cnt = 0; nruns = 0; }
+    if (!valid) {
+        cnt = 0;
+        nruns = 0;
+    }
 
-    const bool rej = (i < fp.n) && !valid;
-    const unsigned long long rejmask = __ballot(rej);
-    if (lane_id() == 0 && rejmask) atomicAdd(&md.st->rejected, (unsigned)__popcll(rejmask));
-
-    const uint32_t base = wave_reserve(&md.st->pairs, cnt);
-
-    // stage each run's leaf and reserve its ranks in the leaf's bucket
-    uint32_t rpos[kMaxRuns], rrank[kMaxRuns];
+    // runs into the block table: local rank of each run inside its leaf
+    uint32_t rent[kMaxRuns], rloc[kMaxRuns];
 #pragma unroll
     for (int q = 0; q < kMaxRuns; ++q) {
-        rpos[q] = kNoPos;
-        rrank[q] = 0;
+        rent[q] = 0;
+        rloc[q] = 0;
         if (q < nruns) {
-            const uint32_t pos = stage_leaf(md, rkey[q]);
-            rpos[q] = pos;
-            if (pos != kNoPos) rrank[q] = atomicAdd(&md.pos_count[pos], rlen[q]);
-            else atomicOr(&md.st->frame_err, 1u);
+            // distinct keys <= runs of the block <= table size, so a free or
+            // matching entry always exists; the probe bound is a safeguard
+            const unsigned long long key = rkey[q];
+            uint32_t h = lds_hash(key);
+            bool found = false;
+            for (int probe = 0; probe < kWalkTable && !found; ++probe) {
+                unsigned long long k = t_key[h];
+                if (k == kEmptyKey) {
+                    k = atomicCAS(&t_key[h], kEmptyKey, key);
+                    if (k == kEmptyKey) {
+                        t_list[atomicAdd(&s_n, 1u)] = h;
+                        k = key;
+                    }
+                }
+                if (k == key) found = true;
+                else h = (h + 1) & (kWalkTable - 1);
+            }
+            if (found) {
+                rent[q] = h;
+                rloc[q] = atomicAdd(&t_cnt[h], rlen[q]);
+            } else {
+                rent[q] = kWalkTable;  // no entry: pairs of this run are dropped, frame rejected
+                atomicOr(&md.st->frame_err.v, 1u);
+            }
         }
     }
+    __syncthreads();
+
+    // one staging lookup and one bucket reservation per leaf of the block
+    const uint32_t nloc = s_n;
+    for (uint32_t e = tid; e < nloc; e += blockDim.x) {
+        const uint32_t h = t_list[e];
+        bool fresh;
+        const uint32_t pos = stage_leaf(md, t_key[h], &fresh);
+        t_pos[h] = pos;
+        if (pos != kNoPos) {
+            t_cnt[h] = atomicAdd(&md.pos_count[pos], t_cnt[h]);
+            if (fresh) t_fresh[atomicAdd(&s_nfresh, 1u)] = pos;
+        } else {
+            atomicOr(&md.st->frame_err.v, 1u);
+        }
+    }
+    __syncthreads();
+    const uint32_t rejected_block = __syncthreads_count((i < fp.n) && !valid);
+    uint32_t total;
+    const uint32_t off = block_excl_scan(cnt, wsum, &total);
+    if (tid == 0) {
+        if (s_nfresh) s_fresh_base = atomicAdd(&md.st->n_touched.v, s_nfresh);
+        if (total) s_pair_base = atomicAdd(&md.st->pairs.v, total);
+        if (rejected_block) atomicAdd(&md.st->rejected.v, rejected_block);
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < s_nfresh; e += blockDim.x) md.touched[s_fresh_base + e] = t_fresh[e];
     if (cnt == 0) return;
 
     // pass 2: write the pairs
-    uint32_t o = base, j = 0;
+    const uint32_t o = s_pair_base + off;
+    uint32_t j = 0;
     int run = -1;
     unsigned long long cur = kEmptyKey;
     uint32_t pos = kNoPos, rank = 0;
@@ -291,16 +394,18 @@ __global__ __launch_bounds__(256) void k_ray_walk_emit(FrameParams fp, MapDev md
             run++;
 #pragma unroll
             for (int q = 0; q < kMaxRuns; ++q)
-                if (q == run) { pos = rpos[q]; rank = rrank[q]; }
+                if (q == run) {
+                    pos = rent[q] < (uint32_t)kWalkTable ? t_pos[rent[q]] : kNoPos;
+                    rank = rent[q] < (uint32_t)kWalkTable ? t_cnt[rent[q]] + rloc[q] : 0u;
+                }
         }
-        const uint32_t off = (uint32_t)(((kx & 7) << 6) | ((ky & 7) << 3) | (kz & 7));
+        const uint32_t voff = (uint32_t)(((kx & 7) << 6) | ((ky & 7) << 3) | (kz & 7));
         if (o + j < md.pair_cap) {
             md.pair_pos[o + j] = pos;
             md.pair_rank[o + j] = rank++;
-            md.pair_key[o + j] = (off << kPidBits) | (uint32_t)i;
+            md.pair_key[o + j] = (voff << kPidBits) | (uint32_t)i;
             md.pair_tsdf[o + j] = fminf(s, fp.tau);
         }
-        if (pos != kNoPos) atomicOr(&md.pos_mask[pos * kMaskWords + (off >> 5)], 1u << (off & 31));
         j++;
     });
 }
@@ -311,30 +416,21 @@ __global__ __launch_bounds__(256) void k_ray_walk_emit(FrameParams fp, MapDev md
 
 __global__ __launch_bounds__(256) void k_leaf_plan(MapDev md)
 {
-    const uint32_t nt = md.st->n_touched;
+    const uint32_t nt = md.st->n_touched.v;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t jb = blockIdx.x * blockDim.x; jb < nt; jb += stride) {
         const uint32_t j = jb + threadIdx.x;
         const bool act = j < nt;
         int32_t slot = -1;
-        uint32_t nnew = 0, nold = 0, npairs = 0, pos = 0;
+        uint32_t npairs = 0, pos = 0;
         if (act) {
             pos = md.touched[j];
             slot = map_find(md, md.skeys[pos]);
-            for (int w = 0; w < kMaskWords; ++w) {
-                const uint32_t m = md.pos_mask[pos * kMaskWords + w];
-                const uint32_t occ = slot >= 0 ? md.leaf_occ[(size_t)slot * kMaskWords + w] : 0u;
-                nnew += __popc(m & ~occ);
-                nold += __popc(m & occ);
-            }
             npairs = md.pos_count[pos];
         }
-        const uint32_t newleaf = wave_reserve(&md.st->new_leaves, (act && slot < 0) ? 1u : 0u);
-        const uint32_t vbase = wave_reserve(&md.st->new_voxels, nnew);
-        const uint32_t bstart = wave_reserve(&md.st->pair_cursor, npairs);
-        const uint32_t oldsum = wave_incl_scan(nold);
-        if (lane_id() == 63 && oldsum) atomicAdd(&md.st->u_old, (unsigned long long)oldsum);
-        if (act) md.pos_plan[pos] = make_int4(slot, slot < 0 ? (int)newleaf : -1, (int)vbase, (int)bstart);
+        const uint32_t newleaf = wave_reserve(&md.st->new_leaves.v, (act && slot < 0) ? 1u : 0u);
+        const uint32_t bstart = wave_reserve(&md.st->pair_cursor.v, npairs);
+        if (act) md.pos_plan[pos] = make_int4(slot, slot < 0 ? (int)newleaf : -1, (int)bstart, 0);
     }
 }
 
@@ -344,282 +440,589 @@ __global__ __launch_bounds__(256) void k_leaf_plan(MapDev md)
 
 __global__ __launch_bounds__(256) void k_pair_bucket(MapDev md)
 {
-    const uint32_t P = min(md.st->pairs, md.pair_cap);
+    const uint32_t P = min(md.st->pairs.v, md.pair_cap);
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += stride) {
         const uint32_t pos = md.pair_pos[i];
         if (pos == kNoPos) continue;
-        const uint32_t dst = (uint32_t)md.pos_plan[pos].w + md.pair_rank[i];
+        const uint32_t dst = (uint32_t)md.pos_plan[pos].z + md.pair_rank[i];
         md.srt_key[dst] = md.pair_key[i];
         md.srt_tsdf[dst] = md.pair_tsdf[i];
     }
 }
 
 // ---------------------------------------------------------------------------
-// 4. per-leaf sort, reduce and conjugate combine
+// 4. per-leaf sort and segment descriptors
 // ---------------------------------------------------------------------------
 
-// Ascending sort of n (key, value) pairs by key, in place, by the whole
-// workgroup.  Bitonic network in which the first merge step of each stage
-// compares mirrored positions, so every block is sorted ascending and
-// positions >= n act as +infinity and are never touched.
-template <class KP, class VP>
-__device__ void block_sort(KP keys, VP vals, uint32_t n)
+// Exclusive prefix sum of 512 LDS counters by 256 threads.
+__device__ void block_scan512(const uint32_t *in, uint32_t *out, uint32_t *wsum)
 {
-    uint32_t np2 = 1;
-    while (np2 < n) np2 <<= 1;
-    const uint32_t half = np2 >> 1;
-    for (uint32_t k = 2; k <= np2; k <<= 1) {
-        // mirrored merge step
-        const uint32_t hk = k >> 1;
-        for (uint32_t t = threadIdx.x; t < half; t += blockDim.x) {
-            const uint32_t blk = t / hk, w = t % hk;
-            const uint32_t a = blk * k + w, b = blk * k + k - 1 - w;
-            if (b < n) {
-                const uint32_t ka = keys[a], kb = keys[b];
-                if (kb < ka) {
-                    keys[a] = kb; keys[b] = ka;
-                    const float va = vals[a];
-                    vals[a] = vals[b]; vals[b] = va;
-                }
-            }
-        }
-        __syncthreads();
-        for (uint32_t d = hk >> 1; d > 0; d >>= 1) {
-            for (uint32_t t = threadIdx.x; t < half; t += blockDim.x) {
-                const uint32_t a = (t / d) * 2 * d + (t % d), b = a + d;
-                if (b < n) {
-                    const uint32_t ka = keys[a], kb = keys[b];
-                    if (kb < ka) {
-                        keys[a] = kb; keys[b] = ka;
-                        const float va = vals[a];
-                        vals[a] = vals[b]; vals[b] = va;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
+    const int t = threadIdx.x;
+    const uint32_t a = in[2 * t], b = in[2 * t + 1];
+    uint32_t total;
+    const uint32_t ex = block_excl_scan(a + b, wsum, &total);
+    out[2 * t] = ex;
+    out[2 * t + 1] = ex + a;
+    __syncthreads();
 }
 
-struct LeafCtx {
-    int slot;
-    uint32_t n;           // pairs in the bucket
-    long long vrec_base;  // first record of this leaf's new voxels
-};
-
-// Reduces and combines every voxel segment of a sorted bucket.  G lanes per
-// segment; lane r of a group owns semantic components r, r + G, ...
-template <int MODE, class KP, class VP>
-__device__ void apply_segments(const FrameParams &fp, const MapDev &md, KP keys, VP vals, const LeafCtx &lc,
-                               const uint32_t *heads, int nseg, const uint32_t *newmask, const uint32_t *occ0,
-                               int G)
+__device__ __forceinline__ uint32_t bits_below(const uint32_t *mask, uint32_t o)
 {
-    const int gid = threadIdx.x / G, lane = threadIdx.x % G, ngroups = blockDim.x / G;
-    const size_t lbase = (size_t)lc.slot * kLeafVoxels;
-    for (int sg = gid; sg < nseg; sg += ngroups) {
-        const uint32_t i0 = heads[sg];
-        const uint32_t off = keys[i0] >> kPidBits;
-        uint32_t i1 = i0 + 1;
-        while (i1 < lc.n && (keys[i1] >> kPidBits) == off) i1++;
-        const float nf = (float)(i1 - i0);
-        const bool existed = (occ0[off >> 5] >> (off & 31)) & 1u;
-        long long rec;
-        if (existed) {
-            rec = md.leaf_index[lbase + off];
-        } else {
-            uint32_t rank = 0;
-            for (uint32_t w = 0; w < (off >> 5); ++w) rank += __popc(newmask[w]);
-            rank += __popc(newmask[off >> 5] & ((1u << (off & 31)) - 1u));
-            rec = lc.vrec_base + rank;
-            if (lane == 0) md.leaf_index[lbase + off] = (int32_t)rec;
-        }
-        float2 dw = existed ? md.vox_dw[rec] : make_float2(0.0f, 0.0f);
-        const float W0 = dw.y, W1 = W0 + nf;
-        if (lane == 0) {
-            // Eq. (1)-(2), unit weights: D' = (W D + sum tsdf) / (W + n)
-            float st = 0.0f;
-            for (uint32_t i = i0; i < i1; ++i) st += vals[i];
-            md.vox_dw[rec] = make_float2((W0 * dw.x + st) / W1, W1);
-        }
-        if (MODE == SLIM_SEM_CLOSED) {
-            float *S = md.vox_sem + (size_t)rec * fp.nsem;
-            if (fp.sem_kind == SLIM_IN_LOGIT_F32) {
-                // K <= G: lane k owns class k; softmax per observation across the group
-                const float *lg = (const float *)fp.sem;
-                float acc = 0.0f;
-                for (uint32_t i = i0; i < i1; ++i) {
-                    const uint32_t pid = keys[i] & kPidMask;
-                    const float l = lane < fp.K ? lg[(size_t)pid * fp.K + lane] : -INFINITY;
-                    float mx = l;
-                    for (int d = G >> 1; d > 0; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d, G));
-                    const float e = lane < fp.K ? expf(l - mx) : 0.0f;
-                    float den = e;
-                    for (int d = G >> 1; d > 0; d >>= 1) den += __shfl_xor(den, d, G);
-                    acc += e / den;
-                }
-                if (lane < fp.K) S[lane] = (existed ? S[lane] : 0.0f) + acc;
-            } else {
-                for (int k = lane; k < fp.K; k += G) {
-                    float acc = 0.0f;
-                    if (fp.sem_kind == SLIM_IN_LABEL_I32) {
-                        const int32_t *lb = (const int32_t *)fp.sem;
-                        for (uint32_t i = i0; i < i1; ++i) acc += (lb[keys[i] & kPidMask] == k) ? 1.0f : 0.0f;
-                    } else {
-                        const float *pr = (const float *)fp.sem;
-                        for (uint32_t i = i0; i < i1; ++i) acc += pr[(size_t)(keys[i] & kPidMask) * fp.K + k];
-                    }
-                    // Eq. (6): concentrations grow by the (expected) counts
-                    S[k] = (existed ? S[k] : 0.0f) + acc;
-                }
-            }
-        } else if (MODE == SLIM_SEM_OPEN) {
-            float *M = md.vox_sem + (size_t)rec * fp.nsem;
-            float *B = M + fp.L;
-            const bool bf = fp.sem_kind == SLIM_IN_EMB_BF16;
-            const float inv_n = 1.0f / nf;
-            const float cross = W0 * nf / W1;
-            for (int d = lane; d < fp.L; d += G) {
-                float s1 = 0.0f;
-                for (uint32_t i = i0; i < i1; ++i) {
-                    const size_t idx = (size_t)(keys[i] & kPidMask) * fp.L + d;
-                    s1 += bf ? __uint_as_float((uint32_t)((const uint16_t *)fp.sem)[idx] << 16)
-                             : ((const float *)fp.sem)[idx];
-                }
-                const float zbar = s1 * inv_n;
-                float s2 = 0.0f;
-                for (uint32_t i = i0; i < i1; ++i) {
-                    const size_t idx = (size_t)(keys[i] & kPidMask) * fp.L + d;
-                    const float z = bf ? __uint_as_float((uint32_t)((const uint16_t *)fp.sem)[idx] << 16)
-                                       : ((const float *)fp.sem)[idx];
-                    const float dz = z - zbar;
-                    s2 += dz * dz;
-                }
-                // Eqs. (11)-(14) with lambda = W, nu = W / 2
-                const float m0 = existed ? M[d] : 0.0f, b0 = existed ? B[d] : 0.0f;
-                const float dm = zbar - m0;
-                B[d] = b0 + 0.5f * s2 + cross * dm * dm * 0.5f;
-                M[d] = (W0 * m0 + nf * zbar) / W1;
-            }
-        }
-    }
+    uint32_t r = 0;
+    for (uint32_t w = 0; w < (o >> 5); ++w) r += __popc(mask[w]);
+    return r + __popc(mask[o >> 5] & ((1u << (o & 31)) - 1u));
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kApplyThreads) void k_leaf_apply(FrameParams fp, MapDev md, int G)
+__global__ __launch_bounds__(kSortThreads) void k_leaf_sort(MapDev md)
 {
-    __shared__ uint32_t s_key[kApplyLdsPairs];
-    __shared__ float s_val[kApplyLdsPairs];
-    __shared__ uint32_t s_heads[kLeafVoxels];
-    __shared__ uint32_t s_newmask[kMaskWords], s_occ0[kMaskWords];
-    __shared__ int s_nseg, s_slot, s_last;
+    __shared__ uint32_t b_key[kSortLdsPairs];
+    __shared__ float b_val[kSortLdsPairs];
+    __shared__ uint32_t hist[kLeafVoxels], bin0[kLeafVoxels], cur[kLeafVoxels];
+    __shared__ uint32_t s_touch[kMaskWords], s_new[kMaskWords], s_occ0[kMaskWords], wsum[4];
+    __shared__ uint32_t s_pre_t[kMaskWords], s_pre_n[kMaskWords];
+    __shared__ uint32_t s_chunk_end, s_nseg, s_nnew;
 
-    DevState *st = md.st;
-    const uint32_t nt = st->n_touched;
-    const unsigned long long lused = st->leaves_used, vused = st->voxels_used;
-    const unsigned long long nl = st->new_leaves, nv = st->new_voxels;
-    const bool ok = st->frame_err == 0 && lused + nl <= (unsigned long long)md.max_leaves &&
-                    vused + nv <= (unsigned long long)md.max_voxels;
+    const uint32_t nt = md.st->n_touched.v;
+    const int tid = threadIdx.x;
 
     for (uint32_t j = blockIdx.x; j < nt; j += gridDim.x) {
         const uint32_t pos = md.touched[j];
         const int4 plan = md.pos_plan[pos];
         const uint32_t n = md.pos_count[pos];
-        if (ok) {
-            if (threadIdx.x == 0) {
-                int slot = plan.x;
-                if (slot < 0) {
-                    slot = (int)(lused + (unsigned long long)plan.y);
-                    const unsigned long long key = md.skeys[pos];
-                    map_insert(md, key, slot);
-                    md.leaf_key[slot] = key;
+        const int slot = plan.x;
+        for (int o = tid; o < kLeafVoxels; o += blockDim.x) hist[o] = 0;
+        if (tid < kMaskWords) s_occ0[tid] = slot >= 0 ? md.leaf_occ[(size_t)slot * kMaskWords + tid] : 0u;
+        __syncthreads();
+
+        uint32_t *gk = md.srt_key + plan.z;
+        float *gv = md.srt_tsdf + plan.z;
+        uint32_t *tk = md.tmp_key + plan.z;
+        float *tv = md.tmp_tsdf + plan.z;
+
+        // histogram of voxel offsets; loads go out kSortBatch at a time per thread,
+        // and a bucket that fits LDS stays in registers until its scatter
+        uint32_t rk[kSortBatch];
+        float rv[kSortBatch];
+        const bool small = n <= (uint32_t)(kSortBatch * kSortThreads);
+        for (uint32_t t0 = 0; t0 < n; t0 += kSortBatch * kSortThreads) {
+#pragma unroll
+            for (int u = 0; u < kSortBatch; ++u) {
+                const uint32_t t = t0 + u * kSortThreads + tid;
+                rk[u] = t < n ? gk[t] : 0u;
+                rv[u] = t < n ? gv[t] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kSortBatch; ++u)
+                if (t0 + u * kSortThreads + tid < n) atomicAdd(&hist[rk[u] >> kPidBits], 1u);
+        }
+        __syncthreads();
+        block_scan512(hist, bin0, wsum);
+        for (int o = tid; o < kLeafVoxels; o += blockDim.x) cur[o] = bin0[o];
+        {
+            // touched offsets: wave w covers bins 64w + [0, 64) and 256 + 64w + [0, 64)
+            const int w = tid >> 6;
+            const unsigned long long b0 = __ballot(hist[tid] != 0u);
+            const unsigned long long b1 = __ballot(hist[tid + 256] != 0u);
+            if (lane_id() == 0) {
+                s_touch[2 * w] = (uint32_t)b0;
+                s_touch[2 * w + 1] = (uint32_t)(b0 >> 32);
+                s_touch[8 + 2 * w] = (uint32_t)b1;
+                s_touch[9 + 2 * w] = (uint32_t)(b1 >> 32);
+            }
+        }
+        __syncthreads();
+        if (tid < kMaskWords) s_new[tid] = s_touch[tid] & ~s_occ0[tid];
+        if (tid == 0) {
+            uint32_t a = 0, b = 0;
+            for (int w = 0; w < kMaskWords; ++w) {
+                s_pre_t[w] = a;
+                s_pre_n[w] = b;
+                a += __popc(s_touch[w]);
+                b += __popc(s_touch[w] & ~s_occ0[w]);
+            }
+            s_nseg = a;
+            s_nnew = b;
+        }
+        __syncthreads();
+
+        if (small) {
+            // bin by offset in LDS (order inside a bin arbitrary), then order each
+            // bin by point index: rank = number of smaller keys in the bin
+#pragma unroll
+            for (int u = 0; u < kSortBatch; ++u)
+                if ((uint32_t)(u * kSortThreads + tid) < n) {
+                    const uint32_t p = atomicAdd(&cur[rk[u] >> kPidBits], 1u);
+                    b_key[p] = rk[u];
+                    b_val[p] = rv[u];
                 }
-                s_slot = slot;
-                s_nseg = 0;
+            __syncthreads();
+            for (uint32_t t = tid; t < n; t += blockDim.x) {
+                const uint32_t k = b_key[t];
+                const uint32_t o = k >> kPidBits, lo = bin0[o], hi = lo + hist[o];
+                uint32_t r = 0;
+#pragma unroll 8
+                for (uint32_t u = lo; u < hi; ++u) r += b_key[u] < k;
+                gk[lo + r] = k;
+                gv[lo + r] = b_val[t];
+            }
+        } else {
+            // large leaf: bin into the scratch buffer, then rank runs of whole
+            // bins that fit in LDS (a single bin larger than LDS ranks in place)
+            for (uint32_t t0 = 0; t0 < n; t0 += kSortBatch * kSortThreads) {
+#pragma unroll
+                for (int u = 0; u < kSortBatch; ++u) {
+                    const uint32_t t = t0 + u * kSortThreads + tid;
+                    rk[u] = t < n ? gk[t] : 0u;
+                    rv[u] = t < n ? gv[t] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kSortBatch; ++u)
+                    if (t0 + u * kSortThreads + tid < n) {
+                        const uint32_t p = atomicAdd(&cur[rk[u] >> kPidBits], 1u);
+                        tk[p] = rk[u];
+                        tv[p] = rv[u];
+                    }
             }
             __syncthreads();
-            const int slot = s_slot;
-            if (plan.x < 0)
-                for (int t = threadIdx.x; t < kLeafVoxels; t += blockDim.x)
-                    md.leaf_index[(size_t)slot * kLeafVoxels + t] = -1;
-            if (threadIdx.x < kMaskWords) {
-                const uint32_t occ = plan.x < 0 ? 0u : md.leaf_occ[(size_t)slot * kMaskWords + threadIdx.x];
-                const uint32_t m = md.pos_mask[(size_t)pos * kMaskWords + threadIdx.x];
-                s_occ0[threadIdx.x] = occ;
-                s_newmask[threadIdx.x] = m & ~occ;
-            }
-            LeafCtx lc;
-            lc.slot = slot;
-            lc.n = n;
-            lc.vrec_base = (long long)vused + plan.z;
-            uint32_t *gk = md.srt_key + plan.w;
-            float *gv = md.srt_tsdf + plan.w;
-            if (n <= (uint32_t)kApplyLdsPairs) {
-                for (uint32_t t = threadIdx.x; t < n; t += blockDim.x) {
-                    s_key[t] = gk[t];
-                    s_val[t] = gv[t];
+            uint32_t o0 = 0;
+            while (o0 < (uint32_t)kLeafVoxels) {
+                if (tid == 0) {
+                    // bin ends are non-decreasing: first o1 > o0 whose end
+                    // passes bin0[o0] + capacity (at least o0 + 1)
+                    const uint32_t lim = bin0[o0] + (uint32_t)kSortLdsPairs;
+                    uint32_t lo = o0 + 1, hi = kLeafVoxels;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (bin0[mid] + hist[mid] <= lim) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    s_chunk_end = lo;
                 }
                 __syncthreads();
-                block_sort(s_key, s_val, n);
-                for (uint32_t t = threadIdx.x; t < n; t += blockDim.x)
-                    if (t == 0 || (s_key[t] >> kPidBits) != (s_key[t - 1] >> kPidBits))
-                        s_heads[atomicAdd(&s_nseg, 1)] = t;
+                const uint32_t o1 = s_chunk_end;
+                const uint32_t lo = bin0[o0], hi = (o1 < (uint32_t)kLeafVoxels) ? bin0[o1] : n;
+                if (hi - lo <= (uint32_t)kSortLdsPairs) {
+#pragma unroll
+                    for (int u = 0; u < kSortBatch; ++u) {
+                        const uint32_t t = lo + u * kSortThreads + tid;
+                        rk[u] = t < hi ? tk[t] : 0u;
+                        rv[u] = t < hi ? tv[t] : 0.0f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kSortBatch; ++u) {
+                        const uint32_t t = lo + u * kSortThreads + tid;
+                        if (t < hi) {
+                            b_key[t - lo] = rk[u];
+                            b_val[t - lo] = rv[u];
+                        }
+                    }
+                    __syncthreads();
+                    for (uint32_t t = lo + tid; t < hi; t += blockDim.x) {
+                        const uint32_t k = b_key[t - lo];
+                        const uint32_t o = k >> kPidBits, blo = bin0[o], bhi = blo + hist[o];
+                        uint32_t r = 0;
+#pragma unroll 8
+                        for (uint32_t u = blo; u < bhi; ++u) r += b_key[u - lo] < k;
+                        gk[blo + r] = k;
+                        gv[blo + r] = b_val[t - lo];
+                    }
+                } else {
+                    for (uint32_t t = lo + tid; t < hi; t += blockDim.x) {
+                        const uint32_t k = tk[t];
+                        uint32_t r = 0;
+                        for (uint32_t u = lo; u < hi; ++u) r += tk[u] < k;
+                        gk[lo + r] = k;
+                        gv[lo + r] = tv[t];
+                    }
+                }
                 __syncthreads();
-                apply_segments<MODE>(fp, md, s_key, s_val, lc, s_heads, s_nseg, s_newmask, s_occ0, G);
-            } else {
-                __syncthreads();
-                block_sort(gk, gv, n);
-                for (uint32_t t = threadIdx.x; t < n; t += blockDim.x)
-                    if (t == 0 || (gk[t] >> kPidBits) != (gk[t - 1] >> kPidBits))
-                        s_heads[atomicAdd(&s_nseg, 1)] = t;
-                __syncthreads();
-                apply_segments<MODE>(fp, md, gk, gv, lc, s_heads, s_nseg, s_newmask, s_occ0, G);
+                o0 = o1;
             }
-            if (threadIdx.x < kMaskWords)
-                md.leaf_occ[(size_t)slot * kMaskWords + threadIdx.x] = s_occ0[threadIdx.x] | s_newmask[threadIdx.x];
         }
-        // the staging entry of this leaf is clean for the next frame
-        if (threadIdx.x < kMaskWords) md.pos_mask[(size_t)pos * kMaskWords + threadIdx.x] = 0u;
-        if (threadIdx.x == 0) {
-            md.pos_count[pos] = 0u;
-            md.skeys[pos] = kEmptyKey;
+
+        // one descriptor per touched voxel, at bucket start + voxel rank
+        if (tid < kMaskWords) md.pos_occ[(size_t)pos * kMaskWords + tid] = s_occ0[tid] | s_touch[tid];
+        if (tid == 0) {
+            md.leaf_cnt[j] = make_uint2(s_nseg, s_nnew);
+            md.leaf_info[j] = make_int4(plan.z, slot >= 0 ? slot : -1 - plan.y, (int)pos, 0);
+        }
+        for (int o = tid; o < kLeafVoxels; o += blockDim.x) {
+            if (!hist[o]) continue;
+            const uint32_t below = (1u << (o & 31)) - 1u;
+            const uint32_t rank = s_pre_t[o >> 5] + __popc(s_touch[o >> 5] & below);
+            const bool existed = (s_occ0[o >> 5] >> (o & 31)) & 1u;
+            const int rec = existed ? md.leaf_index[(size_t)slot * kLeafVoxels + o]
+                                    : (int)(s_pre_n[o >> 5] + __popc(s_new[o >> 5] & below));
+            const uint32_t meta = (uint32_t)o | (existed ? kSegExisted : 0u) | (rank == 0 ? kSegFirst : 0u);
+            md.seg_desc[plan.z + rank] = make_int4((int)(plan.z + bin0[o]), (int)hist[o], rec, (int)meta);
         }
         __syncthreads();
     }
+}
 
-    // the last workgroup commits the frame and clears the frame counters
-    if (threadIdx.x == 0) {
-        __threadfence();
-        s_last = atomicAdd(&st->done_blocks, 1u) == gridDim.x - 1;
-    }
+// ---------------------------------------------------------------------------
+// 5. allocation, capacity decision and commit (one workgroup)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void k_frame_alloc(FrameParams fp, MapDev md)
+{
+    __shared__ uint32_t wsum[16][2];
+    __shared__ uint32_t carry[2];
+    DevState *st = md.st;
+    const uint32_t nt = st->n_touched.v;
+    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+    if (tid == 0) carry[0] = carry[1] = 0;
     __syncthreads();
-    if (s_last && threadIdx.x == 0) {
-        __threadfence();
-        const int err = st->frame_err ? SLIM_ERR_CAPACITY : (ok ? SLIM_OK : SLIM_ERR_CAPACITY);
-        if (err == SLIM_OK) {
+    for (uint32_t b = 0; b < nt; b += 1024) {
+        const uint32_t j = b + tid;
+        const uint2 c = j < nt ? md.leaf_cnt[j] : make_uint2(0u, 0u);
+        const uint32_t i0 = wave_incl_scan(c.x), i1 = wave_incl_scan(c.y);
+        if (lane == 63) {
+            wsum[w][0] = i0;
+            wsum[w][1] = i1;
+        }
+        __syncthreads();
+        uint32_t b0 = carry[0], b1 = carry[1], t0 = 0, t1 = 0;
+        for (int q = 0; q < 16; ++q) {
+            if (q < w) {
+                b0 += wsum[q][0];
+                b1 += wsum[q][1];
+            }
+            t0 += wsum[q][0];
+            t1 += wsum[q][1];
+        }
+        if (j < nt) {
+            const uint32_t sb = b0 + i0 - c.x;
+            md.leaf_base[j] = make_uint2(sb, b1 + i1 - c.y);
+            // leaf of every segment whose index is a multiple of kSegChunk
+            for (uint32_t q = (sb + kSegChunk - 1) / kSegChunk; q * kSegChunk < sb + c.x; ++q) md.chunk_leaf[q] = j;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            carry[0] += t0;
+            carry[1] += t1;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const unsigned long long nseg = carry[0], nnew = carry[1], nl = st->new_leaves.v;
+        const unsigned long long lused = st->leaves_used, vused = st->voxels_used;
+        const bool ok = st->frame_err.v == 0 && lused + nl <= (unsigned long long)md.max_leaves &&
+                        vused + nnew <= (unsigned long long)md.max_voxels;
+        st->ap.nt = nt;
+        st->ap.nseg = (uint32_t)nseg;
+        st->ap.ok = ok ? 1u : 0u;
+        st->ap.lused0 = lused;
+        st->ap.vused0 = vused;
+        if (ok) {
             st->leaves_used = lused + nl;
-            st->voxels_used = vused + nv;
+            st->voxels_used = vused + nnew;
         } else if (st->status == SLIM_OK) {
-            st->status = err;
+            st->status = SLIM_ERR_CAPACITY;
         }
         st->last_points = fp.n;
-        st->last_rejected = st->rejected;
-        st->last_pairs = st->pairs;
+        st->last_rejected = st->rejected.v;
+        st->last_pairs = st->pairs.v;
         st->last_touched = nt;
         st->last_new_leaves = nl;
-        st->last_u_old = (long long)st->u_old;
-        st->last_u_new = nv;
-        st->last_status = err;
-        st->n_touched = 0;
-        st->pairs = 0;
-        st->rejected = 0;
-        st->new_leaves = 0;
-        st->new_voxels = 0;
-        st->pair_cursor = 0;
-        st->u_old = 0;
-        st->frame_err = 0;
-        __threadfence();
-        st->done_blocks = 0;
+        st->last_u_old = (long long)(nseg - nnew);
+        st->last_u_new = (long long)nnew;
+        st->last_status = ok ? SLIM_OK : SLIM_ERR_CAPACITY;
+        st->n_touched.v = 0;
+        st->pairs.v = 0;
+        st->rejected.v = 0;
+        st->new_leaves.v = 0;
+        st->pair_cursor.v = 0;
+        st->frame_err.v = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 6. segment reduce and conjugate combine
+// ---------------------------------------------------------------------------
+
+struct Seg {
+    int4 d;        // first pair, pair count, record, meta
+    int slot;      // leaf slot (after creation for new leaves)
+    int leafnew;   // leaf is created by this frame
+    uint32_t pos;  // staging position of the leaf
+};
+
+// Locates global segment s: its leaf is the last j with leaf_base[j].x <= s,
+// searched between the leaves of the two enclosing chunk marks.
+__device__ __forceinline__ Seg find_segment(const MapDev &md, const ApplyParams &ap, uint32_t s)
+{
+    const uint32_t c = s / kSegChunk;
+    uint32_t lo = md.chunk_leaf[c];
+    uint32_t hi = (c + 1) * kSegChunk < ap.nseg ? md.chunk_leaf[c + 1] + 1 : ap.nt;
+    // invariant: leaf_base[lo].x <= s < leaf_base[hi].x (hi = nt: past the end)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (md.leaf_base[mid].x <= s) lo = mid;
+        else hi = mid;
+    }
+    const uint2 base = md.leaf_base[lo];
+    const int4 info = md.leaf_info[lo];
+    Seg g;
+    g.pos = (uint32_t)info.z;
+    g.d = md.seg_desc[info.x + (s - base.x)];
+    g.leafnew = info.y < 0;
+    g.slot = info.y >= 0 ? info.y : (int)(ap.lused0 + (unsigned long long)(-1 - info.y));
+    if (!((uint32_t)g.d.w & kSegExisted)) g.d.z = (int)(ap.vused0 + base.y + (uint32_t)g.d.z);
+    return g;
+}
+
+// Map bookkeeping of one applied segment: the first segment of a leaf creates
+// it (if new) and publishes its occupancy; a new voxel's record is indexed.
+__device__ __forceinline__ void segment_bookkeeping(const MapDev &md, const Seg &g)
+{
+    const uint32_t meta = (uint32_t)g.d.w;
+    if (meta & kSegFirst) {
+        if (g.leafnew) {
+            const unsigned long long key = md.skeys[g.pos];
+            map_insert(md, key, g.slot);
+            md.leaf_key[g.slot] = key;
+        }
+        for (int w = 0; w < kMaskWords; ++w)
+            md.leaf_occ[(size_t)g.slot * kMaskWords + w] = md.pos_occ[(size_t)g.pos * kMaskWords + w];
+    }
+    if (!(meta & kSegExisted)) md.leaf_index[(size_t)g.slot * kLeafVoxels + (meta & kSegOffMask)] = g.d.z;
+}
+
+// The first segment of each leaf clears the leaf's staging entry.
+__device__ __forceinline__ void clear_staging(const MapDev &md, const Seg &g)
+{
+    if ((uint32_t)g.d.w & kSegFirst) {
+        md.skeys[g.pos] = kEmptyKey;
+        md.pos_count[g.pos] = 0u;
+    }
+}
+
+// One lane per voxel segment; closed set with K <= KMAX classes kept in
+// registers (KMAX = 0: geometry only).  The record (D, W, counts) moves as
+// 16-byte vectors.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_segment_apply_lane(FrameParams fp, MapDev md)
+{
+    const ApplyParams ap = md.st->ap;
+    const int K = fp.K;
+    constexpr int KA = KMAX > 0 ? KMAX : 1;
+    constexpr int NV = (2 + KMAX + 3) / 4;  // float4 per record, at most
+    const int nv = md.rec_stride / 4;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t sgi = blockIdx.x * blockDim.x + threadIdx.x; sgi < ap.nseg; sgi += stride) {
+        const Seg g = find_segment(md, ap, sgi);
+        if (ap.ok) {
+            const int4 d = g.d;
+            const bool existed = ((uint32_t)d.w & kSegExisted) != 0;
+            float4 *R = (float4 *)(md.vox + (size_t)d.z * md.rec_stride);
+            float r[4 * NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const float4 x = (existed && v < nv) ? R[v] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                r[4 * v + 0] = x.x;
+                r[4 * v + 1] = x.y;
+                r[4 * v + 2] = x.z;
+                r[4 * v + 3] = x.w;
+            }
+            float acc[KA];
+#pragma unroll
+            for (int k = 0; k < KA; ++k) acc[k] = 0.0f;
+            float sum_t = 0.0f;
+            const uint32_t n = (uint32_t)d.y;
+            for (uint32_t c0 = 0; c0 < n; c0 += 8) {
+                uint32_t kk[8];
+                float tt[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    kk[q] = c0 + q < n ? md.srt_key[d.x + c0 + q] : 0u;
+                    tt[q] = c0 + q < n ? md.srt_tsdf[d.x + c0 + q] : 0.0f;
+                }
+                if (KMAX > 0 && fp.sem_kind == SLIM_IN_LABEL_I32) {
+                    int lab[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        lab[q] = c0 + q < n ? ((const int32_t *)fp.sem)[kk[q] & kPidMask] : -1;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+#pragma unroll
+                        for (int k = 0; k < KA; ++k) acc[k] += (lab[q] == k) ? 1.0f : 0.0f;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (c0 + q >= n) break;
+                    sum_t += tt[q];
+                    if (KMAX > 0 && fp.sem_kind != SLIM_IN_LABEL_I32) {
+                        const float *row = (const float *)fp.sem + (size_t)(kk[q] & kPidMask) * K;
+                        float x[KA];
+#pragma unroll
+                        for (int k = 0; k < KA; ++k) x[k] = k < K ? row[k] : 0.0f;
+                        if (fp.sem_kind == SLIM_IN_LOGIT_F32) {
+                            // softmax of the logits, max-subtracted
+                            float mx = x[0];
+#pragma unroll
+                            for (int k = 1; k < KA; ++k)
+                                if (k < K) mx = fmaxf(mx, x[k]);
+                            float den = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < KA; ++k) {
+                                x[k] = k < K ? expf(x[k] - mx) : 0.0f;
+                                den += x[k];
+                            }
+#pragma unroll
+                            for (int k = 0; k < KA; ++k) x[k] = x[k] / den;
+                        }
+#pragma unroll
+                        for (int k = 0; k < KA; ++k) acc[k] += x[k];
+                    }
+                }
+            }
+            // Eq. (1)-(2) with unit weights
+            const float nf = (float)n, W0 = r[1], W1 = W0 + nf;
+            r[0] = (W0 * r[0] + sum_t) / W1;
+            r[1] = W1;
+            // Eq. (6): concentrations grow by the (expected) class counts
+#pragma unroll
+            for (int k = 0; k < KA; ++k)
+                if (KMAX > 0 && k < K) r[2 + k] += acc[k];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v < nv) R[v] = make_float4(r[4 * v + 0], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
+            segment_bookkeeping(md, g);
+        }
+        clear_staging(md, g);
+    }
+}
+
+__device__ __forceinline__ float load_emb(const FrameParams &fp, uint32_t pid, int comp)
+{
+    const size_t idx = (size_t)pid * fp.L + comp;
+    return fp.sem_kind == SLIM_IN_EMB_BF16 ? __uint_as_float((uint32_t)((const uint16_t *)fp.sem)[idx] << 16)
+                                           : ((const float *)fp.sem)[idx];
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int d = 32; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// One wave per voxel segment; lane l owns components l, l + 64, ... of the
+// open-set statistics (L <= 1024) or of the class counts (K <= 256).
+constexpr int kWaveComps = 16;
+
+__global__ __launch_bounds__(256) void k_segment_apply_wave(FrameParams fp, MapDev md)
+{
+    const ApplyParams ap = md.st->ap;
+    const int lane = lane_id();
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const bool open = fp.L > 0;
+    const int C = open ? fp.L : fp.K;
+    for (uint32_t sgi = wave; sgi < ap.nseg; sgi += nwaves) {
+        const Seg g = find_segment(md, ap, sgi);
+        if (ap.ok) {
+            const int4 d = g.d;
+            const bool existed = ((uint32_t)d.w & kSegExisted) != 0;
+            float *R = md.vox + (size_t)d.z * md.rec_stride;
+            const uint32_t n = (uint32_t)d.y;
+            float s1[kWaveComps];
+#pragma unroll
+            for (int j = 0; j < kWaveComps; ++j) s1[j] = 0.0f;
+            float sum_t = 0.0f;
+            for (uint32_t c0 = 0; c0 < n; c0 += 64) {
+                const uint32_t my = c0 + lane < n ? md.srt_key[d.x + c0 + lane] : 0u;
+                const float myt = c0 + lane < n ? md.srt_tsdf[d.x + c0 + lane] : 0.0f;
+                const uint32_t cnt = min(64u, n - c0);
+                for (uint32_t q = 0; q < cnt; ++q) {
+                    const uint32_t pid = (uint32_t)__shfl((int)my, (int)q, 64) & kPidMask;
+                    sum_t += __shfl(myt, (int)q, 64);
+                    if (open) {
+#pragma unroll
+                        for (int j = 0; j < kWaveComps; ++j) {
+                            const int comp = lane + 64 * j;
+                            if (comp < C) s1[j] += load_emb(fp, pid, comp);
+                        }
+                    } else if (fp.sem_kind == SLIM_IN_LABEL_I32) {
+                        const int lab = ((const int32_t *)fp.sem)[pid];
+#pragma unroll
+                        for (int j = 0; j < kWaveComps; ++j) s1[j] += (lab == lane + 64 * j) ? 1.0f : 0.0f;
+                    } else if (fp.sem_kind == SLIM_IN_PROB_F32) {
+#pragma unroll
+                        for (int j = 0; j < kWaveComps; ++j) {
+                            const int comp = lane + 64 * j;
+                            if (comp < C) s1[j] += ((const float *)fp.sem)[(size_t)pid * C + comp];
+                        }
+                    } else {
+                        // logits, K <= 64: softmax across the wave
+                        const float l = lane < C ? ((const float *)fp.sem)[(size_t)pid * C + lane] : -INFINITY;
+                        const float mx = wave_max(l);
+                        const float e = lane < C ? expf(l - mx) : 0.0f;
+                        s1[0] += e / wave_sum(e);
+                    }
+                }
+            }
+            const float nf = (float)n;
+            const float W0 = existed ? R[1] : 0.0f, W1 = W0 + nf;
+            const float D0 = existed ? R[0] : 0.0f;
+            if (!open) {
+#pragma unroll
+                for (int j = 0; j < kWaveComps; ++j) {
+                    const int comp = lane + 64 * j;
+                    if (comp < C) R[2 + comp] = (existed ? R[2 + comp] : 0.0f) + s1[j];
+                }
+            } else {
+                // second pass: squared deviations from the batch mean
+                float zbar[kWaveComps], s2[kWaveComps];
+#pragma unroll
+                for (int j = 0; j < kWaveComps; ++j) {
+                    zbar[j] = s1[j] / nf;
+                    s2[j] = 0.0f;
+                }
+                for (uint32_t c0 = 0; c0 < n; c0 += 64) {
+                    const uint32_t my = c0 + lane < n ? md.srt_key[d.x + c0 + lane] : 0u;
+                    const uint32_t cnt = min(64u, n - c0);
+                    for (uint32_t q = 0; q < cnt; ++q) {
+                        const uint32_t pid = (uint32_t)__shfl((int)my, (int)q, 64) & kPidMask;
+#pragma unroll
+                        for (int j = 0; j < kWaveComps; ++j) {
+                            const int comp = lane + 64 * j;
+                            if (comp < C) {
+                                const float dz = load_emb(fp, pid, comp) - zbar[j];
+                                s2[j] += dz * dz;
+                            }
+                        }
+                    }
+                }
+                // Eqs. (11)-(14) with lambda = W, nu = W / 2
+                const float cross = W0 * nf / W1;
+                float *M = R + 2, *B = R + 2 + fp.L;
+#pragma unroll
+                for (int j = 0; j < kWaveComps; ++j) {
+                    const int comp = lane + 64 * j;
+                    if (comp < C) {
+                        const float m0 = existed ? M[comp] : 0.0f, b0 = existed ? B[comp] : 0.0f;
+                        const float dm = zbar[j] - m0;
+                        B[comp] = b0 + 0.5f * s2[j] + cross * dm * dm * 0.5f;
+                        M[comp] = (W0 * m0 + nf * zbar[j]) / W1;
+                    }
+                }
+            }
+            if (lane == 0) {
+                // Eq. (1)-(2) with unit weights
+                R[0] = (W0 * D0 + sum_t) / W1;
+                R[1] = W1;
+                segment_bookkeeping(md, g);
+            }
+        }
+        if (lane == 0) clear_staging(md, g);
     }
 }
 
@@ -627,35 +1030,38 @@ __global__ __launch_bounds__(kApplyThreads) void k_leaf_apply(FrameParams fp, Ma
 // launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_integrate(const FrameParams &fp, const MapDev &md, int apply_blocks, hipStream_t s,
-                            hipEvent_t *ev)
+hipError_t launch_integrate(const FrameParams &fp, const MapDev &md, int cus, hipStream_t s, hipEvent_t *ev)
 {
-    const int bw = (fp.n + 255) / 256;
+    const int bw = (fp.n + kWalkThreads - 1) / kWalkThreads;
     auto rec = [&](int e) {
         if (ev) (void)hipEventRecord(ev[e], s);
     };
     rec(0);
-    hipLaunchKernelGGL(k_ray_walk_emit, dim3(bw > 0 ? bw : 1), dim3(256), 0, s, fp, md);
+    hipLaunchKernelGGL(k_ray_walk_emit, dim3(bw > 0 ? bw : 1), dim3(kWalkThreads), 0, s, fp, md);
     rec(1);
     rec(2);
-    hipLaunchKernelGGL(k_leaf_plan, dim3(256), dim3(256), 0, s, md);
+    hipLaunchKernelGGL(k_leaf_plan, dim3(cus), dim3(256), 0, s, md);
     rec(3);
     rec(4);
-    hipLaunchKernelGGL(k_pair_bucket, dim3(1024), dim3(256), 0, s, md);
+    const int bb = (int)std::min<long long>(((long long)fp.n * fp.maxsteps + 255) / 256, (long long)cus * 16);
+    hipLaunchKernelGGL(k_pair_bucket, dim3(bb > 0 ? bb : 1), dim3(256), 0, s, md);
     rec(5);
-    int G = 1;
-    if (fp.sem_kind != SLIM_IN_NONE) {
-        const int want = (fp.nsem == 0) ? 1 : (fp.L > 0 ? 64 : fp.K);
-        while (G < want && G < 64) G <<= 1;
-    }
     rec(6);
-    if (fp.L > 0)
-        hipLaunchKernelGGL(k_leaf_apply<SLIM_SEM_OPEN>, dim3(apply_blocks), dim3(kApplyThreads), 0, s, fp, md, G);
-    else if (fp.K > 0)
-        hipLaunchKernelGGL(k_leaf_apply<SLIM_SEM_CLOSED>, dim3(apply_blocks), dim3(kApplyThreads), 0, s, fp, md, G);
-    else
-        hipLaunchKernelGGL(k_leaf_apply<SLIM_SEM_NONE>, dim3(apply_blocks), dim3(kApplyThreads), 0, s, fp, md, G);
+    hipLaunchKernelGGL(k_leaf_sort, dim3(cus * 8), dim3(kSortThreads), 0, s, md);
     rec(7);
+    rec(8);
+    hipLaunchKernelGGL(k_frame_alloc, dim3(1), dim3(1024), 0, s, fp, md);
+    rec(9);
+    rec(10);
+    const bool wave = fp.L > 0 || fp.K > 32;
+    const dim3 ga(cus * 8), blk(256);
+    if (wave) hipLaunchKernelGGL(k_segment_apply_wave, ga, blk, 0, s, fp, md);
+    else if (fp.K > 24) hipLaunchKernelGGL(k_segment_apply_lane<32>, ga, blk, 0, s, fp, md);
+    else if (fp.K > 16) hipLaunchKernelGGL(k_segment_apply_lane<24>, ga, blk, 0, s, fp, md);
+    else if (fp.K > 8) hipLaunchKernelGGL(k_segment_apply_lane<16>, ga, blk, 0, s, fp, md);
+    else if (fp.K > 0) hipLaunchKernelGGL(k_segment_apply_lane<8>, ga, blk, 0, s, fp, md);
+    else hipLaunchKernelGGL(k_segment_apply_lane<0>, ga, blk, 0, s, fp, md);
+    rec(11);
     return hipGetLastError();
 }
 
@@ -687,7 +1093,6 @@ hipError_t launch_reset(const MapDev &md, hipStream_t s)
     hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, s, md.hkeys, cap, kEmptyKey);
     hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, s, md.skeys, cap, kEmptyKey);
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, md.pos_count, cap, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, md.pos_mask, cap * kMaskWords, 0u);
     hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, md.st);
     return hipGetLastError();
 }
@@ -701,8 +1106,9 @@ __global__ void k_collect_leaves(const MapDev md, long long nleaves, unsigned lo
     }
 }
 
-// One compare-exchange step of the mirrored bitonic network over n elements
-// (virtual +infinity beyond n), in global memory.
+// One compare-exchange step of a bitonic network over n elements (virtual
+// +infinity beyond n) in global memory.  The first step of each stage compares
+// mirrored positions, so every block sorts ascending.
 __global__ void k_bitonic_step(unsigned long long *keys, int32_t *vals, long long n, long long k, long long d,
                                int mirrored, long long half)
 {
@@ -770,19 +1176,16 @@ __global__ __launch_bounds__(256) void k_extract(const MapDev md, long long nlea
         const uint32_t *occ = md.leaf_occ + (size_t)slot * kMaskWords;
         for (int t = threadIdx.x; t < kLeafVoxels; t += blockDim.x) {
             if (!((occ[t >> 5] >> (t & 31)) & 1u)) continue;
-            uint32_t rank = 0;
-            for (int q = 0; q < (t >> 5); ++q) rank += __popc(occ[q]);
-            rank += __popc(occ[t >> 5] & ((1u << (t & 31)) - 1u));
-            const size_t o = (size_t)offsets[j] + rank;
+            const size_t o = (size_t)offsets[j] + bits_below(occ, (uint32_t)t);
             const long long rec = md.leaf_index[(size_t)slot * kLeafVoxels + t];
+            const float *R = md.vox + (size_t)rec * md.rec_stride;
             keys[3 * o + 0] = lx * 8 + (t >> 6);
             keys[3 * o + 1] = ly * 8 + ((t >> 3) & 7);
             keys[3 * o + 2] = lz * 8 + (t & 7);
-            const float2 dw = md.vox_dw[rec];
-            d[o] = dw.x;
-            w[o] = dw.y;
+            d[o] = R[0];
+            w[o] = R[1];
             if (sem)
-                for (int k = 0; k < nsem; ++k) sem[o * nsem + k] = md.vox_sem[(size_t)rec * nsem + k];
+                for (int k = 0; k < nsem; ++k) sem[o * nsem + k] = R[2 + k];
         }
     }
 }
@@ -831,11 +1234,11 @@ __global__ __launch_bounds__(256) void k_query(const MapDev md, int nsem, float 
             }
         }
         if (rec >= 0) {
-            const float2 dw = md.vox_dw[rec];
-            d[i] = dw.x;
-            w[i] = dw.y;
+            const float *R = md.vox + (size_t)rec * md.rec_stride;
+            d[i] = R[0];
+            w[i] = R[1];
             if (sem)
-                for (int k = 0; k < nsem; ++k) sem[i * nsem + k] = md.vox_sem[(size_t)rec * nsem + k];
+                for (int k = 0; k < nsem; ++k) sem[i * nsem + k] = R[2 + k];
         } else {
             d[i] = 0.0f;
             w[i] = 0.0f;
