@@ -119,8 +119,8 @@ def main():
     b_alg = bytes_points + bytes_sem + bytes_state
 
     # dominant kernel and its algorithmic bytes
-    kalg = {"ray_walk_emit": bytes_points, "leaf_plan": 0, "pair_bucket": 0, "leaf_sort": 0, "frame_alloc": 0,
-            "segment_apply": bytes_sem + bytes_state}
+    kalg = {"ray_walk_emit": bytes_points, "leaf_plan": 0, "pair_bucket": 0, "leaf_fuse": bytes_sem + bytes_state,
+            "frame_commit": 0}
     dom = max(kern, key=lambda k: kern[k][0])
     dom_ms, dom_n = kern[dom]
     dom_avg_s = dom_ms / 1e3 / max(dom_n, 1)

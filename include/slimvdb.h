@@ -67,7 +67,9 @@ typedef struct slim_map_config {
     int32_t embed_dim;  /* L, 1..1024, open set only */
     int32_t device;     /* HIP device ordinal that holds the map */
     int64_t max_leaves; /* capacity in 8^3 leaves, 1 .. 2^26 */
-    int64_t max_voxels; /* capacity in voxel records, 1 .. 2^31 - 1 */
+    int64_t max_voxels; /* capacity in voxel records, 1 .. 2^31 - 1; records are allocated per
+                           8 x 8-voxel slab of a leaf, so this rounds up to a multiple of 64 and
+                           a slab holds 64 records once any of its voxels is observed */
 } slim_map_config;
 
 typedef struct slim_stats {
@@ -147,9 +149,9 @@ slim_status slim_query(slim_map *map, const float *xyz_dev, int64_t m, float *d_
  * with HIP events on the stream it launches on; slim_profile_read returns the
  * accumulated per-kernel time in milliseconds and launch counts (index 0 ray
  * walk and pair emission, 1 leaf planning, 2 pair bucketing, 3 per-leaf sort,
- * 4 allocation and commit, 5 per-voxel reduce and combine) and resets them.
- * Reading synchronises `stream`.  n_kernels is the length of ms_host and
- * launches_host; the call writes min(n_kernels, 6) entries. */
+ * reduce and combine, 4 commit) and resets them.  Reading synchronises
+ * `stream`.  n_kernels is the length of ms_host and launches_host; the call
+ * writes min(n_kernels, 5) entries. */
 slim_status slim_profile_enable(slim_map *map, int32_t enable);
 slim_status slim_profile_read(slim_map *map, double *ms_host, int64_t *launches_host, int32_t n_kernels,
                               void *stream);

@@ -94,6 +94,8 @@ class OracleMap:
         self.h = self._L.om_create(voxel_size, sdf_trunc, min_range, max_range, sem_mode, num_classes, embed_dim)
         if not self.h:
             raise ValueError("invalid oracle map configuration")
+        self.voxel_size = float(np.float32(voxel_size))
+        self.sdf_trunc = float(np.float32(sdf_trunc))
         self.sem_mode = sem_mode
         self.K = num_classes
         self.L = embed_dim

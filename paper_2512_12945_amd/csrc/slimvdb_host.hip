@@ -142,8 +142,8 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s)
     size_t cap = std::max<size_t>(need, m->pair_cap + m->pair_cap / 2);
     cap = std::min<size_t>(cap, 0xFFFFFFF0ull);
     MapDev &md = m->md;
-    void *ptrs[10] = {md.pair_pos, md.pair_rank, md.pair_key, md.pair_tsdf, md.srt_key,
-                      md.srt_tsdf, md.tmp_key,   md.tmp_tsdf, md.seg_desc, md.chunk_leaf};
+    void *ptrs[8] = {md.pair_pos, md.pair_rank, md.pair_key, md.pair_tsdf,
+                     md.srt_key,  md.srt_tsdf,  md.tmp_key,  md.tmp_tsdf};
     for (void *p : ptrs) {
         if (!p) continue;
         (void)hipFree(p);
@@ -151,14 +151,11 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s)
     }
     md.pair_pos = md.pair_rank = md.pair_key = md.srt_key = md.tmp_key = nullptr;
     md.pair_tsdf = md.srt_tsdf = md.tmp_tsdf = nullptr;
-    md.seg_desc = nullptr;
-    md.chunk_leaf = nullptr;
     slim_status r;
     if ((r = dalloc(m, &md.pair_pos, cap)) || (r = dalloc(m, &md.pair_rank, cap)) ||
         (r = dalloc(m, &md.pair_key, cap)) || (r = dalloc(m, &md.pair_tsdf, cap)) ||
         (r = dalloc(m, &md.srt_key, cap)) || (r = dalloc(m, &md.srt_tsdf, cap)) ||
-        (r = dalloc(m, &md.tmp_key, cap)) || (r = dalloc(m, &md.tmp_tsdf, cap)) ||
-        (r = dalloc(m, &md.seg_desc, cap)) || (r = dalloc(m, &md.chunk_leaf, cap / kSegChunk + 2))) {
+        (r = dalloc(m, &md.tmp_key, cap)) || (r = dalloc(m, &md.tmp_tsdf, cap))) {
         m->pair_cap = 0;
         md.pair_cap = 0;
         return r;
@@ -222,17 +219,17 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
     MapDev &md = m->md;
     md.hmask = (uint32_t)(cap - 1);
     md.max_leaves = config->max_leaves;
-    md.max_voxels = config->max_voxels;
+    md.max_pages = (config->max_voxels + kPageVoxels - 1) / kPageVoxels;
     md.rec_stride = record_stride(m->nsem);
-    const size_t L = (size_t)config->max_leaves, V = (size_t)config->max_voxels;
+    md.leaf_blocks = m->cus * 8;
+    const size_t L = (size_t)config->max_leaves, NP = (size_t)md.max_pages;
     if ((r = dalloc(m, &md.hkeys, cap)) || (r = dalloc(m, &md.hvals, cap)) || (r = dalloc(m, &md.skeys, cap)) ||
         (r = dalloc(m, &md.touched, cap)) || (r = dalloc(m, &md.pos_count, cap)) ||
-        (r = dalloc(m, &md.pos_occ, cap * kMaskWords)) || (r = dalloc(m, &md.pos_plan, cap)) ||
-        (r = dalloc(m, &md.leaf_cnt, cap)) || (r = dalloc(m, &md.leaf_base, cap)) ||
-        (r = dalloc(m, &md.leaf_info, cap)) ||
-        (r = dalloc(m, &md.leaf_key, L)) || (r = dalloc(m, &md.leaf_index, L * kLeafVoxels)) ||
-        (r = dalloc(m, &md.leaf_occ, L * kMaskWords)) || (r = dalloc(m, &md.vox, V * (size_t)md.rec_stride)) ||
-        (r = dalloc(m, &md.st, 1))) {
+        (r = dalloc(m, &md.pos_slab, cap)) || (r = dalloc(m, &md.pos_plan, cap)) ||
+        (r = dalloc(m, &md.pos_pages, 2 * cap)) || (r = dalloc(m, &md.leaf_key, L)) ||
+        (r = dalloc(m, &md.leaf_page, L * kLeafPages)) || (r = dalloc(m, &md.leaf_occ, L * kMaskWords)) ||
+        (r = dalloc(m, &md.vox, NP * kPageVoxels * (size_t)md.rec_stride)) ||
+        (r = dalloc(m, &md.blk_stats, (size_t)md.leaf_blocks)) || (r = dalloc(m, &md.st, 1))) {
         free_all(m);
         delete m;
         return r;

@@ -2,27 +2,27 @@
 //
 // One frame runs as five kernels on the map's stream:
 //   1. ray_walk_emit  one lane per point: pose application, ray, band, voxel
-//                     walk (Sec. III-A), truncation gate; the leaf runs of each
-//                     ray are staged in a frame-local leaf table and every kept
-//                     (voxel, point) observation is written as a pair.
+//                     walk (Sec. III-A), truncation gate.  The leaves the
+//                     block's rays touch are collected in an LDS table, so each
+//                     (block, leaf) makes one staging insert and one bucket
+//                     reservation; every kept (voxel, point) observation is
+//                     written as a pair.
 //   2. leaf_plan      one lane per touched leaf: find it in the map (or number
-//                     it as new) and allocate its pair bucket.
+//                     it as new), number record pages for newly touched 8x8
+//                     slabs, allocate its pair bucket.
 //   3. pair_bucket    one lane per pair: scatter into its leaf's bucket.
-//   4. leaf_sort      one workgroup per touched leaf: counting sort of the
+//   4. leaf_fuse      one workgroup per touched leaf: counting sort of the
 //                     bucket by voxel offset in LDS, then by point index inside
-//                     each voxel; one segment descriptor per touched voxel
-//                     (record of an existing voxel, or a new record numbered in
-//                     offset order).
-//   5. segment_apply  one lane (closed set, K <= 32) or one wave (open set,
-//                     wider K) per voxel segment: reduce its observations in
-//                     point order and combine them with the stored state --
-//                     Eq. (1)-(2) for D and W, Eq. (6) for the class counts,
-//                     Eqs. (11)-(14) with lambda = 2 nu = W for the open-set
-//                     mean and beta.  Its last workgroup commits the frame.
-// Kernels 1-4 only read the map; the capacity check at the start of kernel 5
-// precedes every map write, so a frame that does not fit changes nothing.  No
-// floating-point atomics are used: each voxel's sums are formed in point order,
-// so results are bitwise repeatable and independent of launch shapes.
+//                     each voxel, and the conjugate combine of every touched
+//                     voxel in point order -- Eq. (1)-(2) for D and W, Eq. (6)
+//                     for the class counts, Eqs. (11)-(14) with
+//                     lambda = 2 nu = W for the open-set mean and beta.
+//   5. frame_commit   one workgroup: counters, status, frame reset.
+// Kernels 1-3 only read the map, and kernel 4 writes it only if the frame's new
+// leaves and record pages fit (decided from totals that kernel 2 completed), so
+// a frame that does not fit changes nothing.  No floating-point atomics are
+// used: each voxel's sums are formed in point order, so results are bitwise
+// repeatable and independent of launch shapes.
 //
 // The geometric decision path (pose, ray, walk, gate) is a fixed sequence of
 // binary32 operations; build with -ffp-contract=off so that only the fmaf()
@@ -232,6 +232,18 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, 
     return before + incl - v;
 }
 
+// Exclusive prefix sum of 512 LDS counters by 256 threads.
+__device__ void block_scan512(const uint32_t *in, uint32_t *out, uint32_t *wsum)
+{
+    const int t = threadIdx.x;
+    const uint32_t a = in[2 * t], b = in[2 * t + 1];
+    uint32_t total;
+    const uint32_t ex = block_excl_scan(a + b, wsum, &total);
+    out[2 * t] = ex;
+    out[2 * t + 1] = ex + a;
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // 1. ray walk and pair emission
 // ---------------------------------------------------------------------------
@@ -249,6 +261,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, 
     __shared__ unsigned long long t_key[kWalkTable];
     __shared__ uint32_t t_cnt[kWalkTable];   // pairs of this block in the leaf, then their first bucket rank
     __shared__ uint32_t t_pos[kWalkTable];   // staging position
+    __shared__ uint32_t t_slab[kWalkTable];  // x-slabs of the leaf this block touches
     __shared__ uint32_t t_list[kWalkTable];  // occupied entries
     __shared__ uint32_t t_fresh[kWalkTable]; // staging positions this block inserted
     __shared__ uint32_t s_n, s_nfresh, s_fresh_base, s_pair_base, wsum[4];
@@ -257,6 +270,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, 
     for (int e = tid; e < kWalkTable; e += blockDim.x) {
         t_key[e] = kEmptyKey;
         t_cnt[e] = 0;
+        t_slab[e] = 0;
     }
     if (tid == 0) {
         s_n = 0;
@@ -280,11 +294,12 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, 
     uint32_t cnt = 0;
     int nruns = 0;
     unsigned long long rkey[kMaxRuns];
-    uint32_t rlen[kMaxRuns];
+    uint32_t rlen[kMaxRuns], rslab[kMaxRuns];
 #pragma unroll
     for (int q = 0; q < kMaxRuns; ++q) {
         rkey[q] = kEmptyKey;
         rlen[q] = 0;
+        rslab[q] = 0;
     }
     if (valid) {
         bool inrange = true;
@@ -306,7 +321,10 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, 
             }
 #pragma unroll
             for (int q = 0; q < kMaxRuns; ++q)
-                if (q == nruns - 1) rlen[q]++;
+                if (q == nruns - 1) {
+                    rlen[q]++;
+                    rslab[q] |= 1u << (kx & 7);
+                }
             cnt++;
         });
         if (!inrange || nruns > kMaxRuns) valid = false;
@@ -320,7 +338,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, 
     uint32_t rent[kMaxRuns], rloc[kMaxRuns];
 #pragma unroll
     for (int q = 0; q < kMaxRuns; ++q) {
-        rent[q] = 0;
+        rent[q] = kWalkTable;
         rloc[q] = 0;
         if (q < nruns) {
             // distinct keys <= runs of the block <= table size, so a free or
@@ -343,15 +361,15 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, 
             if (found) {
                 rent[q] = h;
                 rloc[q] = atomicAdd(&t_cnt[h], rlen[q]);
+                atomicOr(&t_slab[h], rslab[q]);
             } else {
-                rent[q] = kWalkTable;  // no entry: pairs of this run are dropped, frame rejected
-                atomicOr(&md.st->frame_err.v, 1u);
+                atomicOr(&md.st->frame_err.v, 1u);  // pairs of this run are dropped, frame rejected
             }
         }
     }
     __syncthreads();
 
-    // one staging lookup and one bucket reservation per leaf of the block
+    // one staging lookup, one bucket reservation and one slab update per leaf of the block
     const uint32_t nloc = s_n;
     for (uint32_t e = tid; e < nloc; e += blockDim.x) {
         const uint32_t h = t_list[e];
@@ -360,6 +378,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, 
         t_pos[h] = pos;
         if (pos != kNoPos) {
             t_cnt[h] = atomicAdd(&md.pos_count[pos], t_cnt[h]);
+            atomicOr(&md.pos_slab[pos], t_slab[h]);
             if (fresh) t_fresh[atomicAdd(&s_nfresh, 1u)] = pos;
         } else {
             atomicOr(&md.st->frame_err.v, 1u);
@@ -417,20 +436,42 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, 
 __global__ __launch_bounds__(256) void k_leaf_plan(MapDev md)
 {
     const uint32_t nt = md.st->n_touched.v;
+    const unsigned long long pused = md.st->pages_used;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t jb = blockIdx.x * blockDim.x; jb < nt; jb += stride) {
         const uint32_t j = jb + threadIdx.x;
         const bool act = j < nt;
         int32_t slot = -1;
-        uint32_t npairs = 0, pos = 0;
+        uint32_t npairs = 0, pos = 0, need = 0;
+        int pg[kLeafPages];
+#pragma unroll
+        for (int q = 0; q < kLeafPages; ++q) pg[q] = -1;
         if (act) {
             pos = md.touched[j];
             slot = map_find(md, md.skeys[pos]);
             npairs = md.pos_count[pos];
+            uint32_t have = 0;
+            if (slot >= 0) {
+                const int4 p0 = ((const int4 *)md.leaf_page)[2 * slot], p1 = ((const int4 *)md.leaf_page)[2 * slot + 1];
+                pg[0] = p0.x; pg[1] = p0.y; pg[2] = p0.z; pg[3] = p0.w;
+                pg[4] = p1.x; pg[5] = p1.y; pg[6] = p1.z; pg[7] = p1.w;
+#pragma unroll
+                for (int q = 0; q < kLeafPages; ++q) have |= (pg[q] >= 0 ? 1u : 0u) << q;
+            }
+            need = md.pos_slab[pos] & ~have & 0xFFu;
         }
         const uint32_t newleaf = wave_reserve(&md.st->new_leaves.v, (act && slot < 0) ? 1u : 0u);
+        const uint32_t pbase = wave_reserve(&md.st->new_pages.v, __popc(need));
         const uint32_t bstart = wave_reserve(&md.st->pair_cursor.v, npairs);
-        if (act) md.pos_plan[pos] = make_int4(slot, slot < 0 ? (int)newleaf : -1, (int)bstart, 0);
+        if (act) {
+            uint32_t r = 0;
+#pragma unroll
+            for (int q = 0; q < kLeafPages; ++q)
+                if ((need >> q) & 1u) pg[q] = (int)(pused + pbase + r++);
+            md.pos_pages[2 * pos] = make_int4(pg[0], pg[1], pg[2], pg[3]);
+            md.pos_pages[2 * pos + 1] = make_int4(pg[4], pg[5], pg[6], pg[7]);
+            md.pos_plan[pos] = make_int4(slot, slot < 0 ? (int)newleaf : -1, (int)bstart, 0);
+        }
     }
 }
 
@@ -452,448 +493,17 @@ __global__ __launch_bounds__(256) void k_pair_bucket(MapDev md)
 }
 
 // ---------------------------------------------------------------------------
-// 4. per-leaf sort and segment descriptors
+// 4. per-leaf sort, reduce and conjugate combine
 // ---------------------------------------------------------------------------
 
-// Exclusive prefix sum of 512 LDS counters by 256 threads.
-__device__ void block_scan512(const uint32_t *in, uint32_t *out, uint32_t *wsum)
-{
-    const int t = threadIdx.x;
-    const uint32_t a = in[2 * t], b = in[2 * t + 1];
-    uint32_t total;
-    const uint32_t ex = block_excl_scan(a + b, wsum, &total);
-    out[2 * t] = ex;
-    out[2 * t + 1] = ex + a;
-    __syncthreads();
-}
-
-__device__ __forceinline__ uint32_t bits_below(const uint32_t *mask, uint32_t o)
-{
-    uint32_t r = 0;
-    for (uint32_t w = 0; w < (o >> 5); ++w) r += __popc(mask[w]);
-    return r + __popc(mask[o >> 5] & ((1u << (o & 31)) - 1u));
-}
-
-__global__ __launch_bounds__(kSortThreads) void k_leaf_sort(MapDev md)
-{
-    __shared__ uint32_t b_key[kSortLdsPairs];
-    __shared__ float b_val[kSortLdsPairs];
-    __shared__ uint32_t hist[kLeafVoxels], bin0[kLeafVoxels], cur[kLeafVoxels];
-    __shared__ uint32_t s_touch[kMaskWords], s_new[kMaskWords], s_occ0[kMaskWords], wsum[4];
-    __shared__ uint32_t s_pre_t[kMaskWords], s_pre_n[kMaskWords];
-    __shared__ uint32_t s_chunk_end, s_nseg, s_nnew;
-
-    const uint32_t nt = md.st->n_touched.v;
-    const int tid = threadIdx.x;
-
-    for (uint32_t j = blockIdx.x; j < nt; j += gridDim.x) {
-        const uint32_t pos = md.touched[j];
-        const int4 plan = md.pos_plan[pos];
-        const uint32_t n = md.pos_count[pos];
-        const int slot = plan.x;
-        for (int o = tid; o < kLeafVoxels; o += blockDim.x) hist[o] = 0;
-        if (tid < kMaskWords) s_occ0[tid] = slot >= 0 ? md.leaf_occ[(size_t)slot * kMaskWords + tid] : 0u;
-        __syncthreads();
-
-        uint32_t *gk = md.srt_key + plan.z;
-        float *gv = md.srt_tsdf + plan.z;
-        uint32_t *tk = md.tmp_key + plan.z;
-        float *tv = md.tmp_tsdf + plan.z;
-
-        // histogram of voxel offsets; loads go out kSortBatch at a time per thread,
-        // and a bucket that fits LDS stays in registers until its scatter
-        uint32_t rk[kSortBatch];
-        float rv[kSortBatch];
-        const bool small = n <= (uint32_t)(kSortBatch * kSortThreads);
-        for (uint32_t t0 = 0; t0 < n; t0 += kSortBatch * kSortThreads) {
-#pragma unroll
-            for (int u = 0; u < kSortBatch; ++u) {
-                const uint32_t t = t0 + u * kSortThreads + tid;
-                rk[u] = t < n ? gk[t] : 0u;
-                rv[u] = t < n ? gv[t] : 0.0f;
-            }
-#pragma unroll
-            for (int u = 0; u < kSortBatch; ++u)
-                if (t0 + u * kSortThreads + tid < n) atomicAdd(&hist[rk[u] >> kPidBits], 1u);
-        }
-        __syncthreads();
-        block_scan512(hist, bin0, wsum);
-        for (int o = tid; o < kLeafVoxels; o += blockDim.x) cur[o] = bin0[o];
-        {
-            // touched offsets: wave w covers bins 64w + [0, 64) and 256 + 64w + [0, 64)
-            const int w = tid >> 6;
-            const unsigned long long b0 = __ballot(hist[tid] != 0u);
-            const unsigned long long b1 = __ballot(hist[tid + 256] != 0u);
-            if (lane_id() == 0) {
-                s_touch[2 * w] = (uint32_t)b0;
-                s_touch[2 * w + 1] = (uint32_t)(b0 >> 32);
-                s_touch[8 + 2 * w] = (uint32_t)b1;
-                s_touch[9 + 2 * w] = (uint32_t)(b1 >> 32);
-            }
-        }
-        __syncthreads();
-        if (tid < kMaskWords) s_new[tid] = s_touch[tid] & ~s_occ0[tid];
-        if (tid == 0) {
-            uint32_t a = 0, b = 0;
-            for (int w = 0; w < kMaskWords; ++w) {
-                s_pre_t[w] = a;
-                s_pre_n[w] = b;
-                a += __popc(s_touch[w]);
-                b += __popc(s_touch[w] & ~s_occ0[w]);
-            }
-            s_nseg = a;
-            s_nnew = b;
-        }
-        __syncthreads();
-
-        if (small) {
-            // bin by offset in LDS (order inside a bin arbitrary), then order each
-            // bin by point index: rank = number of smaller keys in the bin
-#pragma unroll
-            for (int u = 0; u < kSortBatch; ++u)
-                if ((uint32_t)(u * kSortThreads + tid) < n) {
-                    const uint32_t p = atomicAdd(&cur[rk[u] >> kPidBits], 1u);
-                    b_key[p] = rk[u];
-                    b_val[p] = rv[u];
-                }
-            __syncthreads();
-            for (uint32_t t = tid; t < n; t += blockDim.x) {
-                const uint32_t k = b_key[t];
-                const uint32_t o = k >> kPidBits, lo = bin0[o], hi = lo + hist[o];
-                uint32_t r = 0;
-#pragma unroll 8
-                for (uint32_t u = lo; u < hi; ++u) r += b_key[u] < k;
-                gk[lo + r] = k;
-                gv[lo + r] = b_val[t];
-            }
-        } else {
-            // large leaf: bin into the scratch buffer, then rank runs of whole
-            // bins that fit in LDS (a single bin larger than LDS ranks in place)
-            for (uint32_t t0 = 0; t0 < n; t0 += kSortBatch * kSortThreads) {
-#pragma unroll
-                for (int u = 0; u < kSortBatch; ++u) {
-                    const uint32_t t = t0 + u * kSortThreads + tid;
-                    rk[u] = t < n ? gk[t] : 0u;
-                    rv[u] = t < n ? gv[t] : 0.0f;
-                }
-#pragma unroll
-                for (int u = 0; u < kSortBatch; ++u)
-                    if (t0 + u * kSortThreads + tid < n) {
-                        const uint32_t p = atomicAdd(&cur[rk[u] >> kPidBits], 1u);
-                        tk[p] = rk[u];
-                        tv[p] = rv[u];
-                    }
-            }
-            __syncthreads();
-            uint32_t o0 = 0;
-            while (o0 < (uint32_t)kLeafVoxels) {
-                if (tid == 0) {
-                    // bin ends are non-decreasing: first o1 > o0 whose end
-                    // passes bin0[o0] + capacity (at least o0 + 1)
-                    const uint32_t lim = bin0[o0] + (uint32_t)kSortLdsPairs;
-                    uint32_t lo = o0 + 1, hi = kLeafVoxels;
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (bin0[mid] + hist[mid] <= lim) lo = mid + 1;
-                        else hi = mid;
-                    }
-                    s_chunk_end = lo;
-                }
-                __syncthreads();
-                const uint32_t o1 = s_chunk_end;
-                const uint32_t lo = bin0[o0], hi = (o1 < (uint32_t)kLeafVoxels) ? bin0[o1] : n;
-                if (hi - lo <= (uint32_t)kSortLdsPairs) {
-#pragma unroll
-                    for (int u = 0; u < kSortBatch; ++u) {
-                        const uint32_t t = lo + u * kSortThreads + tid;
-                        rk[u] = t < hi ? tk[t] : 0u;
-                        rv[u] = t < hi ? tv[t] : 0.0f;
-                    }
-#pragma unroll
-                    for (int u = 0; u < kSortBatch; ++u) {
-                        const uint32_t t = lo + u * kSortThreads + tid;
-                        if (t < hi) {
-                            b_key[t - lo] = rk[u];
-                            b_val[t - lo] = rv[u];
-                        }
-                    }
-                    __syncthreads();
-                    for (uint32_t t = lo + tid; t < hi; t += blockDim.x) {
-                        const uint32_t k = b_key[t - lo];
-                        const uint32_t o = k >> kPidBits, blo = bin0[o], bhi = blo + hist[o];
-                        uint32_t r = 0;
-#pragma unroll 8
-                        for (uint32_t u = blo; u < bhi; ++u) r += b_key[u - lo] < k;
-                        gk[blo + r] = k;
-                        gv[blo + r] = b_val[t - lo];
-                    }
-                } else {
-                    for (uint32_t t = lo + tid; t < hi; t += blockDim.x) {
-                        const uint32_t k = tk[t];
-                        uint32_t r = 0;
-                        for (uint32_t u = lo; u < hi; ++u) r += tk[u] < k;
-                        gk[lo + r] = k;
-                        gv[lo + r] = tv[t];
-                    }
-                }
-                __syncthreads();
-                o0 = o1;
-            }
-        }
-
-        // one descriptor per touched voxel, at bucket start + voxel rank
-        if (tid < kMaskWords) md.pos_occ[(size_t)pos * kMaskWords + tid] = s_occ0[tid] | s_touch[tid];
-        if (tid == 0) {
-            md.leaf_cnt[j] = make_uint2(s_nseg, s_nnew);
-            md.leaf_info[j] = make_int4(plan.z, slot >= 0 ? slot : -1 - plan.y, (int)pos, 0);
-        }
-        for (int o = tid; o < kLeafVoxels; o += blockDim.x) {
-            if (!hist[o]) continue;
-            const uint32_t below = (1u << (o & 31)) - 1u;
-            const uint32_t rank = s_pre_t[o >> 5] + __popc(s_touch[o >> 5] & below);
-            const bool existed = (s_occ0[o >> 5] >> (o & 31)) & 1u;
-            const int rec = existed ? md.leaf_index[(size_t)slot * kLeafVoxels + o]
-                                    : (int)(s_pre_n[o >> 5] + __popc(s_new[o >> 5] & below));
-            const uint32_t meta = (uint32_t)o | (existed ? kSegExisted : 0u) | (rank == 0 ? kSegFirst : 0u);
-            md.seg_desc[plan.z + rank] = make_int4((int)(plan.z + bin0[o]), (int)hist[o], rec, (int)meta);
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// 5. allocation, capacity decision and commit (one workgroup)
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(1024) void k_frame_alloc(FrameParams fp, MapDev md)
-{
-    __shared__ uint32_t wsum[16][2];
-    __shared__ uint32_t carry[2];
-    DevState *st = md.st;
-    const uint32_t nt = st->n_touched.v;
-    const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
-    if (tid == 0) carry[0] = carry[1] = 0;
-    __syncthreads();
-    for (uint32_t b = 0; b < nt; b += 1024) {
-        const uint32_t j = b + tid;
-        const uint2 c = j < nt ? md.leaf_cnt[j] : make_uint2(0u, 0u);
-        const uint32_t i0 = wave_incl_scan(c.x), i1 = wave_incl_scan(c.y);
-        if (lane == 63) {
-            wsum[w][0] = i0;
-            wsum[w][1] = i1;
-        }
-        __syncthreads();
-        uint32_t b0 = carry[0], b1 = carry[1], t0 = 0, t1 = 0;
-        for (int q = 0; q < 16; ++q) {
-            if (q < w) {
-                b0 += wsum[q][0];
-                b1 += wsum[q][1];
-            }
-            t0 += wsum[q][0];
-            t1 += wsum[q][1];
-        }
-        if (j < nt) {
-            const uint32_t sb = b0 + i0 - c.x;
-            md.leaf_base[j] = make_uint2(sb, b1 + i1 - c.y);
-            // leaf of every segment whose index is a multiple of kSegChunk
-            for (uint32_t q = (sb + kSegChunk - 1) / kSegChunk; q * kSegChunk < sb + c.x; ++q) md.chunk_leaf[q] = j;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            carry[0] += t0;
-            carry[1] += t1;
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        const unsigned long long nseg = carry[0], nnew = carry[1], nl = st->new_leaves.v;
-        const unsigned long long lused = st->leaves_used, vused = st->voxels_used;
-        const bool ok = st->frame_err.v == 0 && lused + nl <= (unsigned long long)md.max_leaves &&
-                        vused + nnew <= (unsigned long long)md.max_voxels;
-        st->ap.nt = nt;
-        st->ap.nseg = (uint32_t)nseg;
-        st->ap.ok = ok ? 1u : 0u;
-        st->ap.lused0 = lused;
-        st->ap.vused0 = vused;
-        if (ok) {
-            st->leaves_used = lused + nl;
-            st->voxels_used = vused + nnew;
-        } else if (st->status == SLIM_OK) {
-            st->status = SLIM_ERR_CAPACITY;
-        }
-        st->last_points = fp.n;
-        st->last_rejected = st->rejected.v;
-        st->last_pairs = st->pairs.v;
-        st->last_touched = nt;
-        st->last_new_leaves = nl;
-        st->last_u_old = (long long)(nseg - nnew);
-        st->last_u_new = (long long)nnew;
-        st->last_status = ok ? SLIM_OK : SLIM_ERR_CAPACITY;
-        st->n_touched.v = 0;
-        st->pairs.v = 0;
-        st->rejected.v = 0;
-        st->new_leaves.v = 0;
-        st->pair_cursor.v = 0;
-        st->frame_err.v = 0;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// 6. segment reduce and conjugate combine
-// ---------------------------------------------------------------------------
-
-struct Seg {
-    int4 d;        // first pair, pair count, record, meta
-    int slot;      // leaf slot (after creation for new leaves)
-    int leafnew;   // leaf is created by this frame
-    uint32_t pos;  // staging position of the leaf
+struct LeafShared {
+    uint32_t a_key[kLeafLdsPairs], b_key[kLeafLdsPairs];  // sorted / binned pairs
+    float a_val[kLeafLdsPairs], b_val[kLeafLdsPairs];
+    uint32_t hist[kLeafVoxels], bin0[kLeafVoxels], cur[kLeafVoxels];
+    uint32_t touch[kMaskWords], occ0[kMaskWords], wsum[4];
+    int pages[kLeafPages];
+    uint32_t chunk_end, uold, unew;
 };
-
-// Locates global segment s: its leaf is the last j with leaf_base[j].x <= s,
-// searched between the leaves of the two enclosing chunk marks.
-__device__ __forceinline__ Seg find_segment(const MapDev &md, const ApplyParams &ap, uint32_t s)
-{
-    const uint32_t c = s / kSegChunk;
-    uint32_t lo = md.chunk_leaf[c];
-    uint32_t hi = (c + 1) * kSegChunk < ap.nseg ? md.chunk_leaf[c + 1] + 1 : ap.nt;
-    // invariant: leaf_base[lo].x <= s < leaf_base[hi].x (hi = nt: past the end)
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (md.leaf_base[mid].x <= s) lo = mid;
-        else hi = mid;
-    }
-    const uint2 base = md.leaf_base[lo];
-    const int4 info = md.leaf_info[lo];
-    Seg g;
-    g.pos = (uint32_t)info.z;
-    g.d = md.seg_desc[info.x + (s - base.x)];
-    g.leafnew = info.y < 0;
-    g.slot = info.y >= 0 ? info.y : (int)(ap.lused0 + (unsigned long long)(-1 - info.y));
-    if (!((uint32_t)g.d.w & kSegExisted)) g.d.z = (int)(ap.vused0 + base.y + (uint32_t)g.d.z);
-    return g;
-}
-
-// Map bookkeeping of one applied segment: the first segment of a leaf creates
-// it (if new) and publishes its occupancy; a new voxel's record is indexed.
-__device__ __forceinline__ void segment_bookkeeping(const MapDev &md, const Seg &g)
-{
-    const uint32_t meta = (uint32_t)g.d.w;
-    if (meta & kSegFirst) {
-        if (g.leafnew) {
-            const unsigned long long key = md.skeys[g.pos];
-            map_insert(md, key, g.slot);
-            md.leaf_key[g.slot] = key;
-        }
-        for (int w = 0; w < kMaskWords; ++w)
-            md.leaf_occ[(size_t)g.slot * kMaskWords + w] = md.pos_occ[(size_t)g.pos * kMaskWords + w];
-    }
-    if (!(meta & kSegExisted)) md.leaf_index[(size_t)g.slot * kLeafVoxels + (meta & kSegOffMask)] = g.d.z;
-}
-
-// The first segment of each leaf clears the leaf's staging entry.
-__device__ __forceinline__ void clear_staging(const MapDev &md, const Seg &g)
-{
-    if ((uint32_t)g.d.w & kSegFirst) {
-        md.skeys[g.pos] = kEmptyKey;
-        md.pos_count[g.pos] = 0u;
-    }
-}
-
-// One lane per voxel segment; closed set with K <= KMAX classes kept in
-// registers (KMAX = 0: geometry only).  The record (D, W, counts) moves as
-// 16-byte vectors.
-template <int KMAX>
-__global__ __launch_bounds__(256) void k_segment_apply_lane(FrameParams fp, MapDev md)
-{
-    const ApplyParams ap = md.st->ap;
-    const int K = fp.K;
-    constexpr int KA = KMAX > 0 ? KMAX : 1;
-    constexpr int NV = (2 + KMAX + 3) / 4;  // float4 per record, at most
-    const int nv = md.rec_stride / 4;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t sgi = blockIdx.x * blockDim.x + threadIdx.x; sgi < ap.nseg; sgi += stride) {
-        const Seg g = find_segment(md, ap, sgi);
-        if (ap.ok) {
-            const int4 d = g.d;
-            const bool existed = ((uint32_t)d.w & kSegExisted) != 0;
-            float4 *R = (float4 *)(md.vox + (size_t)d.z * md.rec_stride);
-            float r[4 * NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const float4 x = (existed && v < nv) ? R[v] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                r[4 * v + 0] = x.x;
-                r[4 * v + 1] = x.y;
-                r[4 * v + 2] = x.z;
-                r[4 * v + 3] = x.w;
-            }
-            float acc[KA];
-#pragma unroll
-            for (int k = 0; k < KA; ++k) acc[k] = 0.0f;
-            float sum_t = 0.0f;
-            const uint32_t n = (uint32_t)d.y;
-            for (uint32_t c0 = 0; c0 < n; c0 += 8) {
-                uint32_t kk[8];
-                float tt[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    kk[q] = c0 + q < n ? md.srt_key[d.x + c0 + q] : 0u;
-                    tt[q] = c0 + q < n ? md.srt_tsdf[d.x + c0 + q] : 0.0f;
-                }
-                if (KMAX > 0 && fp.sem_kind == SLIM_IN_LABEL_I32) {
-                    int lab[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        lab[q] = c0 + q < n ? ((const int32_t *)fp.sem)[kk[q] & kPidMask] : -1;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q)
-#pragma unroll
-                        for (int k = 0; k < KA; ++k) acc[k] += (lab[q] == k) ? 1.0f : 0.0f;
-                }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    if (c0 + q >= n) break;
-                    sum_t += tt[q];
-                    if (KMAX > 0 && fp.sem_kind != SLIM_IN_LABEL_I32) {
-                        const float *row = (const float *)fp.sem + (size_t)(kk[q] & kPidMask) * K;
-                        float x[KA];
-#pragma unroll
-                        for (int k = 0; k < KA; ++k) x[k] = k < K ? row[k] : 0.0f;
-                        if (fp.sem_kind == SLIM_IN_LOGIT_F32) {
-                            // softmax of the logits, max-subtracted
-                            float mx = x[0];
-#pragma unroll
-                            for (int k = 1; k < KA; ++k)
-                                if (k < K) mx = fmaxf(mx, x[k]);
-                            float den = 0.0f;
-#pragma unroll
-                            for (int k = 0; k < KA; ++k) {
-                                x[k] = k < K ? expf(x[k] - mx) : 0.0f;
-                                den += x[k];
-                            }
-#pragma unroll
-                            for (int k = 0; k < KA; ++k) x[k] = x[k] / den;
-                        }
-#pragma unroll
-                        for (int k = 0; k < KA; ++k) acc[k] += x[k];
-                    }
-                }
-            }
-            // Eq. (1)-(2) with unit weights
-            const float nf = (float)n, W0 = r[1], W1 = W0 + nf;
-            r[0] = (W0 * r[0] + sum_t) / W1;
-            r[1] = W1;
-            // Eq. (6): concentrations grow by the (expected) class counts
-#pragma unroll
-            for (int k = 0; k < KA; ++k)
-                if (KMAX > 0 && k < K) r[2 + k] += acc[k];
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-                if (v < nv) R[v] = make_float4(r[4 * v + 0], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
-            segment_bookkeeping(md, g);
-        }
-        clear_staging(md, g);
-    }
-}
 
 __device__ __forceinline__ float load_emb(const FrameParams &fp, uint32_t pid, int comp)
 {
@@ -914,115 +524,447 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
-// One wave per voxel segment; lane l owns components l, l + 64, ... of the
-// open-set statistics (L <= 1024) or of the class counts (K <= 256).
-constexpr int kWaveComps = 16;
-
-__global__ __launch_bounds__(256) void k_segment_apply_wave(FrameParams fp, MapDev md)
+// One voxel, one lane: its n observations sit at keys[0..n) / vals[0..n) in
+// point order.  Closed set with K <= KMAX classes in registers (KMAX = 0:
+// geometry only); ROWS: probability or logit rows, else int32 labels.  The
+// record moves as 16-byte vectors.
+template <int KMAX, bool ROWS>
+__device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
+                                             const float *vals, uint32_t n, long long rec, bool existed)
 {
-    const ApplyParams ap = md.st->ap;
-    const int lane = lane_id();
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    const bool open = fp.L > 0;
-    const int C = open ? fp.L : fp.K;
-    for (uint32_t sgi = wave; sgi < ap.nseg; sgi += nwaves) {
-        const Seg g = find_segment(md, ap, sgi);
-        if (ap.ok) {
-            const int4 d = g.d;
-            const bool existed = ((uint32_t)d.w & kSegExisted) != 0;
-            float *R = md.vox + (size_t)d.z * md.rec_stride;
-            const uint32_t n = (uint32_t)d.y;
-            float s1[kWaveComps];
+    constexpr int KA = KMAX > 0 ? KMAX : 1;
+    constexpr int NV = (2 + KMAX + 3) / 4;
+    const int nv = md.rec_stride / 4, K = fp.K;
+    float acc[KA];
 #pragma unroll
-            for (int j = 0; j < kWaveComps; ++j) s1[j] = 0.0f;
-            float sum_t = 0.0f;
-            for (uint32_t c0 = 0; c0 < n; c0 += 64) {
-                const uint32_t my = c0 + lane < n ? md.srt_key[d.x + c0 + lane] : 0u;
-                const float myt = c0 + lane < n ? md.srt_tsdf[d.x + c0 + lane] : 0.0f;
-                const uint32_t cnt = min(64u, n - c0);
-                for (uint32_t q = 0; q < cnt; ++q) {
-                    const uint32_t pid = (uint32_t)__shfl((int)my, (int)q, 64) & kPidMask;
-                    sum_t += __shfl(myt, (int)q, 64);
-                    if (open) {
+    for (int k = 0; k < KA; ++k) acc[k] = 0.0f;
+    float sum_t = 0.0f;
+    for (uint32_t c0 = 0; c0 < n; c0 += 8) {
+        uint32_t kk[8];
 #pragma unroll
-                        for (int j = 0; j < kWaveComps; ++j) {
-                            const int comp = lane + 64 * j;
-                            if (comp < C) s1[j] += load_emb(fp, pid, comp);
-                        }
-                    } else if (fp.sem_kind == SLIM_IN_LABEL_I32) {
-                        const int lab = ((const int32_t *)fp.sem)[pid];
+        for (int q = 0; q < 8; ++q) kk[q] = c0 + q < n ? keys[c0 + q] : 0u;
+        if (KMAX > 0 && !ROWS) {
+            int lab[8];
 #pragma unroll
-                        for (int j = 0; j < kWaveComps; ++j) s1[j] += (lab == lane + 64 * j) ? 1.0f : 0.0f;
-                    } else if (fp.sem_kind == SLIM_IN_PROB_F32) {
+            for (int q = 0; q < 8; ++q) lab[q] = c0 + q < n ? ((const int32_t *)fp.sem)[kk[q] & kPidMask] : -1;
 #pragma unroll
-                        for (int j = 0; j < kWaveComps; ++j) {
-                            const int comp = lane + 64 * j;
-                            if (comp < C) s1[j] += ((const float *)fp.sem)[(size_t)pid * C + comp];
-                        }
-                    } else {
-                        // logits, K <= 64: softmax across the wave
-                        const float l = lane < C ? ((const float *)fp.sem)[(size_t)pid * C + lane] : -INFINITY;
-                        const float mx = wave_max(l);
-                        const float e = lane < C ? expf(l - mx) : 0.0f;
-                        s1[0] += e / wave_sum(e);
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int k = 0; k < KA; ++k) acc[k] += (lab[q] == k) ? 1.0f : 0.0f;
+        }
+        for (int q = 0; q < 8; ++q) {
+            if (c0 + q >= n) break;
+            sum_t += vals[c0 + q];
+            if (KMAX > 0 && ROWS) {
+                const float *row = (const float *)fp.sem + (size_t)(kk[q] & kPidMask) * K;
+                float x[KA];
+#pragma unroll
+                for (int k = 0; k < KA; ++k) x[k] = k < K ? row[k] : 0.0f;
+                if (fp.sem_kind == SLIM_IN_LOGIT_F32) {
+                    // softmax of the logits, max-subtracted
+                    float mx = x[0];
+#pragma unroll
+                    for (int k = 1; k < KA; ++k)
+                        if (k < K) mx = fmaxf(mx, x[k]);
+                    float den = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < KA; ++k) {
+                        x[k] = k < K ? expf(x[k] - mx) : 0.0f;
+                        den += x[k];
                     }
-                }
-            }
-            const float nf = (float)n;
-            const float W0 = existed ? R[1] : 0.0f, W1 = W0 + nf;
-            const float D0 = existed ? R[0] : 0.0f;
-            if (!open) {
 #pragma unroll
-                for (int j = 0; j < kWaveComps; ++j) {
-                    const int comp = lane + 64 * j;
-                    if (comp < C) R[2 + comp] = (existed ? R[2 + comp] : 0.0f) + s1[j];
+                    for (int k = 0; k < KA; ++k) x[k] = x[k] / den;
                 }
-            } else {
-                // second pass: squared deviations from the batch mean
-                float zbar[kWaveComps], s2[kWaveComps];
 #pragma unroll
-                for (int j = 0; j < kWaveComps; ++j) {
-                    zbar[j] = s1[j] / nf;
-                    s2[j] = 0.0f;
-                }
-                for (uint32_t c0 = 0; c0 < n; c0 += 64) {
-                    const uint32_t my = c0 + lane < n ? md.srt_key[d.x + c0 + lane] : 0u;
-                    const uint32_t cnt = min(64u, n - c0);
-                    for (uint32_t q = 0; q < cnt; ++q) {
-                        const uint32_t pid = (uint32_t)__shfl((int)my, (int)q, 64) & kPidMask;
-#pragma unroll
-                        for (int j = 0; j < kWaveComps; ++j) {
-                            const int comp = lane + 64 * j;
-                            if (comp < C) {
-                                const float dz = load_emb(fp, pid, comp) - zbar[j];
-                                s2[j] += dz * dz;
-                            }
-                        }
-                    }
-                }
-                // Eqs. (11)-(14) with lambda = W, nu = W / 2
-                const float cross = W0 * nf / W1;
-                float *M = R + 2, *B = R + 2 + fp.L;
-#pragma unroll
-                for (int j = 0; j < kWaveComps; ++j) {
-                    const int comp = lane + 64 * j;
-                    if (comp < C) {
-                        const float m0 = existed ? M[comp] : 0.0f, b0 = existed ? B[comp] : 0.0f;
-                        const float dm = zbar[j] - m0;
-                        B[comp] = b0 + 0.5f * s2[j] + cross * dm * dm * 0.5f;
-                        M[comp] = (W0 * m0 + nf * zbar[j]) / W1;
-                    }
-                }
-            }
-            if (lane == 0) {
-                // Eq. (1)-(2) with unit weights
-                R[0] = (W0 * D0 + sum_t) / W1;
-                R[1] = W1;
-                segment_bookkeeping(md, g);
+                for (int k = 0; k < KA; ++k) acc[k] += x[k];
             }
         }
-        if (lane == 0) clear_staging(md, g);
+    }
+    float4 *R = (float4 *)(md.vox + (size_t)rec * md.rec_stride);
+    float r[4 * NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const float4 x = (existed && v < nv) ? R[v] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        r[4 * v + 0] = x.x;
+        r[4 * v + 1] = x.y;
+        r[4 * v + 2] = x.z;
+        r[4 * v + 3] = x.w;
+    }
+    // Eq. (1)-(2) with unit weights
+    const float nf = (float)n, W0 = r[1], W1 = W0 + nf;
+    r[0] = (W0 * r[0] + sum_t) / W1;
+    r[1] = W1;
+    // Eq. (6): concentrations grow by the (expected) class counts
+#pragma unroll
+    for (int k = 0; k < KA; ++k)
+        if (KMAX > 0 && k < K) r[2 + k] += acc[k];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        if (v < nv) R[v] = make_float4(r[4 * v + 0], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
+}
+
+// One voxel, one wave: lane l owns components l, l + 64, ... of the open-set
+// statistics (L <= 1024) or of the class counts (K <= 1024).
+constexpr int kWaveComps = 16;
+
+__device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
+                                             const float *vals, uint32_t n, long long rec, bool existed)
+{
+    const int lane = lane_id();
+    const bool open = fp.L > 0;
+    const int C = open ? fp.L : fp.K;
+    float *R = md.vox + (size_t)rec * md.rec_stride;
+    float s1[kWaveComps];
+#pragma unroll
+    for (int j = 0; j < kWaveComps; ++j) s1[j] = 0.0f;
+    float sum_t = 0.0f;
+    for (uint32_t q = 0; q < n; ++q) {
+        const uint32_t pid = keys[q] & kPidMask;
+        sum_t += vals[q];
+        if (open) {
+#pragma unroll
+            for (int j = 0; j < kWaveComps; ++j) {
+                const int comp = lane + 64 * j;
+                if (comp < C) s1[j] += load_emb(fp, pid, comp);
+            }
+        } else if (fp.sem_kind == SLIM_IN_LABEL_I32) {
+            const int lab = ((const int32_t *)fp.sem)[pid];
+#pragma unroll
+            for (int j = 0; j < kWaveComps; ++j) s1[j] += (lab == lane + 64 * j) ? 1.0f : 0.0f;
+        } else if (fp.sem_kind == SLIM_IN_PROB_F32) {
+#pragma unroll
+            for (int j = 0; j < kWaveComps; ++j) {
+                const int comp = lane + 64 * j;
+                if (comp < C) s1[j] += ((const float *)fp.sem)[(size_t)pid * C + comp];
+            }
+        } else {
+            // logits, K <= 64: softmax across the wave
+            const float l = lane < C ? ((const float *)fp.sem)[(size_t)pid * C + lane] : -INFINITY;
+            const float mx = wave_max(l);
+            const float e = lane < C ? expf(l - mx) : 0.0f;
+            s1[0] += e / wave_sum(e);
+        }
+    }
+    const float nf = (float)n;
+    const float W0 = existed ? R[1] : 0.0f, W1 = W0 + nf;
+    const float D0 = existed ? R[0] : 0.0f;
+    if (!open) {
+#pragma unroll
+        for (int j = 0; j < kWaveComps; ++j) {
+            const int comp = lane + 64 * j;
+            if (comp < C) R[2 + comp] = (existed ? R[2 + comp] : 0.0f) + s1[j];
+        }
+    } else {
+        // second pass: squared deviations from the batch mean
+        float zbar[kWaveComps], s2[kWaveComps];
+#pragma unroll
+        for (int j = 0; j < kWaveComps; ++j) {
+            zbar[j] = s1[j] / nf;
+            s2[j] = 0.0f;
+        }
+        for (uint32_t q = 0; q < n; ++q) {
+            const uint32_t pid = keys[q] & kPidMask;
+#pragma unroll
+            for (int j = 0; j < kWaveComps; ++j) {
+                const int comp = lane + 64 * j;
+                if (comp < C) {
+                    const float dz = load_emb(fp, pid, comp) - zbar[j];
+                    s2[j] += dz * dz;
+                }
+            }
+        }
+        // Eqs. (11)-(14) with lambda = W, nu = W / 2
+        const float cross = W0 * nf / W1;
+        float *M = R + 2, *B = R + 2 + fp.L;
+#pragma unroll
+        for (int j = 0; j < kWaveComps; ++j) {
+            const int comp = lane + 64 * j;
+            if (comp < C) {
+                const float m0 = existed ? M[comp] : 0.0f, b0 = existed ? B[comp] : 0.0f;
+                const float dm = zbar[j] - m0;
+                B[comp] = b0 + 0.5f * s2[j] + cross * dm * dm * 0.5f;
+                M[comp] = (W0 * m0 + nf * zbar[j]) / W1;
+            }
+        }
+    }
+    if (lane == 0) {
+        // Eq. (1)-(2) with unit weights
+        R[0] = (W0 * D0 + sum_t) / W1;
+        R[1] = W1;
+    }
+}
+
+// Combines every touched voxel with offset in [o0, o1); the sorted pairs of
+// bin o sit at keys[bin0[o] - base] / vals[bin0[o] - base] (LDS or global).
+template <int KMAX, bool WAVE, bool ROWS>
+__device__ void combine_range(const FrameParams &fp, const MapDev &md, LeafShared &sh, const uint32_t *keys,
+                              const float *vals, uint32_t o0, uint32_t o1, uint32_t base)
+{
+    if (!WAVE) {
+        for (uint32_t o = o0 + threadIdx.x; o < o1; o += blockDim.x) {
+            const uint32_t n = sh.hist[o];
+            if (!n) continue;
+            const long long rec = (long long)sh.pages[o >> 6] * kPageVoxels + (o & (kPageVoxels - 1));
+            const bool existed = (sh.occ0[o >> 5] >> (o & 31)) & 1u;
+            combine_lane<KMAX, ROWS>(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base), n, rec,
+                                     existed);
+        }
+    } else {
+        const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        for (uint32_t o = o0 + wave; o < o1; o += nw) {
+            const uint32_t n = sh.hist[o];
+            if (!n) continue;
+            const long long rec = (long long)sh.pages[o >> 6] * kPageVoxels + (o & (kPageVoxels - 1));
+            const bool existed = (sh.occ0[o >> 5] >> (o & 31)) & 1u;
+            combine_wave(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base), n, rec, existed);
+        }
+    }
+}
+
+// Orders the pairs of bins [o0, o1) (binned in `bk`/`bv`, at bucket indices
+// starting at `lo`) by point index inside each bin: a pair's position is the
+// number of smaller keys in its bin.  Writes sh.a_*.
+template <class KP, class VP>
+__device__ __forceinline__ void rank_bins(LeafShared &sh, KP bk, VP bv, uint32_t lo, uint32_t hi)
+{
+    for (uint32_t t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+        const uint32_t k = bk[t - lo];
+        const uint32_t o = k >> kPidBits, blo = sh.bin0[o], bhi = blo + sh.hist[o];
+        uint32_t r = 0;
+#pragma unroll 8
+        for (uint32_t u = blo; u < bhi; ++u) r += bk[u - lo] < k;
+        sh.a_key[blo + r - lo] = k;
+        sh.a_val[blo + r - lo] = bv[t - lo];
+    }
+}
+
+template <int KMAX, bool WAVE, bool ROWS>
+__global__ __launch_bounds__(kLeafThreads) void k_leaf_fuse(FrameParams fp, MapDev md)
+{
+    __shared__ LeafShared sh;
+    const DevState *st = md.st;
+    const uint32_t nt = st->n_touched.v;
+    const unsigned long long lused = st->leaves_used;
+    const bool ok = st->frame_err.v == 0 && lused + st->new_leaves.v <= (unsigned long long)md.max_leaves &&
+                    st->pages_used + st->new_pages.v <= (unsigned long long)md.max_pages;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        sh.uold = 0;
+        sh.unew = 0;
+    }
+
+    for (uint32_t j = blockIdx.x; j < nt; j += gridDim.x) {
+        const uint32_t pos = md.touched[j];
+        const int4 plan = md.pos_plan[pos];
+        const uint32_t n = md.pos_count[pos];
+        const int slot = plan.x >= 0 ? plan.x : (int)(lused + (unsigned long long)plan.y);
+        for (int o = tid; o < kLeafVoxels; o += blockDim.x) sh.hist[o] = 0;
+        if (tid < kMaskWords) sh.occ0[tid] = plan.x >= 0 ? md.leaf_occ[(size_t)plan.x * kMaskWords + tid] : 0u;
+        if (tid < kLeafPages) sh.pages[tid] = ((const int *)md.pos_pages)[8 * (size_t)pos + tid];
+        __syncthreads();
+
+        const uint32_t *gk = md.srt_key + plan.z;
+        const float *gv = md.srt_tsdf + plan.z;
+        uint32_t *tk = md.tmp_key + plan.z;
+        float *tv = md.tmp_tsdf + plan.z;
+        const bool small = n <= (uint32_t)kLeafLdsPairs;
+
+        // histogram of voxel offsets; kLeafBatch loads in flight per thread, and
+        // a bucket that fits LDS stays in registers until its scatter
+        uint32_t rk[kLeafBatch];
+        float rv[kLeafBatch];
+        for (uint32_t t0 = 0; t0 < n; t0 += kLeafLdsPairs) {
+#pragma unroll
+            for (int u = 0; u < kLeafBatch; ++u) {
+                const uint32_t t = t0 + u * kLeafThreads + tid;
+                rk[u] = t < n ? gk[t] : 0u;
+                rv[u] = t < n ? gv[t] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < kLeafBatch; ++u)
+                if (t0 + u * kLeafThreads + tid < n) atomicAdd(&sh.hist[rk[u] >> kPidBits], 1u);
+        }
+        __syncthreads();
+        block_scan512(sh.hist, sh.bin0, sh.wsum);
+        for (int o = tid; o < kLeafVoxels; o += blockDim.x) sh.cur[o] = sh.bin0[o];
+        {
+            // touched offsets: wave w covers bins 64w + [0, 64) and 256 + 64w + [0, 64)
+            const int w = tid >> 6;
+            const unsigned long long b0 = __ballot(sh.hist[tid] != 0u);
+            const unsigned long long b1 = __ballot(sh.hist[tid + 256] != 0u);
+            if (lane_id() == 0) {
+                sh.touch[2 * w] = (uint32_t)b0;
+                sh.touch[2 * w + 1] = (uint32_t)(b0 >> 32);
+                sh.touch[8 + 2 * w] = (uint32_t)b1;
+                sh.touch[9 + 2 * w] = (uint32_t)(b1 >> 32);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t uo = 0, un = 0;
+            for (int w = 0; w < kMaskWords; ++w) {
+                uo += __popc(sh.touch[w] & sh.occ0[w]);
+                un += __popc(sh.touch[w] & ~sh.occ0[w]);
+            }
+            sh.uold += uo;
+            sh.unew += un;
+        }
+
+        // bin by offset (order inside a bin arbitrary): in LDS if the bucket fits,
+        // else in the scratch buffer
+        if (small) {
+#pragma unroll
+            for (int u = 0; u < kLeafBatch; ++u)
+                if ((uint32_t)(u * kLeafThreads + tid) < n) {
+                    const uint32_t p = atomicAdd(&sh.cur[rk[u] >> kPidBits], 1u);
+                    sh.b_key[p] = rk[u];
+                    sh.b_val[p] = rv[u];
+                }
+        } else {
+            for (uint32_t t0 = 0; t0 < n; t0 += kLeafLdsPairs) {
+#pragma unroll
+                for (int u = 0; u < kLeafBatch; ++u) {
+                    const uint32_t t = t0 + u * kLeafThreads + tid;
+                    rk[u] = t < n ? gk[t] : 0u;
+                    rv[u] = t < n ? gv[t] : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kLeafBatch; ++u)
+                    if (t0 + u * kLeafThreads + tid < n) {
+                        const uint32_t p = atomicAdd(&sh.cur[rk[u] >> kPidBits], 1u);
+                        tk[p] = rk[u];
+                        tv[p] = rv[u];
+                    }
+            }
+        }
+        __syncthreads();
+
+        // runs of whole bins that fit LDS: order each bin by point index, then
+        // combine its voxels (a small bucket is one run, already in LDS)
+        uint32_t o0 = 0;
+        while (o0 < (uint32_t)kLeafVoxels) {
+            uint32_t o1 = kLeafVoxels;
+            if (!small) {
+                if (tid == 0) {
+                    // bin ends are non-decreasing: first o1 > o0 whose end passes
+                    // bin0[o0] + capacity (at least o0 + 1)
+                    const uint32_t lim = sh.bin0[o0] + (uint32_t)kLeafLdsPairs;
+                    uint32_t lo = o0 + 1, hi = kLeafVoxels;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (sh.bin0[mid] + sh.hist[mid] <= lim) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    sh.chunk_end = lo;
+                }
+                __syncthreads();
+                o1 = sh.chunk_end;
+            }
+            const uint32_t lo = sh.bin0[o0], hi = (o1 < (uint32_t)kLeafVoxels) ? sh.bin0[o1] : n;
+            const bool fits = hi - lo <= (uint32_t)kLeafLdsPairs;
+            if (fits) {
+                if (!small) {
+                    for (uint32_t t = lo + tid; t < hi; t += blockDim.x) {
+                        sh.b_key[t - lo] = tk[t];
+                        sh.b_val[t - lo] = tv[t];
+                    }
+                    __syncthreads();
+                }
+                rank_bins(sh, sh.b_key, sh.b_val, lo, hi);
+            } else {
+                // one bin larger than LDS: order it in the bucket itself
+                uint32_t *bk = md.srt_key + plan.z;
+                float *bv = md.srt_tsdf + plan.z;
+                for (uint32_t t = lo + tid; t < hi; t += blockDim.x) {
+                    const uint32_t k = tk[t];
+                    uint32_t r = 0;
+                    for (uint32_t u = lo; u < hi; ++u) r += tk[u] < k;
+                    bk[lo + r] = k;
+                    bv[lo + r] = tv[t];
+                }
+            }
+            __syncthreads();
+            if (ok) {
+                // sorted pairs of bin o sit at keys[bin0[o] - base]
+                const uint32_t *ck = fits ? sh.a_key : md.srt_key + plan.z;
+                const float *cv = fits ? sh.a_val : md.srt_tsdf + plan.z;
+                combine_range<KMAX, WAVE, ROWS>(fp, md, sh, ck, cv, o0, o1, fits ? lo : 0u);
+            }
+            __syncthreads();
+            o0 = o1;
+        }
+
+        // leaf bookkeeping, then the staging entry is clean for the next frame
+        if (ok) {
+            if (tid == 0 && plan.x < 0) {
+                const unsigned long long key = md.skeys[pos];
+                map_insert(md, key, slot);
+                md.leaf_key[slot] = key;
+            }
+            if (tid < kLeafPages) md.leaf_page[(size_t)slot * kLeafPages + tid] = sh.pages[tid];
+            if (tid < kMaskWords) md.leaf_occ[(size_t)slot * kMaskWords + tid] = sh.occ0[tid] | sh.touch[tid];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            md.skeys[pos] = kEmptyKey;
+            md.pos_count[pos] = 0u;
+            md.pos_slab[pos] = 0u;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) md.blk_stats[blockIdx.x] = make_uint2(sh.uold, sh.unew);
+}
+
+// ---------------------------------------------------------------------------
+// 5. commit (one workgroup)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_frame_commit(FrameParams fp, MapDev md)
+{
+    __shared__ unsigned long long s_old[256], s_new[256];
+    DevState *st = md.st;
+    unsigned long long uo = 0, un = 0;
+    for (int b = threadIdx.x; b < md.leaf_blocks; b += blockDim.x) {
+        const uint2 v = md.blk_stats[b];
+        uo += v.x;
+        un += v.y;
+    }
+    s_old[threadIdx.x] = uo;
+    s_new[threadIdx.x] = un;
+    __syncthreads();
+    for (int d = 128; d > 0; d >>= 1) {
+        if (threadIdx.x < (unsigned)d) {
+            s_old[threadIdx.x] += s_old[threadIdx.x + d];
+            s_new[threadIdx.x] += s_new[threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const unsigned long long nl = st->new_leaves.v, np = st->new_pages.v;
+        const bool ok = st->frame_err.v == 0 && st->leaves_used + nl <= (unsigned long long)md.max_leaves &&
+                        st->pages_used + np <= (unsigned long long)md.max_pages;
+        if (ok) {
+            st->leaves_used += nl;
+            st->pages_used += np;
+            st->voxels_used += s_new[0];
+        } else if (st->status == SLIM_OK) {
+            st->status = SLIM_ERR_CAPACITY;
+        }
+        st->last_points = fp.n;
+        st->last_rejected = st->rejected.v;
+        st->last_pairs = st->pairs.v;
+        st->last_touched = st->n_touched.v;
+        st->last_new_leaves = nl;
+        st->last_u_old = (long long)s_old[0];
+        st->last_u_new = (long long)s_new[0];
+        st->last_status = ok ? SLIM_OK : SLIM_ERR_CAPACITY;
+        st->n_touched.v = 0;
+        st->pairs.v = 0;
+        st->rejected.v = 0;
+        st->new_leaves.v = 0;
+        st->new_pages.v = 0;
+        st->pair_cursor.v = 0;
+        st->frame_err.v = 0;
     }
 }
 
@@ -1047,21 +989,24 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md, int cus, hi
     hipLaunchKernelGGL(k_pair_bucket, dim3(bb > 0 ? bb : 1), dim3(256), 0, s, md);
     rec(5);
     rec(6);
-    hipLaunchKernelGGL(k_leaf_sort, dim3(cus * 8), dim3(kSortThreads), 0, s, md);
+    const dim3 gl(md.leaf_blocks), bl(kLeafThreads);
+    const bool rows = fp.sem_kind == SLIM_IN_PROB_F32 || fp.sem_kind == SLIM_IN_LOGIT_F32;
+    if (fp.L > 0 || fp.K > 32) hipLaunchKernelGGL((k_leaf_fuse<0, true, false>), gl, bl, 0, s, fp, md);
+    else if (fp.K == 0) hipLaunchKernelGGL((k_leaf_fuse<0, false, false>), gl, bl, 0, s, fp, md);
+    else if (rows) {
+        if (fp.K > 16) hipLaunchKernelGGL((k_leaf_fuse<32, false, true>), gl, bl, 0, s, fp, md);
+        else if (fp.K > 8) hipLaunchKernelGGL((k_leaf_fuse<16, false, true>), gl, bl, 0, s, fp, md);
+        else hipLaunchKernelGGL((k_leaf_fuse<8, false, true>), gl, bl, 0, s, fp, md);
+    } else {
+        if (fp.K > 24) hipLaunchKernelGGL((k_leaf_fuse<32, false, false>), gl, bl, 0, s, fp, md);
+        else if (fp.K > 16) hipLaunchKernelGGL((k_leaf_fuse<24, false, false>), gl, bl, 0, s, fp, md);
+        else if (fp.K > 8) hipLaunchKernelGGL((k_leaf_fuse<16, false, false>), gl, bl, 0, s, fp, md);
+        else hipLaunchKernelGGL((k_leaf_fuse<8, false, false>), gl, bl, 0, s, fp, md);
+    }
     rec(7);
     rec(8);
-    hipLaunchKernelGGL(k_frame_alloc, dim3(1), dim3(1024), 0, s, fp, md);
+    hipLaunchKernelGGL(k_frame_commit, dim3(1), dim3(256), 0, s, fp, md);
     rec(9);
-    rec(10);
-    const bool wave = fp.L > 0 || fp.K > 32;
-    const dim3 ga(cus * 8), blk(256);
-    if (wave) hipLaunchKernelGGL(k_segment_apply_wave, ga, blk, 0, s, fp, md);
-    else if (fp.K > 24) hipLaunchKernelGGL(k_segment_apply_lane<32>, ga, blk, 0, s, fp, md);
-    else if (fp.K > 16) hipLaunchKernelGGL(k_segment_apply_lane<24>, ga, blk, 0, s, fp, md);
-    else if (fp.K > 8) hipLaunchKernelGGL(k_segment_apply_lane<16>, ga, blk, 0, s, fp, md);
-    else if (fp.K > 0) hipLaunchKernelGGL(k_segment_apply_lane<8>, ga, blk, 0, s, fp, md);
-    else hipLaunchKernelGGL(k_segment_apply_lane<0>, ga, blk, 0, s, fp, md);
-    rec(11);
     return hipGetLastError();
 }
 
@@ -1093,8 +1038,16 @@ hipError_t launch_reset(const MapDev &md, hipStream_t s)
     hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, s, md.hkeys, cap, kEmptyKey);
     hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, s, md.skeys, cap, kEmptyKey);
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, md.pos_count, cap, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, md.pos_slab, cap, 0u);
     hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, md.st);
     return hipGetLastError();
+}
+
+__device__ __forceinline__ uint32_t bits_below(const uint32_t *mask, uint32_t o)
+{
+    uint32_t r = 0;
+    for (uint32_t w = 0; w < (o >> 5); ++w) r += __popc(mask[w]);
+    return r + __popc(mask[o >> 5] & ((1u << (o & 31)) - 1u));
 }
 
 __global__ void k_collect_leaves(const MapDev md, long long nleaves, unsigned long long *keys, int32_t *slots)
@@ -1177,7 +1130,8 @@ __global__ __launch_bounds__(256) void k_extract(const MapDev md, long long nlea
         for (int t = threadIdx.x; t < kLeafVoxels; t += blockDim.x) {
             if (!((occ[t >> 5] >> (t & 31)) & 1u)) continue;
             const size_t o = (size_t)offsets[j] + bits_below(occ, (uint32_t)t);
-            const long long rec = md.leaf_index[(size_t)slot * kLeafVoxels + t];
+            const long long rec =
+                (long long)md.leaf_page[(size_t)slot * kLeafPages + (t >> 6)] * kPageVoxels + (t & (kPageVoxels - 1));
             const float *R = md.vox + (size_t)rec * md.rec_stride;
             keys[3 * o + 0] = lx * 8 + (t >> 6);
             keys[3 * o + 1] = ly * 8 + ((t >> 3) & 7);
@@ -1229,7 +1183,8 @@ __global__ __launch_bounds__(256) void k_query(const MapDev md, int nsem, float 
                 if (slot >= 0) {
                     const int off = ((kx & 7) << 6) | ((ky & 7) << 3) | (kz & 7);
                     if ((md.leaf_occ[(size_t)slot * kMaskWords + (off >> 5)] >> (off & 31)) & 1u)
-                        rec = md.leaf_index[(size_t)slot * kLeafVoxels + off];
+                        rec = (long long)md.leaf_page[(size_t)slot * kLeafPages + (off >> 6)] * kPageVoxels +
+                              (off & (kPageVoxels - 1));
                 }
             }
         }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libslimvdb.so")
 OK, ERR_INVALID, ERR_CAPACITY, ERR_DEVICE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 SEM_NONE, SEM_CLOSED, SEM_OPEN = 0, 1, 2
 IN_NONE, IN_LABEL_I32, IN_PROB_F32, IN_LOGIT_F32, IN_EMB_BF16, IN_EMB_F32 = range(6)
-KERNELS = ("ray_walk_emit", "leaf_plan", "pair_bucket", "leaf_sort", "frame_alloc", "segment_apply")
+KERNELS = ("ray_walk_emit", "leaf_plan", "pair_bucket", "leaf_fuse", "frame_commit")
 
 EXPORTS = ("slim_map_create", "slim_map_destroy", "slim_map_reset", "slim_integrate", "slim_map_stats",
            "slim_extract", "slim_query", "slim_profile_enable", "slim_profile_read", "slim_last_error")

@@ -288,6 +288,96 @@ class StreetScene:
         return dict(points=pts, pose=pose, label=lab, true_class=cls.astype(np.int32), range=r, dirs=dirs)
 
 
+    # --- differentiation workload: rays, logits, ground truth, surface samples ---
+
+    def ray_sweep(self, t, true_logit=3.0):
+        """Sweep t as (range, unit sensor-frame direction) pairs with 20-class logits:
+        the observed (possibly flickered) class gets `true_logit`, the others N(0, 1).
+        Misses and returns beyond max_range have range NaN."""
+        sw = self.sweep(t)
+        r = sw["range"].astype(np.float64)
+        r = np.where(r <= self.max_range, r, np.nan).astype(np.float32)
+        rng = _rng(self.seed, 5, t)
+        logits = rng.normal(0.0, 1.0, size=(len(r), STREET_CLASSES))
+        logits[np.arange(len(r)), sw["label"]] = true_logit
+        return dict(ranges=r, dirs=sw["dirs"].astype(np.float32), pose=sw["pose"],
+                    logits=logits.astype(np.float32), label=sw["label"], true_class=sw["true_class"])
+
+    def nearest_class(self, xyz, margin=2.0):
+        """Class of the primitive (ground, box or cylinder) nearest to each point.
+
+        Primitives are tested only against points within `margin` of their
+        bounding box; points left farther than `margin` from everything tested
+        get a full test."""
+        p_all = np.asarray(xyz, np.float64)
+        order = np.argsort(p_all[:, 0], kind="stable")
+        p = p_all[order]
+        xs = p[:, 0]
+        best = np.abs(p[:, 2])  # ground plane z = 0
+        cls = np.zeros(len(p), np.int64)
+
+        def box_dist(q, lo, hi):
+            out = np.linalg.norm(np.maximum(lo - q, 0.0) + np.maximum(q - hi, 0.0), axis=1)
+            inside = np.minimum(np.min(q - lo, axis=1), np.min(hi - q, axis=1))
+            return np.where(out > 0, out, inside)
+
+        def cyl_dist(q, j):
+            dx = np.hypot(q[:, 0] - self.cyl_xy[j, 0], q[:, 1] - self.cyl_xy[j, 1]) - self.cyl_r[j]
+            dz = np.maximum(q[:, 2] - self.cyl_h[j], 0.0) + np.maximum(-q[:, 2], 0.0)
+            return np.where((dx > 0) | (dz > 0), np.hypot(np.maximum(dx, 0.0), dz),
+                            np.minimum(-dx, np.minimum(q[:, 2], self.cyl_h[j] - q[:, 2])))
+
+        def visit(lo, hi, dist, label, full):
+            if full:
+                sel = np.arange(len(p))
+            else:
+                a, b = np.searchsorted(xs, [lo[0] - margin, hi[0] + margin])
+                sel = np.arange(a, b)
+                q = p[sel]
+                keep = np.all((q[:, 1:] >= lo[1:] - margin) & (q[:, 1:] <= hi[1:] + margin), axis=1)
+                sel = sel[keep]
+            if len(sel) == 0:
+                return
+            d = dist(p[sel])
+            closer = d < best[sel]
+            best[sel[closer]] = d[closer]
+            cls[sel[closer]] = label
+
+        def sweep(full):
+            for j in range(len(self.box_lo)):
+                lo, hi = self.box_lo[j], self.box_hi[j]
+                visit(lo, hi, lambda q: box_dist(q, lo, hi), self.box_class[j], full)
+            for j in range(len(self.cyl_r)):
+                lo = np.array([self.cyl_xy[j, 0] - self.cyl_r[j], self.cyl_xy[j, 1] - self.cyl_r[j], 0.0])
+                hi = np.array([self.cyl_xy[j, 0] + self.cyl_r[j], self.cyl_xy[j, 1] + self.cyl_r[j], self.cyl_h[j]])
+                visit(lo, hi, lambda q, j=j: cyl_dist(q, j), self.cyl_class[j], full)
+
+        sweep(False)
+        far = best > margin
+        if far.any():
+            keep_p, keep_xs, keep_best, keep_cls = p, xs, best, cls
+            p, xs = keep_p[far], keep_xs[far]
+            best, cls = keep_best[far].copy(), keep_cls[far].copy()
+            sweep(True)
+            keep_best[far], keep_cls[far] = best, cls
+            p, xs, best, cls = keep_p, keep_xs, keep_best, keep_cls
+        out = np.empty(len(p_all), np.int32)
+        out[order] = cls
+        return out
+
+    def surface_samples(self, frames, count=10000, seed=5):
+        """`count` noiseless hit points (world frame, float32) drawn from the valid
+        returns of the given ray sweeps."""
+        pts = []
+        for fr in frames:
+            ok = np.isfinite(fr["ranges"])
+            p = fr["dirs"][ok].astype(np.float64) * fr["ranges"][ok, None].astype(np.float64)
+            pts.append(p @ fr["pose"][:3, :3].T + fr["pose"][:3, 3])
+        pts = np.concatenate(pts)
+        idx = _rng(seed, 6).choice(len(pts), size=min(count, len(pts)), replace=False)
+        return pts[np.sort(idx)].astype(np.float32)
+
+
 # ----------------------------------------------------------------------------
 # RGB-D room, open set with bf16 embeddings
 # ----------------------------------------------------------------------------
