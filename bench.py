@@ -36,11 +36,65 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--no-diff", action="store_true", help="skip the forward+backward measurement")
+    ap.add_argument("--diff-reps", type=int, default=5)
     return ap.parse_args()
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def diff_bench(sv, synth, torch, scene, frames=16, reps=5, vs=0.1, tau=0.3, ncls=20):
+    """Differentiation workload: 16 ray sweeps (ranges, directions, 20-class
+    logits) integrated into a fresh map, the map loss, and its backward w.r.t.
+    logits and ranges; times the plain forward and forward + backward."""
+    t0 = time.time()
+    sw = [scene.ray_sweep(t) for t in range(frames)]
+    dev = torch.device("cuda", 0)
+    ranges = torch.from_numpy(np.stack([s["ranges"] for s in sw])).to(dev)
+    dirs = torch.from_numpy(np.stack([s["dirs"] for s in sw])).to(dev)
+    logits = torch.from_numpy(np.stack([s["logits"] for s in sw])).to(dev)
+    poses = [s["pose"] for s in sw]
+    gmap = sv.Map(vs, tau, 0.0, 50.0, sv.SEM_CLOSED, ncls, 0, 0, max_leaves=1 << 18, max_voxels=1 << 24)
+
+    def forward():
+        gmap.reset()
+        for f in range(frames):
+            gmap.integrate_rays(ranges[f], dirs[f], poses[f], logits[f], sv.IN_LOGIT_F32)
+
+    forward()
+    ex = gmap.extract()
+    keys = ex["keys"]
+    labels = torch.from_numpy(scene.nearest_class((keys.cpu().numpy() + 0.5) * np.float64(np.float32(vs)))).to(dev)
+    samples = torch.from_numpy(scene.surface_samples(sw, count=10000)).to(dev)
+    gl = torch.empty_like(logits)
+    gr = torch.empty_like(ranges)
+    log(f"differentiation inputs ready in {time.time() - t0:.1f}s: {keys.shape[0]} voxels")
+
+    def fwd_bwd():
+        forward()
+        gmap.loss(keys, labels, samples, 1.0)
+        for f in range(frames):
+            gmap.backward_rays(ranges[f], dirs[f], poses[f], logits[f], gl[f], gr[f])
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            s = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - s)
+        return float(np.median(ts)) * 1e3
+
+    t_fwd = timed(forward)
+    t_fb = timed(fwd_bwd)
+    return {"workload": f"{frames} LiDAR ray sweeps x {ranges.shape[1]} rays, 20-class logits, map loss = "
+                        "Dirichlet-predictive cross-entropy over all voxels + mean |D| at 10k surface samples",
+            "fwd_ms": t_fwd, "fwd_bwd_ms": t_fb, "ratio": t_fb / t_fwd, "voxels": int(keys.shape[0]),
+            "points_per_s_fwd_bwd": frames * ranges.shape[1] / (t_fb / 1e3)}
 
 
 def main():
@@ -154,6 +208,10 @@ def main():
                      "frac": dom_gbs / HBM_PEAK_GBS, "traffic": None,
                      "alg_bytes_per_launch": kalg[dom] / K},
     }
+
+    if not args.no_diff:
+        result["fwd_bwd"] = diff_bench(sv, synth, torch, scene, reps=args.diff_reps)
+        log(f"fwd+bwd {result['fwd_bwd']}")
 
     if not args.no_cpu:
         import oracle  # test infrastructure: the CPU baseline leg only

@@ -145,6 +145,77 @@ slim_status slim_extract(slim_map *map, int64_t capacity, int32_t *keys_dev, flo
 slim_status slim_query(slim_map *map, const float *xyz_dev, int64_t m, float *d_dev, float *w_dev, float *sem_dev,
                        void *stream);
 
+/* As slim_integrate, with each point given as a range along a direction:
+ * point i is ranges_dev[i] * dirs_dev[3 i .. 3 i + 2] (one binary32 product per
+ * component; dirs are unit vectors in the sensor frame).  A non-finite range
+ * rejects the point. */
+slim_status slim_integrate_rays(slim_map *map, const float *ranges_dev, const float *dirs_dev, int64_t n,
+                                const double *pose_host, const void *sem_dev, int32_t sem_kind, void *stream);
+
+/* Map loss of a closed-set map (differentiation workload):
+ *   L = (1/m) sum_v -log p_v(labels_v)  +  (1/M') sum_s |D(v_s)|
+ * where p_v(i) = (alpha0 + c_vi) / (K alpha0 + sum_i c_vi) is the Dirichlet
+ * posterior predictive (Eq. (7)), the first sum runs over the m voxels listed in
+ * keys_dev (int32 [m x 3]; they must be all voxels of the map, e.g. from
+ * slim_extract) with ground-truth classes labels_dev (int32 [m]), and the second
+ * over the M' of the s world points samples_dev (float [s x 3]) whose voxel
+ * (floor(x / voxel_size), binary32 division) is in the map.  Writes
+ * loss_dev[0..2] = (L, first term, second term) on the device and keeps the
+ * per-voxel adjoints dL/dc and dL/dD for slim_backward_rays.  Sums are formed in
+ * a fixed order (bitwise repeatable).  Queued on `stream`; the first call on a
+ * map allocates the adjoint buffers (synchronising).  SLIM_ERR_UNSUPPORTED for
+ * open-set or geometry-only maps. */
+slim_status slim_map_loss(slim_map *map, const int32_t *keys_dev, const int32_t *labels_dev, int64_t m,
+                          const float *samples_dev, int64_t s, float alpha0, float *loss_dev, void *stream);
+
+/* Gradient of the last slim_map_loss with respect to the logits and ranges of
+ * one frame that was integrated with slim_integrate_rays(SLIM_IN_LOGIT_F32) into
+ * the map (same arguments; the map must not have changed since the loss).  For
+ * each point, the band walk is recomputed and
+ *   dL/dlogit_k = p_k (G_k - sum_i p_i G_i),  G = sum over its voxels of dL/dc_v,
+ *   dL/drange   = sum over its voxels with sdf < tau of dL/dD_v / W_v
+ * (p the softmax of the point's logits; d sdf / d range = 1 along the ray).
+ * Writes grad_logits_dev (float [n x K]) and grad_ranges_dev (float [n]);
+ * rejected points get zeros.  grad_scale_dev (float [1], may be NULL = 1)
+ * multiplies both.  K <= 32.  Queued on `stream`. */
+slim_status slim_backward_rays(slim_map *map, const float *ranges_dev, const float *dirs_dev, int64_t n,
+                               const double *pose_host, const float *logits_dev, const float *grad_scale_dev,
+                               float *grad_logits_dev, float *grad_ranges_dev, void *stream);
+
+/* One frame of a batched integration: either points (points != NULL) or
+ * ranges and directions, as for slim_integrate / slim_integrate_rays. */
+typedef struct slim_frame {
+    const float *points; /* dev, n x 3 sensor frame, or NULL */
+    const float *ranges; /* dev, n, with dirs */
+    const float *dirs;   /* dev, n x 3 unit sensor-frame directions */
+    int64_t n;
+    double pose[16];     /* map_T_sensor, row-major */
+    const void *sem;     /* dev, layout per sem_kind */
+    int32_t sem_kind;    /* SLIM_IN_* */
+    int32_t reserved;
+} slim_frame;
+
+/* Integrates frames[i] into maps[i] for i < nmaps, for maps of any mix of
+ * modes, classes and embedding sizes on one device, as one launch per kernel
+ * stage for all maps (six launches in all) instead of five per map.  Results
+ * are identical to nmaps calls of slim_integrate.  With use_graph != 0 the
+ * launches are captured once into a HIP graph, which later calls with the same
+ * maps, the same per-map walk grid (ceil(n_i / 256) blocks) and the same launch
+ * shape replay; point counts, poses and buffers may change between replays.
+ * Maps must be distinct.  The launch resources belong to maps[0] (the first
+ * call allocates them, synchronising).  Queued on `stream`. */
+slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const slim_frame *frames, int32_t use_graph,
+                                   void *stream);
+
+/* Grid sizes of the grid-stride kernels of integration: leaf planning and pair
+ * bucketing blocks, and leaf-kernel blocks per compute unit (1 .. 32).  Results
+ * do not depend on them (each voxel is reduced in point order); they only move
+ * time.  NULL restores the defaults.  Batched calls use the shape of maps[0]. */
+typedef struct slim_launch_shape {
+    int32_t plan_blocks, bucket_blocks, leaf_blocks_per_cu, reserved;
+} slim_launch_shape;
+slim_status slim_set_launch_shape(slim_map *map, const slim_launch_shape *shape);
+
 /* Kernel timing.  While enabled, slim_integrate brackets each of its kernels
  * with HIP events on the stream it launches on; slim_profile_read returns the
  * accumulated per-kernel time in milliseconds and launch counts (index 0 ray

@@ -23,6 +23,7 @@ constexpr int kLeafThreads = 256;
 constexpr int kLeafBatch = 8;                // loads in flight per thread in the leaf kernel
 constexpr int kLeafLdsPairs = kLeafBatch * kLeafThreads;  // pairs a leaf holds in LDS at once
 constexpr int kNumProfiled = 5;
+constexpr int kMaxLeafBlocksPerCu = 32;
 
 // floats of one voxel record: D, W, then the semantic state, padded to 16 bytes
 __host__ __device__ inline int record_stride(int nsem) { return (2 + nsem + 3) & ~3; }
@@ -67,8 +68,25 @@ struct FrameParams {
     int n;             // points
     int sem_kind;      // SLIM_IN_*
     int K, L, nsem;    // classes, embedding dim, floats of semantic state per voxel
-    const float *pts;  // n x 3
+    const float *pts;  // n x 3, or NULL when the points come as ranges and directions
+    const float *ranges, *dirs;  // n and n x 3: point = range * direction
     const void *sem;   // per-point semantics
+};
+
+// Inputs and outputs of the map loss and its backward.
+struct LossParams {
+    const int32_t *keys;     // m x 3 voxel keys (all voxels of the map)
+    const int32_t *labels;   // m ground-truth classes
+    long long m;
+    const float *samples;    // s x 3 world points
+    long long s;
+    float alpha0;
+    float *loss;             // 3 floats: total, cross-entropy term, L1 term
+    float *adj;              // per record: K adjoints dL/dc, then dL/dD (stride adj_stride)
+    int32_t *adj_cnt;        // per record: surface samples in the voxel
+    int adj_stride;
+    float *part;             // block partial sums
+    int32_t *part_cnt;       // block partial sample counts
 };
 
 // Device pointers of one map.
@@ -104,10 +122,40 @@ struct MapDev {
     float *tmp_tsdf;
     uint32_t pair_cap;
     uint2 *blk_stats;     // per leaf-kernel block: (voxels updated that existed, voxels created)
-    int leaf_blocks;      // grid of the leaf kernel
+    int leaf_blocks;      // grid of the leaf kernel of the current frame (<= kMaxLeafBlocksPerCu * CUs)
     DevState *st;
     long long max_leaves, max_pages;
 };
+
+// Device descriptor of a batched launch over several maps (one frame each).
+struct MapBatch {
+    const MapDev *mds;       // nmaps
+    const FrameParams *fps;  // nmaps
+    const int *walk_start;   // nmaps + 1: first walk block of each map
+    const int *subset;       // the maps one leaf-kernel launch handles
+    int nmaps, nsubset;
+};
+
+// Grid sizes of the grid-stride kernels (results do not depend on them).
+struct LaunchShape {
+    int plan_blocks;    // leaf planning
+    int bucket_blocks;  // pair bucketing
+    int leaf_blocks;    // per-leaf sort and combine (also the size of blk_stats in use)
+};
+
+// Host view of a batched launch: the leaf kernel is launched once per group of
+// maps that share its template (classes in registers, wave per voxel, rows).
+struct BatchPlan {
+    int nmaps;
+    int walk_blocks;                 // total blocks of the walk kernel
+    int ngroups;
+    int group_kind[8];               // leaf-kernel variant of each group
+    int group_begin[8], group_size[8];  // slice of the device subset array
+};
+
+int leaf_kernel_kind(const FrameParams &fp);
+hipError_t launch_integrate_batched(const MapBatch &mb, const BatchPlan &plan, const LaunchShape &shape,
+                                    hipStream_t s);
 
 __host__ __device__ inline unsigned long long pack_leaf(int lx, int ly, int lz)
 {
@@ -117,9 +165,13 @@ __host__ __device__ inline unsigned long long pack_leaf(int lx, int ly, int lz)
 }
 
 // kernel launchers (slimvdb_kernels.hip)
-hipError_t launch_integrate(const FrameParams &fp, const MapDev &md, int cus, hipStream_t s,
+hipError_t launch_integrate(const FrameParams &fp, const MapDev &md, const LaunchShape &shape, hipStream_t s,
                             hipEvent_t *ev /* 2 * kNumProfiled events or nullptr */);
 hipError_t launch_reset(const MapDev &md, hipStream_t s);
+hipError_t launch_loss(const FrameParams &fp, const MapDev &md, const LossParams &lp, hipStream_t s);
+hipError_t launch_backward(const FrameParams &fp, const MapDev &md, const LossParams &lp, const float *grad_scale,
+                           float *grad_logits, float *grad_ranges, hipStream_t s);
+constexpr int kLossThreads = 256;
 hipError_t launch_extract(const MapDev &md, int nsem, long long nleaves, unsigned long long *tmp_keys,
                           int32_t *tmp_slots, uint32_t *tmp_offsets, int32_t *keys, float *d, float *w, float *sem,
                           hipStream_t s);

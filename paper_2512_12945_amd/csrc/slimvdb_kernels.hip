@@ -156,6 +156,22 @@ __device__ __forceinline__ bool make_ray(const FrameParams &fp, float x, float y
     return true;
 }
 
+// Sensor-frame point i: given directly, or as range * unit direction (one
+// binary32 product per component).
+__device__ __forceinline__ void load_point(const FrameParams &fp, int i, float &x, float &y, float &z)
+{
+    if (fp.pts) {
+        x = fp.pts[3 * i + 0];
+        y = fp.pts[3 * i + 1];
+        z = fp.pts[3 * i + 2];
+    } else {
+        const float r = fp.ranges[i];
+        x = r * fp.dirs[3 * i + 0];
+        y = r * fp.dirs[3 * i + 1];
+        z = r * fp.dirs[3 * i + 2];
+    }
+}
+
 // Amanatides-Woo walk over the band of the ray from the sensor origin
 // (fp.t).  Calls visit(cx, cy, cz) per cell (anchor-relative).  Ties between
 // axes step the lowest axis first, one axis per step; the walk stops when the
@@ -255,7 +271,8 @@ __device__ __forceinline__ uint32_t lds_hash(unsigned long long k)
     return (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 40) & (kWalkTable - 1);
 }
 
-__global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, MapDev md)
+// One block of the walk: rays blk * blockDim.x + [0, blockDim.x) of a frame.
+__device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const MapDev &md, int blk)
 {
     // block-local table of the leaves this block's rays touch
     __shared__ unsigned long long t_key[kWalkTable];
@@ -278,11 +295,12 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, 
     }
     __syncthreads();
 
-    const int i = blockIdx.x * blockDim.x + tid;
+    const int i = blk * blockDim.x + tid;
     Ray ry;
     bool valid = false;
     if (i < fp.n) {
-        const float x = fp.pts[3 * i + 0], y = fp.pts[3 * i + 1], z = fp.pts[3 * i + 2];
+        float x, y, z;
+        load_point(fp, i, x, y, z);
         valid = make_ray(fp, x, y, z, ry);
         if (valid && fp.sem_kind == SLIM_IN_LABEL_I32) {
             const int lab = ((const int32_t *)fp.sem)[i];
@@ -429,16 +447,39 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, 
     });
 }
 
+__global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, MapDev md)
+{
+    walk_emit_block(fp, md, blockIdx.x);
+}
+
+// Map of a block of a batched launch: the last i with start[i] <= blk.
+__device__ __forceinline__ int batch_map(const int *start, int nmaps, int blk)
+{
+    int lo = 0, hi = nmaps;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= blk) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit_batch(MapBatch mb)
+{
+    const int i = batch_map(mb.walk_start, mb.nmaps, blockIdx.x);
+    walk_emit_block(mb.fps[i], mb.mds[i], blockIdx.x - mb.walk_start[i]);
+}
+
 // ---------------------------------------------------------------------------
 // 2. leaf planning
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_leaf_plan(MapDev md)
+__device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, uint32_t nblk)
 {
     const uint32_t nt = md.st->n_touched.v;
     const unsigned long long pused = md.st->pages_used;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t jb = blockIdx.x * blockDim.x; jb < nt; jb += stride) {
+    const uint32_t stride = nblk * blockDim.x;
+    for (uint32_t jb = blk * blockDim.x; jb < nt; jb += stride) {
         const uint32_t j = jb + threadIdx.x;
         const bool act = j < nt;
         int32_t slot = -1;
@@ -475,21 +516,41 @@ __global__ __launch_bounds__(256) void k_leaf_plan(MapDev md)
     }
 }
 
+__global__ __launch_bounds__(256) void k_leaf_plan(MapDev md)
+{
+    leaf_plan_range(md, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_leaf_plan_batch(MapBatch mb)
+{
+    for (int i = 0; i < mb.nmaps; ++i) leaf_plan_range(mb.mds[i], blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // 3. pair bucketing
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_pair_bucket(MapDev md)
+__device__ __forceinline__ void pair_bucket_range(const MapDev &md, uint32_t blk, uint32_t nblk)
 {
     const uint32_t P = min(md.st->pairs.v, md.pair_cap);
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < P; i += stride) {
+    const uint32_t stride = nblk * blockDim.x;
+    for (uint32_t i = blk * blockDim.x + threadIdx.x; i < P; i += stride) {
         const uint32_t pos = md.pair_pos[i];
         if (pos == kNoPos) continue;
         const uint32_t dst = (uint32_t)md.pos_plan[pos].z + md.pair_rank[i];
         md.srt_key[dst] = md.pair_key[i];
         md.srt_tsdf[dst] = md.pair_tsdf[i];
     }
+}
+
+__global__ __launch_bounds__(256) void k_pair_bucket(MapDev md)
+{
+    pair_bucket_range(md, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_pair_bucket_batch(MapBatch mb)
+{
+    for (int i = 0; i < mb.nmaps; ++i) pair_bucket_range(mb.mds[i], blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -738,10 +799,12 @@ __device__ __forceinline__ void rank_bins(LeafShared &sh, KP bk, VP bv, uint32_t
     }
 }
 
+// Leaves blk, blk + nblk, ... of one map's frame; block statistics go to
+// md.blk_stats[blk].
 template <int KMAX, bool WAVE, bool ROWS>
-__global__ __launch_bounds__(kLeafThreads) void k_leaf_fuse(FrameParams fp, MapDev md)
+__device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const MapDev &md, LeafShared &sh,
+                                                uint32_t blk, uint32_t nblk)
 {
-    __shared__ LeafShared sh;
     const DevState *st = md.st;
     const uint32_t nt = st->n_touched.v;
     const unsigned long long lused = st->leaves_used;
@@ -753,7 +816,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_fuse(FrameParams fp, MapD
         sh.unew = 0;
     }
 
-    for (uint32_t j = blockIdx.x; j < nt; j += gridDim.x) {
+    for (uint32_t j = blk; j < nt; j += nblk) {
         const uint32_t pos = md.touched[j];
         const int4 plan = md.pos_plan[pos];
         const uint32_t n = md.pos_count[pos];
@@ -912,14 +975,34 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_fuse(FrameParams fp, MapD
         }
     }
     __syncthreads();
-    if (tid == 0) md.blk_stats[blockIdx.x] = make_uint2(sh.uold, sh.unew);
+    if (tid == 0) md.blk_stats[blk] = make_uint2(sh.uold, sh.unew);
+    __syncthreads();
 }
+
+template <int KMAX, bool WAVE, bool ROWS>
+__global__ __launch_bounds__(kLeafThreads) void k_leaf_fuse(FrameParams fp, MapDev md)
+{
+    __shared__ LeafShared sh;
+    leaf_fuse_range<KMAX, WAVE, ROWS>(fp, md, sh, blockIdx.x, gridDim.x);
+}
+
+// The maps mb.subset[0 .. nsubset) of a batch, all of this kernel's kind.
+template <int KMAX, bool WAVE, bool ROWS>
+__global__ __launch_bounds__(kLeafThreads) void k_leaf_fuse_batch(MapBatch mb)
+{
+    __shared__ LeafShared sh;
+    for (int q = 0; q < mb.nsubset; ++q) {
+        const int i = mb.subset[q];
+        leaf_fuse_range<KMAX, WAVE, ROWS>(mb.fps[i], mb.mds[i], sh, blockIdx.x, gridDim.x);
+    }
+}
+
 
 // ---------------------------------------------------------------------------
 // 5. commit (one workgroup)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_frame_commit(FrameParams fp, MapDev md)
+__device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const MapDev &md)
 {
     __shared__ unsigned long long s_old[256], s_new[256];
     DevState *st = md.st;
@@ -968,12 +1051,69 @@ __global__ __launch_bounds__(256) void k_frame_commit(FrameParams fp, MapDev md)
     }
 }
 
+__global__ __launch_bounds__(256) void k_frame_commit(FrameParams fp, MapDev md)
+{
+    frame_commit_block(fp, md);
+}
+
+__global__ __launch_bounds__(256) void k_frame_commit_batch(MapBatch mb)
+{
+    frame_commit_block(mb.fps[blockIdx.x], mb.mds[blockIdx.x]);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_integrate(const FrameParams &fp, const MapDev &md, int cus, hipStream_t s, hipEvent_t *ev)
+// Variant of the leaf kernel a frame needs: 0 geometry; 1..4 labels with
+// 8/16/24/32 classes in registers; 5..7 probability or logit rows with 8/16/32;
+// 8 one wave per voxel (open set, or more than 32 classes).
+int leaf_kernel_kind(const FrameParams &fp)
 {
+    if (fp.L > 0 || fp.K > 32) return 8;
+    if (fp.K == 0) return 0;
+    const bool rows = fp.sem_kind == SLIM_IN_PROB_F32 || fp.sem_kind == SLIM_IN_LOGIT_F32;
+    if (rows) return fp.K > 16 ? 7 : (fp.K > 8 ? 6 : 5);
+    return fp.K > 24 ? 4 : (fp.K > 16 ? 3 : (fp.K > 8 ? 2 : 1));
+}
+
+static void launch_leaf(int kind, const FrameParams &fp, const MapDev &md, int blocks, hipStream_t s)
+{
+    const dim3 gl(blocks), bl(kLeafThreads);
+    switch (kind) {
+    case 0: hipLaunchKernelGGL((k_leaf_fuse<0, false, false>), gl, bl, 0, s, fp, md); break;
+    case 1: hipLaunchKernelGGL((k_leaf_fuse<8, false, false>), gl, bl, 0, s, fp, md); break;
+    case 2: hipLaunchKernelGGL((k_leaf_fuse<16, false, false>), gl, bl, 0, s, fp, md); break;
+    case 3: hipLaunchKernelGGL((k_leaf_fuse<24, false, false>), gl, bl, 0, s, fp, md); break;
+    case 4: hipLaunchKernelGGL((k_leaf_fuse<32, false, false>), gl, bl, 0, s, fp, md); break;
+    case 5: hipLaunchKernelGGL((k_leaf_fuse<8, false, true>), gl, bl, 0, s, fp, md); break;
+    case 6: hipLaunchKernelGGL((k_leaf_fuse<16, false, true>), gl, bl, 0, s, fp, md); break;
+    case 7: hipLaunchKernelGGL((k_leaf_fuse<32, false, true>), gl, bl, 0, s, fp, md); break;
+    default: hipLaunchKernelGGL((k_leaf_fuse<0, true, false>), gl, bl, 0, s, fp, md); break;
+    }
+}
+
+static void launch_leaf_batch(int kind, const MapBatch &mb, int blocks, hipStream_t s)
+{
+    const dim3 gl(blocks), bl(kLeafThreads);
+    switch (kind) {
+    case 0: hipLaunchKernelGGL((k_leaf_fuse_batch<0, false, false>), gl, bl, 0, s, mb); break;
+    case 1: hipLaunchKernelGGL((k_leaf_fuse_batch<8, false, false>), gl, bl, 0, s, mb); break;
+    case 2: hipLaunchKernelGGL((k_leaf_fuse_batch<16, false, false>), gl, bl, 0, s, mb); break;
+    case 3: hipLaunchKernelGGL((k_leaf_fuse_batch<24, false, false>), gl, bl, 0, s, mb); break;
+    case 4: hipLaunchKernelGGL((k_leaf_fuse_batch<32, false, false>), gl, bl, 0, s, mb); break;
+    case 5: hipLaunchKernelGGL((k_leaf_fuse_batch<8, false, true>), gl, bl, 0, s, mb); break;
+    case 6: hipLaunchKernelGGL((k_leaf_fuse_batch<16, false, true>), gl, bl, 0, s, mb); break;
+    case 7: hipLaunchKernelGGL((k_leaf_fuse_batch<32, false, true>), gl, bl, 0, s, mb); break;
+    default: hipLaunchKernelGGL((k_leaf_fuse_batch<0, true, false>), gl, bl, 0, s, mb); break;
+    }
+}
+
+hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const LaunchShape &shape, hipStream_t s,
+                            hipEvent_t *ev)
+{
+    MapDev md = md_in;
+    md.leaf_blocks = shape.leaf_blocks;
     const int bw = (fp.n + kWalkThreads - 1) / kWalkThreads;
     auto rec = [&](int e) {
         if (ev) (void)hipEventRecord(ev[e], s);
@@ -982,31 +1122,252 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md, int cus, hi
     hipLaunchKernelGGL(k_ray_walk_emit, dim3(bw > 0 ? bw : 1), dim3(kWalkThreads), 0, s, fp, md);
     rec(1);
     rec(2);
-    hipLaunchKernelGGL(k_leaf_plan, dim3(cus), dim3(256), 0, s, md);
+    hipLaunchKernelGGL(k_leaf_plan, dim3(shape.plan_blocks), dim3(256), 0, s, md);
     rec(3);
     rec(4);
-    const int bb = (int)std::min<long long>(((long long)fp.n * fp.maxsteps + 255) / 256, (long long)cus * 16);
-    hipLaunchKernelGGL(k_pair_bucket, dim3(bb > 0 ? bb : 1), dim3(256), 0, s, md);
+    const long long want = ((long long)fp.n * fp.maxsteps + 255) / 256;
+    const int bb = (int)std::max<long long>(1, std::min<long long>(want, shape.bucket_blocks));
+    hipLaunchKernelGGL(k_pair_bucket, dim3(bb), dim3(256), 0, s, md);
     rec(5);
     rec(6);
-    const dim3 gl(md.leaf_blocks), bl(kLeafThreads);
-    const bool rows = fp.sem_kind == SLIM_IN_PROB_F32 || fp.sem_kind == SLIM_IN_LOGIT_F32;
-    if (fp.L > 0 || fp.K > 32) hipLaunchKernelGGL((k_leaf_fuse<0, true, false>), gl, bl, 0, s, fp, md);
-    else if (fp.K == 0) hipLaunchKernelGGL((k_leaf_fuse<0, false, false>), gl, bl, 0, s, fp, md);
-    else if (rows) {
-        if (fp.K > 16) hipLaunchKernelGGL((k_leaf_fuse<32, false, true>), gl, bl, 0, s, fp, md);
-        else if (fp.K > 8) hipLaunchKernelGGL((k_leaf_fuse<16, false, true>), gl, bl, 0, s, fp, md);
-        else hipLaunchKernelGGL((k_leaf_fuse<8, false, true>), gl, bl, 0, s, fp, md);
-    } else {
-        if (fp.K > 24) hipLaunchKernelGGL((k_leaf_fuse<32, false, false>), gl, bl, 0, s, fp, md);
-        else if (fp.K > 16) hipLaunchKernelGGL((k_leaf_fuse<24, false, false>), gl, bl, 0, s, fp, md);
-        else if (fp.K > 8) hipLaunchKernelGGL((k_leaf_fuse<16, false, false>), gl, bl, 0, s, fp, md);
-        else hipLaunchKernelGGL((k_leaf_fuse<8, false, false>), gl, bl, 0, s, fp, md);
-    }
+    launch_leaf(leaf_kernel_kind(fp), fp, md, shape.leaf_blocks, s);
     rec(7);
     rec(8);
     hipLaunchKernelGGL(k_frame_commit, dim3(1), dim3(256), 0, s, fp, md);
     rec(9);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate_batched(const MapBatch &mb, const BatchPlan &plan, const LaunchShape &shape,
+                                    hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ray_walk_emit_batch, dim3(std::max(plan.walk_blocks, 1)), dim3(kWalkThreads), 0, s, mb);
+    hipLaunchKernelGGL(k_leaf_plan_batch, dim3(shape.plan_blocks), dim3(256), 0, s, mb);
+    hipLaunchKernelGGL(k_pair_bucket_batch, dim3(shape.bucket_blocks), dim3(256), 0, s, mb);
+    for (int g = 0; g < plan.ngroups; ++g) {
+        MapBatch sub = mb;
+        sub.subset = mb.subset + plan.group_begin[g];
+        sub.nsubset = plan.group_size[g];
+        launch_leaf_batch(plan.group_kind[g], sub, shape.leaf_blocks, s);
+    }
+    hipLaunchKernelGGL(k_frame_commit_batch, dim3(plan.nmaps), dim3(256), 0, s, mb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// map loss and backward (differentiation workload)
+// ---------------------------------------------------------------------------
+
+// Record of the voxel with integer key (kx, ky, kz), or -1 if it has W = 0.
+__device__ __forceinline__ long long voxel_record(const MapDev &md, int kx, int ky, int kz)
+{
+    const int slot = map_find(md, pack_leaf(kx >> 3, ky >> 3, kz >> 3));
+    if (slot < 0) return -1;
+    const int off = ((kx & 7) << 6) | ((ky & 7) << 3) | (kz & 7);
+    if (!((md.leaf_occ[(size_t)slot * kMaskWords + (off >> 5)] >> (off & 31)) & 1u)) return -1;
+    return (long long)md.leaf_page[(size_t)slot * kLeafPages + (off >> 6)] * kPageVoxels + (off & (kPageVoxels - 1));
+}
+
+// Record of the voxel holding world point (x, y, z): floor(x / vs), binary32.
+__device__ __forceinline__ long long point_record(const MapDev &md, float vs, float x, float y, float z)
+{
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) return -1;
+    const float fx = floorf(x / vs), fy = floorf(y / vs), fz = floorf(z / vs);
+    const float lim = (float)kKeyLimit;
+    if (!(fabsf(fx) < lim && fabsf(fy) < lim && fabsf(fz) < lim)) return -1;
+    return voxel_record(md, (int)fx, (int)fy, (int)fz);
+}
+
+// Block sum of one float per thread in a fixed tree order (blockDim.x = 256).
+__device__ __forceinline__ float block_sum(float v, float *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = kLossThreads / 2; d > 0; d >>= 1) {
+        if (threadIdx.x < (unsigned)d) red[threadIdx.x] += red[threadIdx.x + d];
+        __syncthreads();
+    }
+    const float r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_loss_clear(MapDev md, LossParams lp)
+{
+    const size_t n = (size_t)md.st->pages_used * kPageVoxels;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        lp.adj_cnt[i] = 0;
+}
+
+// Surface samples: per voxel count (integer, so order-free) and block partials
+// of |D| and of the number of samples that land in the map.
+__global__ __launch_bounds__(kLossThreads) void k_loss_samples(FrameParams fp, MapDev md, LossParams lp)
+{
+    __shared__ float red[kLossThreads];
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    float a = 0.0f, c = 0.0f;
+    if (i < lp.s) {
+        const long long rec = point_record(md, fp.vs, lp.samples[3 * i], lp.samples[3 * i + 1], lp.samples[3 * i + 2]);
+        if (rec >= 0) {
+            atomicAdd(&lp.adj_cnt[rec], 1);
+            a = fabsf(md.vox[(size_t)rec * md.rec_stride]);
+            c = 1.0f;
+        }
+    }
+    a = block_sum(a, red);
+    c = block_sum(c, red);
+    if (threadIdx.x == 0) {
+        lp.part[blockIdx.x] = a;
+        lp.part_cnt[blockIdx.x] = (int)c;
+    }
+}
+
+// Voxels: cross-entropy of the Dirichlet predictive (Eq. (7)) at the true class,
+// adjoints dL/dc and dL/dD, block partials of the cross-entropy.
+__global__ __launch_bounds__(kLossThreads) void k_loss_voxels(FrameParams fp, MapDev md, LossParams lp, int nsb)
+{
+    __shared__ float red[kLossThreads];
+    __shared__ int s_mp;
+    if (threadIdx.x == 0) {
+        int mp = 0;
+        for (int b = 0; b < nsb; ++b) mp += lp.part_cnt[b];
+        s_mp = mp;
+    }
+    __syncthreads();
+    const float inv_m = 1.0f / (float)lp.m, inv_mp = s_mp > 0 ? 1.0f / (float)s_mp : 0.0f;
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const int K = fp.K;
+    float ce = 0.0f;
+    if (i < lp.m) {
+        const long long rec = voxel_record(md, lp.keys[3 * i], lp.keys[3 * i + 1], lp.keys[3 * i + 2]);
+        const int y = lp.labels[i];
+        if (rec >= 0 && y >= 0 && y < K) {
+            const float *R = md.vox + (size_t)rec * md.rec_stride;
+            float tot = (float)K * lp.alpha0;
+            for (int k = 0; k < K; ++k) tot += R[2 + k];
+            const float ay = lp.alpha0 + R[2 + y];
+            ce = -logf(ay / tot);
+            float *A = lp.adj + (size_t)rec * lp.adj_stride;
+            const float g = inv_m / tot;
+            for (int k = 0; k < K; ++k) A[k] = k == y ? g - inv_m / ay : g;
+            const float D = R[0];
+            const float sg = D > 0.0f ? 1.0f : (D < 0.0f ? -1.0f : 0.0f);
+            A[K] = sg * (float)lp.adj_cnt[rec] * inv_mp;
+        }
+    }
+    ce = block_sum(ce, red);
+    if (threadIdx.x == 0) lp.part[nsb + blockIdx.x] = ce;
+}
+
+__global__ __launch_bounds__(256) void k_loss_final(LossParams lp, int nsb, int nvb)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float l1 = 0.0f, ce = 0.0f;
+    int mp = 0;
+    for (int b = 0; b < nsb; ++b) {
+        l1 += lp.part[b];
+        mp += lp.part_cnt[b];
+    }
+    for (int b = 0; b < nvb; ++b) ce += lp.part[nsb + b];
+    const float t_ce = ce / (float)lp.m, t_l1 = mp > 0 ? l1 / (float)mp : 0.0f;
+    lp.loss[0] = t_ce + t_l1;
+    lp.loss[1] = t_ce;
+    lp.loss[2] = t_l1;
+}
+
+hipError_t launch_loss(const FrameParams &fp, const MapDev &md, const LossParams &lp, hipStream_t s)
+{
+    const int nsb = (int)((lp.s + kLossThreads - 1) / kLossThreads);
+    const int nvb = (int)((lp.m + kLossThreads - 1) / kLossThreads);
+    hipLaunchKernelGGL(k_loss_clear, dim3(1024), dim3(256), 0, s, md, lp);
+    if (nsb > 0) hipLaunchKernelGGL(k_loss_samples, dim3(nsb), dim3(kLossThreads), 0, s, fp, md, lp);
+    if (nvb > 0) hipLaunchKernelGGL(k_loss_voxels, dim3(nvb), dim3(kLossThreads), 0, s, fp, md, lp, nsb);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, lp, nsb, nvb);
+    return hipGetLastError();
+}
+
+// One lane per ray: recompute the band walk, gather the adjoints of the voxels
+// it observed, and chain them through the softmax and the clamp.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_backward_rays(FrameParams fp, MapDev md, LossParams lp,
+                                                       const float *grad_scale, float *grad_logits,
+                                                       float *grad_ranges)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= fp.n) return;
+    const int K = fp.K;
+    float G[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) G[k] = 0.0f;
+    float gr = 0.0f;
+    Ray ry;
+    float x, y, z;
+    load_point(fp, i, x, y, z);
+    bool valid = make_ray(fp, x, y, z, ry);
+    if (valid) {
+        bool inrange = true;
+        unsigned long long cur = kEmptyKey;
+        int slot = -1;
+        band_walk(fp, ry, [&](int cx, int cy, int cz) {
+            const int kx = fp.a[0] + cx, ky = fp.a[1] + cy, kz = fp.a[2] + cz;
+            if (!(key_ok(kx) && key_ok(ky) && key_ok(kz))) {
+                inrange = false;
+                return;
+            }
+            const float sdf = cell_sdf(fp, ry, cx, cy, cz);
+            if (!(sdf > -fp.tau) || !inrange) return;
+            const unsigned long long lk = pack_leaf(kx >> 3, ky >> 3, kz >> 3);
+            if (lk != cur) {
+                cur = lk;
+                slot = map_find(md, lk);
+            }
+            if (slot < 0) return;
+            const int off = ((kx & 7) << 6) | ((ky & 7) << 3) | (kz & 7);
+            const int page = md.leaf_page[(size_t)slot * kLeafPages + (off >> 6)];
+            if (page < 0) return;  // not a voxel of this map (inputs differ from the integrated ones)
+            const long long rec = (long long)page * kPageVoxels + (off & (kPageVoxels - 1));
+            const float *A = lp.adj + (size_t)rec * lp.adj_stride;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < K) G[k] += A[k];
+            if (sdf < fp.tau) gr += A[K] / md.vox[(size_t)rec * md.rec_stride + 1];
+        });
+        valid = inrange;
+    }
+    const float sc = grad_scale ? grad_scale[0] : 1.0f;
+    float l[KMAX];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        l[k] = k < K ? ((const float *)fp.sem)[(size_t)i * K + k] : -INFINITY;
+        mx = fmaxf(mx, l[k]);
+    }
+    float den = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        l[k] = k < K ? expf(l[k] - mx) : 0.0f;
+        den += l[k];
+    }
+    float pg = 0.0f;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        l[k] /= den;
+        pg += l[k] * G[k];
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+        if (k < K) grad_logits[(size_t)i * K + k] = valid ? sc * l[k] * (G[k] - pg) : 0.0f;
+    grad_ranges[i] = valid ? sc * gr : 0.0f;
+}
+
+hipError_t launch_backward(const FrameParams &fp, const MapDev &md, const LossParams &lp, const float *grad_scale,
+                           float *grad_logits, float *grad_ranges, hipStream_t s)
+{
+    const int b = (fp.n + 255) / 256;
+    if (b == 0) return hipGetLastError();
+    if (fp.K > 16) hipLaunchKernelGGL(k_backward_rays<32>, dim3(b), dim3(256), 0, s, fp, md, lp, grad_scale, grad_logits, grad_ranges);
+    else if (fp.K > 8) hipLaunchKernelGGL(k_backward_rays<16>, dim3(b), dim3(256), 0, s, fp, md, lp, grad_scale, grad_logits, grad_ranges);
+    else hipLaunchKernelGGL(k_backward_rays<8>, dim3(b), dim3(256), 0, s, fp, md, lp, grad_scale, grad_logits, grad_ranges);
     return hipGetLastError();
 }
 

@@ -20,8 +20,10 @@ SEM_NONE, SEM_CLOSED, SEM_OPEN = 0, 1, 2
 IN_NONE, IN_LABEL_I32, IN_PROB_F32, IN_LOGIT_F32, IN_EMB_BF16, IN_EMB_F32 = range(6)
 KERNELS = ("ray_walk_emit", "leaf_plan", "pair_bucket", "leaf_fuse", "frame_commit")
 
-EXPORTS = ("slim_map_create", "slim_map_destroy", "slim_map_reset", "slim_integrate", "slim_map_stats",
-           "slim_extract", "slim_query", "slim_profile_enable", "slim_profile_read", "slim_last_error")
+EXPORTS = ("slim_map_create", "slim_map_destroy", "slim_map_reset", "slim_integrate", "slim_integrate_rays",
+           "slim_map_stats", "slim_extract", "slim_query", "slim_map_loss", "slim_backward_rays",
+           "slim_integrate_batched", "slim_set_launch_shape", "slim_profile_enable", "slim_profile_read",
+           "slim_last_error")
 
 
 class MapConfig(ctypes.Structure):
@@ -40,6 +42,17 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("ranges", ctypes.c_void_p), ("dirs", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("pose", ctypes.c_double * 16), ("sem", ctypes.c_void_p),
+                ("sem_kind", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class LaunchShape(ctypes.Structure):
+    _fields_ = [("plan_blocks", ctypes.c_int32), ("bucket_blocks", ctypes.c_int32),
+                ("leaf_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SlimError(RuntimeError):
@@ -63,9 +76,14 @@ def load(path: str = LIB_PATH):
         L.slim_map_destroy.argtypes = [vp]
         L.slim_map_reset.argtypes = [vp, vp]
         L.slim_integrate.argtypes = [vp, vp, i64, vp, vp, i32, vp]
+        L.slim_integrate_rays.argtypes = [vp, vp, vp, i64, vp, vp, i32, vp]
+        L.slim_map_loss.argtypes = [vp, vp, vp, i64, vp, i64, ctypes.c_float, vp, vp]
+        L.slim_backward_rays.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.slim_map_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
         L.slim_extract.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
         L.slim_query.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+        L.slim_integrate_batched.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Frame), i32, vp]
+        L.slim_set_launch_shape.argtypes = [vp, ctypes.POINTER(LaunchShape)]
         L.slim_profile_enable.argtypes = [vp, i32]
         L.slim_profile_read.argtypes = [vp, vp, vp, i32, vp]
         L.slim_last_error.restype = ctypes.c_char_p
@@ -122,6 +140,28 @@ class Map:
         _check(self._L.slim_integrate(self.h, _ptr(points), n, self._pose.ctypes.data_as(ctypes.c_void_p),
                                       _ptr(sem), kind, _stream(self.device)))
 
+    def integrate_rays(self, ranges, dirs, pose, sem=None, kind=IN_NONE):
+        """ranges: (N,) float32; dirs: (N, 3) float32 unit sensor-frame directions (cuda tensors)."""
+        self._pose[:] = np.asarray(pose, np.float64).reshape(16)
+        n = ranges.shape[0]
+        _check(self._L.slim_integrate_rays(self.h, _ptr(ranges), _ptr(dirs), n,
+                                           self._pose.ctypes.data_as(ctypes.c_void_p), _ptr(sem), kind,
+                                           _stream(self.device)))
+
+    def loss(self, keys, labels, samples, alpha0=1.0, out=None):
+        """Map loss (see include/slimvdb.h); returns a (3,) cuda tensor (total, ce, l1)."""
+        out = torch.empty(3, dtype=torch.float32, device=self.device) if out is None else out
+        _check(self._L.slim_map_loss(self.h, _ptr(keys), _ptr(labels), keys.shape[0], _ptr(samples),
+                                     samples.shape[0], float(alpha0), _ptr(out), _stream(self.device)))
+        return out
+
+    def backward_rays(self, ranges, dirs, pose, logits, grad_logits, grad_ranges, grad_scale=None):
+        self._pose[:] = np.asarray(pose, np.float64).reshape(16)
+        _check(self._L.slim_backward_rays(self.h, _ptr(ranges), _ptr(dirs), ranges.shape[0],
+                                          self._pose.ctypes.data_as(ctypes.c_void_p), _ptr(logits),
+                                          _ptr(grad_scale), _ptr(grad_logits), _ptr(grad_ranges),
+                                          _stream(self.device)))
+
     def stats(self):
         st = Stats()
         _check(self._L.slim_map_stats(self.h, ctypes.byref(st), _stream(self.device)))
@@ -151,6 +191,14 @@ class Map:
                                   _stream(self.device)))
         return dict(D=d[:m], W=w[:m], sem=sem[:m, : self.nsem])
 
+    def set_launch_shape(self, plan_blocks=None, bucket_blocks=None, leaf_blocks_per_cu=None):
+        """Grid sizes of the grid-stride kernels; all None restores the defaults."""
+        if plan_blocks is None and bucket_blocks is None and leaf_blocks_per_cu is None:
+            _check(self._L.slim_set_launch_shape(self.h, None))
+        else:
+            sh = LaunchShape(plan_blocks, bucket_blocks, leaf_blocks_per_cu, 0)
+            _check(self._L.slim_set_launch_shape(self.h, ctypes.byref(sh)))
+
     def profile(self, enable=True):
         _check(self._L.slim_profile_enable(self.h, 1 if enable else 0))
 
@@ -160,3 +208,22 @@ class Map:
         _check(self._L.slim_profile_read(self.h, ms.ctypes.data_as(ctypes.c_void_p),
                                          n.ctypes.data_as(ctypes.c_void_p), len(KERNELS), _stream(self.device)))
         return {k: (float(a), int(b)) for k, a, b in zip(KERNELS, ms, n)}
+
+
+def integrate_batched(maps, frames, use_graph=False):
+    """frames[i] = dict(points=cuda (n,3) | ranges=..., dirs=..., pose=4x4, sem=cuda tensor, kind=IN_*)
+    integrated into maps[i], all in one batched launch sequence (see include/slimvdb.h)."""
+    L = load()
+    n = len(maps)
+    arr = (Frame * n)()
+    for i, f in enumerate(frames):
+        pts = f.get("points")
+        arr[i].points = pts.data_ptr() if pts is not None else None
+        arr[i].ranges = f["ranges"].data_ptr() if f.get("ranges") is not None else None
+        arr[i].dirs = f["dirs"].data_ptr() if f.get("dirs") is not None else None
+        arr[i].n = (pts if pts is not None else f["ranges"]).shape[0]
+        arr[i].pose[:] = [float(v) for v in np.asarray(f["pose"], np.float64).reshape(16)]
+        arr[i].sem = f["sem"].data_ptr() if f.get("sem") is not None else None
+        arr[i].sem_kind = f.get("kind", IN_NONE)
+    handles = (ctypes.c_void_p * n)(*[m.h.value for m in maps])
+    _check(L.slim_integrate_batched(handles, n, arr, 1 if use_graph else 0, _stream(maps[0].device)))

@@ -261,6 +261,10 @@ class StreetScene:
         cls = np.zeros(len(t), np.int64)
         cls = np.where(which == 1, self.box_class[np.maximum(ib, 0)], cls)
         cls = np.where(which == 2, self.cyl_class[np.maximum(ic, 0)], cls)
+        # primitive index: ground 0, boxes 1.., cylinders after the boxes
+        prim = np.where(which == 1, 1 + np.maximum(ib, 0), 0)
+        prim = np.where(which == 2, 1 + len(self.box_lo) + np.maximum(ic, 0), prim)
+        self._last_prim = prim
         return t, cls
 
     def sweeps(self, ts, workers=8):
@@ -285,7 +289,8 @@ class StreetScene:
         rng = _rng(self.seed, 3, t)
         flick = rng.random(len(r)) < self.flicker
         lab = np.where(flick, rng.integers(0, STREET_CLASSES, len(r)), cls).astype(np.int32)
-        return dict(points=pts, pose=pose, label=lab, true_class=cls.astype(np.int32), range=r, dirs=dirs)
+        return dict(points=pts, pose=pose, label=lab, true_class=cls.astype(np.int32), range=r, dirs=dirs,
+                    prim=self._last_prim.astype(np.int32))
 
 
     # --- differentiation workload: rays, logits, ground truth, surface samples ---
@@ -376,6 +381,39 @@ class StreetScene:
         pts = np.concatenate(pts)
         idx = _rng(seed, 6).choice(len(pts), size=min(count, len(pts)), replace=False)
         return pts[np.sort(idx)].astype(np.float32)
+
+
+def primitive_embeddings(scene, prim, L, seed, t, noise=0.1):
+    """Open-set embeddings for street points: a random unit prototype per
+    primitive plus N(0, noise^2) per component, L2-normalised, bf16 bits."""
+    nprim = 1 + len(scene.box_lo) + len(scene.cyl_r)
+    proto = _rng(seed, 7).normal(size=(nprim, L)).astype(np.float32)
+    proto /= np.linalg.norm(proto, axis=1, keepdims=True)
+    z = proto[prim]
+    z += _rng(seed, 8, t).standard_normal(z.shape, dtype=np.float32) * np.float32(noise)
+    z /= np.linalg.norm(z, axis=1, keepdims=True)
+    return to_bf16_bits(z)
+
+
+def batched_workload(seed=4, nmaps=32, n_lo=10_000, n_hi=130_000, closed_maps=16, K=20, L=256, beams=128):
+    """Many independent maps, one frame each: the first n_i rays (azimuth-major)
+    of a 128-beam sweep of the street from a random trajectory pose, n_i uniform
+    in [n_lo, n_hi].  Maps below `closed_maps` get int32 labels (K classes), the
+    others bf16 embeddings of size L.  Returns a list of dicts (kind, frame)."""
+    scene = StreetScene(seed=2, beams=beams)
+    rng = _rng(seed, 9)
+    out = []
+    for i in range(nmaps):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        t = int(rng.integers(0, 100))
+        sw = scene.sweep(t, nrays=n)
+        item = dict(points=sw["points"], pose=sw["pose"], n=n)
+        if i < closed_maps:
+            item.update(mode="closed", K=K, label=sw["label"])
+        else:
+            item.update(mode="open", L=L, emb=primitive_embeddings(scene, sw["prim"], L, seed, t))
+        out.append(item)
+    return out
 
 
 # ----------------------------------------------------------------------------

@@ -75,3 +75,10 @@ def test_null_arguments():
     assert L.slim_query(None, None, 0, None, None, None, None) == sv.ERR_INVALID
     assert L.slim_profile_enable(None, 1) == sv.ERR_INVALID
     assert L.slim_map_destroy(None) == sv.OK
+
+
+def test_differentiation_entry_points_reject_bad_arguments():
+    L = sv.load()
+    assert L.slim_integrate_rays(None, None, None, 0, None, None, 0, None) == sv.ERR_INVALID
+    assert L.slim_map_loss(None, None, None, 0, None, 0, 1.0, None, None) == sv.ERR_INVALID
+    assert L.slim_backward_rays(None, None, None, 0, None, None, None, None, None, None) == sv.ERR_INVALID

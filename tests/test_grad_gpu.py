@@ -1,0 +1,83 @@
+"""GPU parity of the differentiation workload: the map loss and its
+hand-written backward (through the C ABI, behind torch.autograd.Function)
+against the oracle's FP64 loss and analytic gradient, which the CPU tests pin
+to FP64 finite differences."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import loss as ol
+from paper_2512_12945_amd import slimvdb as sv
+from paper_2512_12945_amd import synth
+from paper_2512_12945_amd.autograd import map_loss
+
+from _gpu_util import cuda, extract_np
+
+pytestmark = pytest.mark.gpu
+VS, TAU, K = 0.1, 0.3, 20
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sv.load()
+    sc = synth.StreetScene(seed=2)
+    frames = [sc.ray_sweep(t) for t in range(3)]
+    om = oracle.OracleMap(VS, TAU, 0.0, 50.0, oracle.SEM_CLOSED, K)
+    for fr in frames:
+        om.integrate(ol.rays_to_points(fr["ranges"], fr["dirs"]), fr["pose"], fr["logits"], oracle.IN_LOGIT_F32)
+    ex = om.extract()
+    y = sc.nearest_class((ex["keys"] + 0.5) * np.float64(np.float32(VS)))
+    samples = sc.surface_samples(frames, count=3000)
+    lo = ol.map_loss(ex, y, samples, VS)
+    grads = [ol.frame_gradients(om, fr, ex, lo)[:2] for fr in frames]
+    return frames, ex, y, samples, lo, grads
+
+
+def _run(frames, ex, y, samples, gmap):
+    ranges = cuda(np.stack([f["ranges"] for f in frames])).requires_grad_(True)
+    logits = cuda(np.stack([f["logits"] for f in frames])).requires_grad_(True)
+    dirs = cuda(np.stack([f["dirs"] for f in frames]))
+    poses = [f["pose"] for f in frames]
+    loss = map_loss(ranges, logits, dirs, poses, gmap, cuda(ex["keys"]), cuda(y.astype(np.int32)), cuda(samples))
+    loss.backward()
+    torch.cuda.synchronize()
+    return loss, ranges.grad.cpu().numpy(), logits.grad.cpu().numpy()
+
+
+def test_loss_and_gradients_match_oracle(setup):
+    frames, ex, y, samples, lo, grads = setup
+    _say(f"3 ray sweeps, {lo['M']} voxels, {lo['Mp']} samples in the map")
+    gmap = sv.Map(VS, TAU, 0.0, 50.0, sv.SEM_CLOSED, K, 0, 0, 1 << 16, 1 << 22)
+    loss, gr, gl = _run(frames, ex, y, samples, gmap)
+    gx = extract_np(gmap)
+    assert np.array_equal(gx["keys"], ex["keys"]) and np.array_equal(gx["W"].astype(np.float64), ex["W"])
+    rel = abs(float(loss) - lo["loss"]) / lo["loss"]
+    _say(f"  loss gpu {float(loss):.9g} oracle {lo['loss']:.9g} rel {rel:.2e}")
+    assert rel < 1e-5
+    worst_l, worst_r = 0.0, 0.0
+    for f, (g_logit, g_r) in enumerate(grads):
+        sl, sr = np.abs(g_logit).max(), np.abs(g_r).max()
+        el = np.abs(gl[f] - g_logit) / (np.abs(g_logit) + sl)
+        er = np.abs(gr[f] - g_r) / (np.abs(g_r) + sr)
+        worst_l, worst_r = max(worst_l, el.max()), max(worst_r, er.max())
+        assert el.max() < 1e-5 and er.max() < 1e-5, (f, el.max(), er.max())
+    _say(f"  worst gradient error (relative to |g| + max|g|): logits {worst_l:.2e}, ranges {worst_r:.2e}")
+
+
+def test_backward_is_deterministic(setup):
+    frames, ex, y, samples, lo, grads = setup
+    gmap = sv.Map(VS, TAU, 0.0, 50.0, sv.SEM_CLOSED, K, 0, 0, 1 << 16, 1 << 22)
+    a = _run(frames, ex, y, samples, gmap)
+    b = _run(frames, ex, y, samples, gmap)
+    assert float(a[0]) == float(b[0])
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
