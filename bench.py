@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-diff", action="store_true", help="skip the forward+backward measurement")
     ap.add_argument("--diff-reps", type=int, default=5)
+    ap.add_argument("--no-batched", action="store_true", help="skip the many-map batched measurement")
+    ap.add_argument("--no-open", action="store_true", help="skip the open-set RGB-D measurement")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="also run plain device copies of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -97,6 +101,172 @@ def diff_bench(sv, synth, torch, scene, frames=16, reps=5, vs=0.1, tau=0.3, ncls
             "points_per_s_fwd_bwd": frames * ranges.shape[1] / (t_fb / 1e3)}
 
 
+def batched_bench(sv, synth, torch, reps=10, log_fn=log):
+    """Many-map workload: 32 independent maps, one frame each with 10k-130k
+    rays of a 128-beam street sweep; 16 maps 20-class closed set (int32
+    labels), 16 maps 256-d open set (bf16 embeddings).  The launch shape comes
+    from the autotuner.  Times, in steady state (each map already holds its
+    frame once, so every voxel exists), one batched call per replay (eager and
+    graph) against one plain integration per map on the same stream."""
+    from paper_2512_12945_amd import autotune
+
+    t0 = time.time()
+    w = synth.batched_workload(workers=min(8, os.cpu_count() or 1))
+    dev = torch.device("cuda", 0)
+    frames, cfgs = [], []
+    for item in w:
+        if item["mode"] == "closed":
+            frames.append(dict(points=torch.from_numpy(item["points"]).to(dev), pose=item["pose"],
+                               sem=torch.from_numpy(item["label"]).to(dev), kind=sv.IN_LABEL_I32))
+            cfgs.append(dict(voxel_size=0.1, sdf_trunc=0.3, min_range=0.0, max_range=50.0, sem_mode=sv.SEM_CLOSED,
+                             num_classes=item["K"], embed_dim=0, device=0, max_leaves=1 << 15,
+                             max_voxels=1 << 21))
+        else:
+            frames.append(dict(points=torch.from_numpy(item["points"]).to(dev), pose=item["pose"],
+                               sem=torch.from_numpy(item["emb"]).to(dev), kind=sv.IN_EMB_BF16))
+            cfgs.append(dict(voxel_size=0.1, sdf_trunc=0.3, min_range=0.0, max_range=50.0, sem_mode=sv.SEM_OPEN,
+                             num_classes=0, embed_dim=item["L"], device=0, max_leaves=1 << 15,
+                             max_voxels=1 << 21))
+    torch.cuda.synchronize()
+    log_fn(f"batched inputs ready in {time.time() - t0:.1f}s: {sum(x['n'] for x in w)} points over {len(w)} maps")
+    shape = autotune.tune(cfgs, frames, cache_path=os.path.join(os.environ.get("TMPDIR", "/tmp"),
+                                                                "slimvdb_autotune.json"), log=log_fn)
+    maps = [sv.Map(**c) for c in cfgs]
+    maps[0].set_launch_shape(*shape)
+    for m in maps[1:]:
+        m.set_launch_shape(*shape)
+
+    def sequential():
+        for m, f in zip(maps, frames):
+            m.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            s = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - s)
+        return float(np.median(ts)) * 1e3
+
+    t_seq = timed(sequential)
+    t_eager = timed(lambda: sv.integrate_batched(maps, frames, use_graph=False))
+    t_graph = timed(lambda: sv.integrate_batched(maps, frames, use_graph=True))
+    st = [m.stats() for m in maps]
+    npts = sum(x["n"] for x in w)
+    pairs = sum(s["pairs_last"] for s in st)
+    for m in maps:
+        m.close()
+    return {"workload": "32 maps, one street-sweep frame each with 10k-130k rays (128 beams); 16 maps 20-class "
+                        "int32 labels, 16 maps 256-d bf16 embeddings; voxel 0.1 m, trunc 0.3 m; steady state",
+            "points": npts, "pairs": pairs, "launch_shape": list(shape),
+            "sequential_ms": t_seq, "batched_ms": t_eager, "batched_graph_ms": t_graph,
+            "speedup_graph_vs_sequential": t_seq / t_graph,
+            "points_per_s_graph": npts / (t_graph / 1e3)}
+
+
+def run_sequence(torch, gmap, seq, W, K):
+    """Integrates seq[0:W] (warm-up) and times seq[W:W+K], three passes over a
+    reset map: one with stats after every frame (the counts), one with kernel
+    events (per-kernel time), one plain (the step time)."""
+    per = []
+    for f in seq:
+        gmap.integrate(*f)
+        per.append(gmap.stats())
+    gmap.reset()
+
+    def warm():
+        for f in seq[:W]:
+            gmap.integrate(*f)
+        torch.cuda.synchronize()
+
+    warm()
+    gmap.profile(True)
+    gmap.profile_read()
+    start = time.perf_counter()
+    for f in seq[W:W + K]:
+        gmap.integrate(*f)
+    torch.cuda.synchronize()
+    elapsed_events = time.perf_counter() - start
+    kern = gmap.profile_read()
+    gmap.profile(False)
+    assert gmap.stats()["voxels"] == per[-1]["voxels"], "timed pass diverged from the counting pass"
+    gmap.reset()
+    warm()
+    start = time.perf_counter()
+    for f in seq[W:W + K]:
+        gmap.integrate(*f)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - start
+    assert gmap.stats()["voxels"] == per[-1]["voxels"], "timed pass diverged from the counting pass"
+    return dict(per=per, kern=kern, elapsed=elapsed, elapsed_events=elapsed_events)
+
+
+def account(timed, n_pts, b_sem, S_v):
+    """Algorithmic HBM bytes of the timed frames: every point read once
+    (12 B of coordinates plus b_sem of semantics), every voxel that existed read
+    and written (2 S_v), every new voxel written (S_v).  Split by kernel: the
+    walk reads the coordinates, the fused leaf kernel the semantics and state."""
+    P = sum(s["pairs_last"] for s in timed)
+    valid = sum(s["points_last"] - s["rejected_last"] for s in timed)
+    u_old = sum(s["voxels_old_last"] for s in timed)
+    u_new = sum(s["voxels_new_last"] for s in timed)
+    K = len(timed)
+    bytes_points = n_pts * K * 12
+    bytes_sem = n_pts * K * b_sem
+    bytes_state = u_old * 2 * S_v + u_new * S_v
+    kalg = {"ray_walk_emit": bytes_points, "leaf_plan": 0, "pair_bucket": 0, "leaf_fuse": bytes_sem + bytes_state,
+            "frame_commit": 0}
+    return dict(pairs=P, valid=valid, u_old=u_old, u_new=u_new, kalg=kalg,
+                b_alg=bytes_points + bytes_sem + bytes_state)
+
+
+def dominant(kern, kalg, K):
+    """Kernel with the most time, its achieved algorithmic GB/s (bytes per
+    launch over its average event-timed duration) and its bytes per launch."""
+    dom = max(kern, key=lambda k: kern[k][0])
+    dom_ms, dom_n = kern[dom]
+    avg_s = dom_ms / 1e3 / max(dom_n, 1)
+    per_launch = kalg[dom] / K
+    return dom, (per_launch / avg_s / 1e9 if avg_s > 0 else 0.0), per_launch
+
+
+def open_bench(sv, synth, torch, warm=2, steps=6, log_fn=log):
+    """Open-set RGB-D workload: 640x480 depth frames (307,200 points) of a room
+    with 50 boxes on a 0.5 deg/frame orbit, per-pixel 512-d bf16 embeddings,
+    voxel 0.02 m, trunc 0.06 m.  Integrates `warm` frames, then times `steps`
+    more; reports points/s, voxel updates/s and the roofline of the dominant
+    kernel as for the LiDAR sweep."""
+    L = 512
+    t0 = time.time()
+    sc = synth.OpenRoomScene(L=L)
+    fr = sc.frames(range(warm + steps), workers=min(8, os.cpu_count() or 1))
+    dev = torch.device("cuda", 0)
+    seq = [(torch.from_numpy(f["points"]).to(dev), f["pose"], torch.from_numpy(f["emb"]).to(dev), sv.IN_EMB_BF16)
+           for f in fr]
+    n_pts = fr[0]["points"].shape[0]
+    del fr
+    torch.cuda.synchronize()
+    log_fn(f"open-set frames ready in {time.time() - t0:.1f}s")
+    gmap = sv.Map(0.02, 0.06, 0.0, 10.0, sv.SEM_OPEN, 0, L, 0, max_leaves=1 << 14, max_voxels=1 << 21)
+    run = run_sequence(torch, gmap, seq, warm, steps)
+    gmap.close()
+    acc = account(run["per"][warm:warm + steps], n_pts, 2 * L, 8 + 8 * L)
+    dom, dom_gbs, dom_bytes = dominant(run["kern"], acc["kalg"], steps)
+    el = run["elapsed"]
+    return {"workload": "open-set RGB-D: 640x480 depth frames (307,200 points), room of 50 boxes, orbit 0.5 deg/frame, "
+                        "512-d bf16 embeddings, voxel 0.02 m, trunc 0.06 m",
+            "frames_timed": steps, "first_timed_frame": warm, "points_per_s": n_pts * steps / el,
+            "ms_per_frame": el / steps * 1e3, "voxel_updates_per_s": acc["pairs"] / el,
+            "valid_points_per_s": acc["valid"] / el, "alg_bytes_per_frame": acc["b_alg"] / steps,
+            "path_roofline_frac": acc["b_alg"] / el / 1e9 / HBM_PEAK_GBS,
+            "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in run["kern"].items()},
+            "roofline": {"kernel": dom, "bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": dom_gbs / HBM_PEAK_GBS, "alg_bytes_per_launch": dom_bytes}}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -124,61 +294,14 @@ def main():
     n_pts = sweeps[0]["points"].shape[0]
 
     gmap = sv.Map(vs, tau, 0.0, rmax, sv.SEM_CLOSED, ncls, 0, 0, max_leaves=1 << 18, max_voxels=1 << 24)
-
-    # counts per sweep (deterministic): one untimed pass with stats
-    per = []
-    for i in range(W + K):
-        gmap.integrate(pts[i], poses[i], lab[i], sv.IN_LABEL_I32)
-        per.append(gmap.stats())
-    gmap.reset()
-    torch.cuda.synchronize()
-
-    # timed pass: warm-up sweeps, then K timed sweeps with kernel events
-    for i in range(W):
-        gmap.integrate(pts[i], poses[i], lab[i], sv.IN_LABEL_I32)
-    gmap.profile(True)
-    gmap.profile_read()
-    torch.cuda.synchronize()
-    start = time.perf_counter()
-    for i in range(W, W + K):
-        gmap.integrate(pts[i], poses[i], lab[i], sv.IN_LABEL_I32)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - start
-    kern = gmap.profile_read()
-    gmap.profile(False)
-    final = gmap.stats()
-    assert final["voxels"] == per[-1]["voxels"], "timed pass diverged from the counting pass"
-
-    # same K sweeps again without events, for the step time without event overhead
-    gmap.reset()
-    for i in range(W):
-        gmap.integrate(pts[i], poses[i], lab[i], sv.IN_LABEL_I32)
-    torch.cuda.synchronize()
-    s2 = time.perf_counter()
-    for i in range(W, W + K):
-        gmap.integrate(pts[i], poses[i], lab[i], sv.IN_LABEL_I32)
-    torch.cuda.synchronize()
-    elapsed_noev = time.perf_counter() - s2
-
-    timed = per[W:W + K]
-    P = sum(s["pairs_last"] for s in timed)
-    valid = sum(s["points_last"] - s["rejected_last"] for s in timed)
-    u_old = sum(s["voxels_old_last"] for s in timed)
-    u_new = sum(s["voxels_new_last"] for s in timed)
-    S_v = 8 + 4 * ncls  # D, W and K float counts
-    b_sem = 4           # int32 label
-    bytes_points = n_pts * K * 12
-    bytes_sem = n_pts * K * b_sem
-    bytes_state = u_old * 2 * S_v + u_new * S_v
-    b_alg = bytes_points + bytes_sem + bytes_state
-
-    # dominant kernel and its algorithmic bytes
-    kalg = {"ray_walk_emit": bytes_points, "leaf_plan": 0, "pair_bucket": 0, "leaf_fuse": bytes_sem + bytes_state,
-            "frame_commit": 0}
-    dom = max(kern, key=lambda k: kern[k][0])
-    dom_ms, dom_n = kern[dom]
-    dom_avg_s = dom_ms / 1e3 / max(dom_n, 1)
-    dom_gbs = kalg[dom] / K / dom_avg_s / 1e9 if dom_avg_s > 0 else 0.0
+    seq = [(pts[i], poses[i], lab[i], sv.IN_LABEL_I32) for i in range(W + K)]
+    run = run_sequence(torch, gmap, seq, W, K)
+    gmap.close()
+    elapsed_noev = run["elapsed"]
+    b_sem = 4  # int32 label
+    acc = account(run["per"][W:W + K], n_pts, b_sem, 8 + 4 * ncls)
+    dom, dom_gbs, dom_bytes = dominant(run["kern"], acc["kalg"], K)
+    P, valid, b_alg = acc["pairs"], acc["valid"], acc["b_alg"]
     ms_step = elapsed_noev / K * 1e3
 
     result = {
@@ -200,18 +323,36 @@ def main():
                    "first_timed_sweep": W},
         "voxel_updates_per_s": P / elapsed_noev,
         "valid_points_per_s": valid / elapsed_noev,
-        "ms_per_step_with_kernel_events": elapsed / K * 1e3,
+        "ms_per_step_with_kernel_events": run["elapsed_events"] / K * 1e3,
         "alg_bytes_per_step": b_alg / K,
         "path_roofline_frac": (b_alg / elapsed_noev / 1e9) / HBM_PEAK_GBS,
-        "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kern.items()},
+        "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in run["kern"].items()},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": kalg[dom] / K},
+                     "alg_bytes_per_launch": dom_bytes},
     }
 
     if not args.no_diff:
         result["fwd_bwd"] = diff_bench(sv, synth, torch, scene, reps=args.diff_reps)
         log(f"fwd+bwd {result['fwd_bwd']}")
+
+    if not args.no_open:
+        result["open_set"] = open_bench(sv, synth, torch)
+        log(f"open set {result['open_set']}")
+
+    if not args.no_batched:
+        result["batched"] = batched_bench(sv, synth, torch)
+        log(f"batched {result['batched']}")
+
+    if args.copy_calib:
+        n = args.copy_calib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calib_bytes"] = {"read": n * 4, "write": n * 4, "launches": 5}
+        del src, dst
 
     if not args.no_cpu:
         import oracle  # test infrastructure: the CPU baseline leg only

@@ -395,18 +395,29 @@ def primitive_embeddings(scene, prim, L, seed, t, noise=0.1):
     return to_bf16_bits(z)
 
 
-def batched_workload(seed=4, nmaps=32, n_lo=10_000, n_hi=130_000, closed_maps=16, K=20, L=256, beams=128):
+def batched_workload(seed=4, nmaps=32, n_lo=10_000, n_hi=130_000, closed_maps=16, K=20, L=256, beams=128,
+                     workers=1):
     """Many independent maps, one frame each: the first n_i rays (azimuth-major)
     of a 128-beam sweep of the street from a random trajectory pose, n_i uniform
     in [n_lo, n_hi].  Maps below `closed_maps` get int32 labels (K classes), the
     others bf16 embeddings of size L.  Returns a list of dicts (kind, frame)."""
     scene = StreetScene(seed=2, beams=beams)
     rng = _rng(seed, 9)
-    out = []
+    draws = []
     for i in range(nmaps):
         n = int(rng.integers(n_lo, n_hi + 1))
         t = int(rng.integers(0, 100))
-        sw = scene.sweep(t, nrays=n)
+        draws.append((t, n))
+    if workers > 1 and nmaps >= 4:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+
+        with cf.ProcessPoolExecutor(max_workers=min(workers, nmaps), mp_context=mp.get_context("fork")) as ex:
+            sweeps = list(ex.map(scene.sweep, *zip(*draws)))
+    else:
+        sweeps = [scene.sweep(t, nrays=n) for t, n in draws]
+    out = []
+    for i, ((t, n), sw) in enumerate(zip(draws, sweeps)):
         item = dict(points=sw["points"], pose=sw["pose"], n=n)
         if i < closed_maps:
             item.update(mode="closed", K=K, label=sw["label"])
@@ -465,6 +476,17 @@ class OpenRoomScene:
         target = np.array([c[0], c[1], 1.0])
         return pose_matrix(camera_rotation(target - pos), pos)
 
+    def frames(self, ts, workers=8):
+        """Several frames with embeddings, generated in worker processes."""
+        ts = list(ts)
+        if workers <= 1 or len(ts) < 2:
+            return [self.frame(t) for t in ts]
+        import concurrent.futures as cf
+        import multiprocessing as mp
+
+        with cf.ProcessPoolExecutor(max_workers=min(workers, len(ts)), mp_context=mp.get_context("fork")) as ex:
+            return list(ex.map(self.frame, ts))
+
     def frame(self, t, with_embeddings=True):
         pose = self.pose(t)
         R, o = pose[:3, :3], pose[:3, 3]
@@ -480,9 +502,18 @@ class OpenRoomScene:
         pts[~ok] = np.nan
         out = dict(points=pts, pose=pose, obj=obj.astype(np.int32))
         if with_embeddings:
+            # row blocks keep the temporaries small; the normal draws continue
+            # one stream across blocks, so the result equals one whole-frame draw
             rng = _rng(self.seed, 4, t)
-            z = self.proto[obj].astype(np.float32)
-            z += rng.standard_normal(z.shape, dtype=np.float32) * np.float32(self.noise)
-            z /= np.linalg.norm(z, axis=1, keepdims=True)
-            out["emb"] = to_bf16_bits(z)
+            proto = self.proto.astype(np.float32)
+            emb = np.empty((len(obj), self.L), np.uint16)
+            noise = np.float32(self.noise)
+            for b in range(0, len(obj), 8192):
+                z = proto[obj[b:b + 8192]]
+                n = rng.standard_normal(z.shape, dtype=np.float32)
+                n *= noise
+                z += n
+                z /= np.linalg.norm(z, axis=1, keepdims=True)
+                emb[b:b + 8192] = to_bf16_bits(z)
+            out["emb"] = emb
         return out
