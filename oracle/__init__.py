@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "slim_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-SEM_NONE, SEM_CLOSED, SEM_OPEN = 0, 1, 2
+SEM_NONE, SEM_CLOSED, SEM_OPEN, SEM_CLOSED_LAST, SEM_OPEN_LAST = 0, 1, 2, 3, 4
 IN_NONE, IN_LABEL_I32, IN_PROB_F32, IN_LOGIT_F32, IN_EMB_BF16, IN_EMB_F32 = range(6)
 
 GCC_FLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall"]
@@ -99,7 +99,8 @@ class OracleMap:
         self.sem_mode = sem_mode
         self.K = num_classes
         self.L = embed_dim
-        self.nsem = num_classes if sem_mode == SEM_CLOSED else (2 * embed_dim if sem_mode == SEM_OPEN else 0)
+        self.nsem = {SEM_CLOSED: num_classes, SEM_OPEN: 2 * embed_dim, SEM_CLOSED_LAST: 1,
+                     SEM_OPEN_LAST: embed_dim}.get(sem_mode, 0)
         self.maxsteps = self._L.om_maxsteps(self.h)
 
     def __del__(self):

@@ -36,7 +36,9 @@
 #include <string.h>
 
 /* ---- input kinds (values shared with the Python wrapper by convention) ---- */
-enum { OM_SEM_NONE = 0, OM_SEM_CLOSED = 1, OM_SEM_OPEN = 2 };
+/* CLOSED_LAST and OPEN_LAST: the non-Bayesian ablation of Sec. IV (SLIM-VDB*),
+ * where a voxel's semantics are those of its most recent measurement. */
+enum { OM_SEM_NONE = 0, OM_SEM_CLOSED = 1, OM_SEM_OPEN = 2, OM_SEM_CLOSED_LAST = 3, OM_SEM_OPEN_LAST = 4 };
 enum { OM_IN_NONE = 0, OM_IN_LABEL_I32 = 1, OM_IN_PROB_F32 = 2, OM_IN_LOGIT_F32 = 3,
        OM_IN_EMB_BF16 = 4, OM_IN_EMB_F32 = 5 };
 
@@ -46,7 +48,8 @@ enum { OM_IN_NONE = 0, OM_IN_LABEL_I32 = 1, OM_IN_PROB_F32 = 2, OM_IN_LOGIT_F32 
 typedef struct {
     /* parameters, as the float values the caller configured */
     float vs, tau, rmin, rmax;
-    int sem_mode, K, L, nsem; /* nsem: K (closed), 2L (open: m then beta), 0 */
+    int sem_mode, K, L, nsem; /* nsem: K (closed), 2L (open: m then beta), 1 (closed last: class),
+                                 L (open last: embedding), 0 */
     int maxsteps;
     /* voxel table: packed key -> record */
     uint64_t *hkey;
@@ -206,13 +209,18 @@ static int64_t voxel_get(omap *m, uint64_t k, int *created)
 omap *om_create(float vs, float tau, float rmin, float rmax, int sem_mode, int K, int L)
 {
     if (!(vs > 0.0f) || !(tau >= vs) || !(rmin >= 0.0f) || !(rmax > rmin)) return NULL;
-    if (sem_mode == OM_SEM_CLOSED && K < 1) return NULL;
-    if (sem_mode == OM_SEM_OPEN && L < 1) return NULL;
+    if ((sem_mode == OM_SEM_CLOSED || sem_mode == OM_SEM_CLOSED_LAST) && K < 1) return NULL;
+    if ((sem_mode == OM_SEM_OPEN || sem_mode == OM_SEM_OPEN_LAST) && L < 1) return NULL;
+    if (sem_mode < OM_SEM_NONE || sem_mode > OM_SEM_OPEN_LAST) return NULL;
     omap *m = (omap *)calloc(1, sizeof(omap));
     if (!m) return NULL;
     m->vs = vs; m->tau = tau; m->rmin = rmin; m->rmax = rmax;
     m->sem_mode = sem_mode; m->K = K; m->L = L;
-    m->nsem = sem_mode == OM_SEM_CLOSED ? K : (sem_mode == OM_SEM_OPEN ? 2 * L : 0);
+    m->nsem = sem_mode == OM_SEM_CLOSED        ? K
+              : sem_mode == OM_SEM_OPEN        ? 2 * L
+              : sem_mode == OM_SEM_CLOSED_LAST ? 1
+              : sem_mode == OM_SEM_OPEN_LAST   ? L
+                                               : 0;
     /* visit cap: the band is at most 2 tau long; a walk of that length crosses
      * at most 2 tau / vs planes per axis plus one; this bound is generous. */
     m->maxsteps = 3 * (int)ceil((2.0 * (double)tau) / (double)vs) + 4;
@@ -352,7 +360,7 @@ int om_ray_visits(float vs, float tau, const float o[3], const float p[3], int32
 
 static int label_ok(const omap *m, const void *sem, int kind, int64_t j)
 {
-    if (m->sem_mode == OM_SEM_CLOSED && kind == OM_IN_LABEL_I32) {
+    if ((m->sem_mode == OM_SEM_CLOSED || m->sem_mode == OM_SEM_CLOSED_LAST) && kind == OM_IN_LABEL_I32) {
         int32_t l = ((const int32_t *)sem)[j];
         return l >= 0 && l < m->K;
     }
@@ -430,7 +438,7 @@ static void sem_row(const omap *m, const void *sem, int kind, int64_t j, double 
             for (int i = 0; i < K; ++i) { out[i] = exp((double)l[i] - mx); s += out[i]; }
             for (int i = 0; i < K; ++i) out[i] /= s;
         }
-    } else if (m->sem_mode == OM_SEM_OPEN) {
+    } else if (m->sem_mode == OM_SEM_OPEN || m->sem_mode == OM_SEM_OPEN_LAST) {
         int L = m->L;
         if (kind == OM_IN_EMB_BF16) {
             const uint16_t *z = (const uint16_t *)sem + j * L;
@@ -440,6 +448,19 @@ static void sem_row(const omap *m, const void *sem, int kind, int64_t j, double 
             for (int d = 0; d < L; ++d) out[d] = (double)z[d];
         }
     }
+}
+
+/* The class a single measurement names (non-Bayesian mode): the label, or the
+ * first index of the largest given probability or logit.  Compared in the
+ * input's own binary32 values. */
+static int last_class(const omap *m, const void *sem, int kind, int64_t j)
+{
+    if (kind == OM_IN_LABEL_I32) return ((const int32_t *)sem)[j];
+    const float *row = (const float *)sem + j * m->K;
+    int best = 0;
+    for (int i = 1; i < m->K; ++i)
+        if (row[i] > row[best]) best = i;
+    return best;
 }
 
 typedef struct { uint64_t key; uint32_t pid; int64_t idx; } opair_ref;
@@ -471,6 +492,7 @@ int om_apply(omap *m, int64_t P, const int32_t *keys, const uint32_t *pid, const
 
     int nsem = m->nsem;
     int rowlen = m->sem_mode == OM_SEM_CLOSED ? m->K : (m->sem_mode == OM_SEM_OPEN ? m->L : 0);
+    int last = m->sem_mode == OM_SEM_CLOSED_LAST || m->sem_mode == OM_SEM_OPEN_LAST;
     int64_t rowcap = 0;
     double *rows = NULL;     /* rows of the current segment */
 
@@ -496,7 +518,14 @@ int om_apply(omap *m, int64_t P, const int32_t *keys, const uint32_t *pid, const
         m->D[r] = (W0 * m->D[r] + sum_t) / W1;
         m->W[r] = W1;
 
-        if (rowlen) {
+        if (last) {
+            /* the most recent measurement: pairs of a voxel are in point
+             * order, and a ray visits a voxel at most once */
+            int64_t j = ord[e - 1].pid;
+            double *st = m->sem + r * nsem;
+            if (m->sem_mode == OM_SEM_CLOSED_LAST) st[0] = (double)last_class(m, sem, kind, j);
+            else sem_row(m, sem, kind, j, st);
+        } else if (rowlen) {
             if (n > rowcap) {
                 free(rows);
                 rowcap = n;
@@ -592,7 +621,8 @@ static int cmp_ext(const void *a, const void *b)
 
 /* Writes every voxel with W > 0, ordered by its 8^3 leaf (x, then y, then z
  * of the leaf coordinate) and then by its position inside the leaf (x, y, z).
- * keys: M x 3; D, W: M; sem: M x nsem (class counts, or m then beta).
+ * keys: M x 3; D, W: M; sem: M x nsem (class counts; m then beta; the class
+ * index (closed last); the embedding (open last)).
  * Returns M; writes nothing if cap < M. */
 int64_t om_extract(const omap *m, int32_t *keys, double *D, double *W, double *sem, int64_t cap)
 {
