@@ -46,6 +46,11 @@ typedef int32_t slim_status;
 #define SLIM_SEM_NONE 0   /* geometry only: D and W */
 #define SLIM_SEM_CLOSED 1 /* K Dirichlet class counts per voxel (Sec. III-C) */
 #define SLIM_SEM_OPEN 2   /* L-dim NIG mean m and diagonal beta per voxel (Sec. III-D) */
+/* Non-Bayesian ablation (SLIM-VDB* of Sec. IV): a voxel keeps the semantics of
+ * its most recent measurement -- the observing point with the highest index in
+ * the latest frame that observed it.  D and W follow Eq. (1)-(2) as above. */
+#define SLIM_SEM_CLOSED_LAST 3 /* 1 float per voxel: the class index (label, or first argmax of the row) */
+#define SLIM_SEM_OPEN_LAST 4   /* L floats per voxel: the embedding */
 
 /* layout of the per-point semantic input of slim_integrate */
 #define SLIM_IN_NONE 0      /* no semantics (SLIM_SEM_NONE maps) */

@@ -68,6 +68,7 @@ struct FrameParams {
     int n;             // points
     int sem_kind;      // SLIM_IN_*
     int K, L, nsem;    // classes, embedding dim, floats of semantic state per voxel
+    int last;          // 1: non-Bayesian mode, a voxel keeps its most recent measurement
     const float *pts;  // n x 3, or NULL when the points come as ranges and directions
     const float *ranges, *dirs;  // n and n x 3: point = range * direction
     const void *sem;   // per-point semantics
@@ -149,10 +150,11 @@ struct BatchPlan {
     int nmaps;
     int walk_blocks;                 // total blocks of the walk kernel
     int ngroups;
-    int group_kind[8];               // leaf-kernel variant of each group
-    int group_begin[8], group_size[8];  // slice of the device subset array
+    int group_kind[16];                   // leaf-kernel variant of each group
+    int group_begin[16], group_size[16];  // slice of the device subset array
 };
 
+constexpr int kLeafKinds = 11;  // variants of the leaf kernel (leaf_kernel_kind)
 int leaf_kernel_kind(const FrameParams &fp);
 hipError_t launch_integrate_batched(const MapBatch &mb, const BatchPlan &plan, const LaunchShape &shape,
                                     hipStream_t s);

@@ -149,9 +149,9 @@ slim_status validate_config(const slim_map_config *c)
         return fail(SLIM_ERR_INVALID, "need 0 <= min_range < max_range < inf");
     if ((double)c->max_range / (double)c->voxel_size >= (double)(1 << 19))
         return fail(SLIM_ERR_INVALID, "max_range must be below 2^19 voxel sizes");
-    if (c->sem_mode == SLIM_SEM_CLOSED) {
+    if (c->sem_mode == SLIM_SEM_CLOSED || c->sem_mode == SLIM_SEM_CLOSED_LAST) {
         if (c->num_classes < 1 || c->num_classes > 256) return fail(SLIM_ERR_INVALID, "num_classes must be 1..256");
-    } else if (c->sem_mode == SLIM_SEM_OPEN) {
+    } else if (c->sem_mode == SLIM_SEM_OPEN || c->sem_mode == SLIM_SEM_OPEN_LAST) {
         if (c->embed_dim < 1 || c->embed_dim > 1024) return fail(SLIM_ERR_INVALID, "embed_dim must be 1..1024");
     } else if (c->sem_mode != SLIM_SEM_NONE) {
         return fail(SLIM_ERR_INVALID, "unknown sem_mode %d", c->sem_mode);
@@ -241,9 +241,11 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
 
     slim_map *m = new slim_map();
     m->cfg = *config;
-    m->nsem = config->sem_mode == SLIM_SEM_CLOSED ? config->num_classes
-              : config->sem_mode == SLIM_SEM_OPEN ? 2 * config->embed_dim
-                                                   : 0;
+    m->nsem = config->sem_mode == SLIM_SEM_CLOSED        ? config->num_classes
+              : config->sem_mode == SLIM_SEM_OPEN        ? 2 * config->embed_dim
+              : config->sem_mode == SLIM_SEM_CLOSED_LAST ? 1
+              : config->sem_mode == SLIM_SEM_OPEN_LAST   ? config->embed_dim
+                                                         : 0;
     m->maxsteps = max_steps(config->voxel_size, config->sdf_trunc);
     size_t cap = 1024;
     while (cap < 2 * (size_t)config->max_leaves) cap <<= 1;
@@ -321,11 +323,13 @@ slim_status make_frame(slim_map *m, const float *points, const float *ranges, co
     const slim_map_config &c = m->cfg;
     bool kind_ok = false;
     if (c.sem_mode == SLIM_SEM_NONE) kind_ok = kind == SLIM_IN_NONE;
-    if (c.sem_mode == SLIM_SEM_CLOSED)
-        kind_ok = kind == SLIM_IN_LABEL_I32 || kind == SLIM_IN_PROB_F32 || kind == SLIM_IN_LOGIT_F32;
-    if (c.sem_mode == SLIM_SEM_OPEN) kind_ok = kind == SLIM_IN_EMB_BF16 || kind == SLIM_IN_EMB_F32;
+    const bool closed = c.sem_mode == SLIM_SEM_CLOSED || c.sem_mode == SLIM_SEM_CLOSED_LAST;
+    const bool open = c.sem_mode == SLIM_SEM_OPEN || c.sem_mode == SLIM_SEM_OPEN_LAST;
+    const bool last = c.sem_mode == SLIM_SEM_CLOSED_LAST || c.sem_mode == SLIM_SEM_OPEN_LAST;
+    if (closed) kind_ok = kind == SLIM_IN_LABEL_I32 || kind == SLIM_IN_PROB_F32 || kind == SLIM_IN_LOGIT_F32;
+    if (open) kind_ok = kind == SLIM_IN_EMB_BF16 || kind == SLIM_IN_EMB_F32;
     if (!kind_ok) return fail(SLIM_ERR_INVALID, "semantic input kind %d does not match the map's mode", kind);
-    if (kind == SLIM_IN_LOGIT_F32 && c.num_classes > 64)
+    if (kind == SLIM_IN_LOGIT_F32 && !last && c.num_classes > 64)
         return fail(SLIM_ERR_UNSUPPORTED, "logit input supports at most 64 classes");
     if (kind != SLIM_IN_NONE && n > 0 && !sem) return fail(SLIM_ERR_INVALID, "semantic input is NULL");
     if (((uintptr_t)sem & (kind == SLIM_IN_EMB_BF16 ? 1u : 3u)) != 0)
@@ -348,8 +352,9 @@ slim_status make_frame(slim_map *m, const float *points, const float *ranges, co
     fp->maxsteps = m->maxsteps;
     fp->n = (int)n;
     fp->sem_kind = kind;
-    fp->K = c.sem_mode == SLIM_SEM_CLOSED ? c.num_classes : 0;
-    fp->L = c.sem_mode == SLIM_SEM_OPEN ? c.embed_dim : 0;
+    fp->K = closed ? c.num_classes : 0;
+    fp->L = open ? c.embed_dim : 0;
+    fp->last = last ? 1 : 0;
     fp->nsem = m->nsem;
     fp->pts = points;
     fp->ranges = points ? nullptr : ranges;
@@ -618,7 +623,8 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
     }
     plan.walk_blocks = start[nmaps];
     // group the maps by leaf-kernel variant
-    for (int kind = 0; kind <= 8; ++kind) {
+    static_assert(kLeafKinds <= (int)(sizeof(plan.group_kind) / sizeof(int)), "group arrays too small");
+    for (int kind = 0; kind < kLeafKinds; ++kind) {
         const int begin = (int)subset.size();
         for (int i = 0; i < nmaps; ++i)
             if (kinds[i] == kind) subset.push_back(i);

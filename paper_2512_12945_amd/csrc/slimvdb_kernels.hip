@@ -755,6 +755,60 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
     }
 }
 
+// Non-Bayesian mode (SLIM-VDB*, Sec. IV): D and W as Eq. (1)-(2); the voxel's
+// semantics become those of its most recent measurement, the last pair in point
+// order (a ray visits a voxel at most once, so point indices are distinct).
+__device__ __forceinline__ float last_sum_tsdf(const float *vals, uint32_t n)
+{
+    float sum_t = 0.0f;
+    for (uint32_t q = 0; q < n; ++q) sum_t += vals[q];
+    return sum_t;
+}
+
+// Closed set, one lane per voxel: the class the measurement names -- its label,
+// or the first index of the largest probability or logit of its row.
+__device__ __forceinline__ void combine_last_lane(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
+                                                  const float *vals, uint32_t n, long long rec, bool existed)
+{
+    const uint32_t pid = keys[n - 1] & kPidMask;
+    int cls;
+    if (fp.sem_kind == SLIM_IN_LABEL_I32) {
+        cls = ((const int32_t *)fp.sem)[pid];
+    } else {
+        const float *row = (const float *)fp.sem + (size_t)pid * fp.K;
+        float best = row[0];
+        cls = 0;
+        for (int k = 1; k < fp.K; ++k) {
+            const float x = row[k];
+            if (x > best) {
+                best = x;
+                cls = k;
+            }
+        }
+    }
+    const float sum_t = last_sum_tsdf(vals, n);
+    float4 *R = (float4 *)(md.vox + (size_t)rec * md.rec_stride);
+    const float4 r = existed ? R[0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float nf = (float)n, W1 = r.y + nf;
+    R[0] = make_float4((r.y * r.x + sum_t) / W1, W1, (float)cls, 0.0f);
+}
+
+// Open set, one wave per voxel: lane l copies components l, l + 64, ... of the
+// measurement's embedding.
+__device__ __forceinline__ void combine_last_wave(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
+                                                  const float *vals, uint32_t n, long long rec, bool existed)
+{
+    const uint32_t pid = keys[n - 1] & kPidMask;
+    float *R = md.vox + (size_t)rec * md.rec_stride;
+    for (int comp = lane_id(); comp < fp.L; comp += 64) R[2 + comp] = load_emb(fp, pid, comp);
+    if (lane_id() == 0) {
+        const float sum_t = last_sum_tsdf(vals, n);
+        const float W0 = existed ? R[1] : 0.0f, D0 = existed ? R[0] : 0.0f, W1 = W0 + (float)n;
+        R[0] = (W0 * D0 + sum_t) / W1;
+        R[1] = W1;
+    }
+}
+
 // Combines every touched voxel with offset in [o0, o1); the sorted pairs of
 // bin o sit at keys[bin0[o] - base] / vals[bin0[o] - base] (LDS or global).
 template <int KMAX, bool WAVE, bool ROWS>
@@ -767,8 +821,11 @@ __device__ void combine_range(const FrameParams &fp, const MapDev &md, LeafShare
             if (!n) continue;
             const long long rec = (long long)sh.pages[o >> 6] * kPageVoxels + (o & (kPageVoxels - 1));
             const bool existed = (sh.occ0[o >> 5] >> (o & 31)) & 1u;
-            combine_lane<KMAX, ROWS>(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base), n, rec,
-                                     existed);
+            if (KMAX < 0)
+                combine_last_lane(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base), n, rec, existed);
+            else
+                combine_lane<(KMAX < 0 ? 0 : KMAX), ROWS>(fp, md, keys + (sh.bin0[o] - base),
+                                                          vals + (sh.bin0[o] - base), n, rec, existed);
         }
     } else {
         const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -777,7 +834,10 @@ __device__ void combine_range(const FrameParams &fp, const MapDev &md, LeafShare
             if (!n) continue;
             const long long rec = (long long)sh.pages[o >> 6] * kPageVoxels + (o & (kPageVoxels - 1));
             const bool existed = (sh.occ0[o >> 5] >> (o & 31)) & 1u;
-            combine_wave(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base), n, rec, existed);
+            if (KMAX < 0)
+                combine_last_wave(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base), n, rec, existed);
+            else
+                combine_wave(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base), n, rec, existed);
         }
     }
 }
@@ -1067,9 +1127,11 @@ __global__ __launch_bounds__(256) void k_frame_commit_batch(MapBatch mb)
 
 // Variant of the leaf kernel a frame needs: 0 geometry; 1..4 labels with
 // 8/16/24/32 classes in registers; 5..7 probability or logit rows with 8/16/32;
-// 8 one wave per voxel (open set, or more than 32 classes).
+// 8 one wave per voxel (open set, or more than 32 classes); 9 and 10 the
+// most-recent-measurement modes (closed: lane per voxel; open: wave per voxel).
 int leaf_kernel_kind(const FrameParams &fp)
 {
+    if (fp.last) return fp.L > 0 ? 10 : 9;
     if (fp.L > 0 || fp.K > 32) return 8;
     if (fp.K == 0) return 0;
     const bool rows = fp.sem_kind == SLIM_IN_PROB_F32 || fp.sem_kind == SLIM_IN_LOGIT_F32;
@@ -1089,6 +1151,8 @@ static void launch_leaf(int kind, const FrameParams &fp, const MapDev &md, int b
     case 5: hipLaunchKernelGGL((k_leaf_fuse<8, false, true>), gl, bl, 0, s, fp, md); break;
     case 6: hipLaunchKernelGGL((k_leaf_fuse<16, false, true>), gl, bl, 0, s, fp, md); break;
     case 7: hipLaunchKernelGGL((k_leaf_fuse<32, false, true>), gl, bl, 0, s, fp, md); break;
+    case 9: hipLaunchKernelGGL((k_leaf_fuse<-1, false, false>), gl, bl, 0, s, fp, md); break;
+    case 10: hipLaunchKernelGGL((k_leaf_fuse<-1, true, false>), gl, bl, 0, s, fp, md); break;
     default: hipLaunchKernelGGL((k_leaf_fuse<0, true, false>), gl, bl, 0, s, fp, md); break;
     }
 }
@@ -1105,6 +1169,8 @@ static void launch_leaf_batch(int kind, const MapBatch &mb, int blocks, hipStrea
     case 5: hipLaunchKernelGGL((k_leaf_fuse_batch<8, false, true>), gl, bl, 0, s, mb); break;
     case 6: hipLaunchKernelGGL((k_leaf_fuse_batch<16, false, true>), gl, bl, 0, s, mb); break;
     case 7: hipLaunchKernelGGL((k_leaf_fuse_batch<32, false, true>), gl, bl, 0, s, mb); break;
+    case 9: hipLaunchKernelGGL((k_leaf_fuse_batch<-1, false, false>), gl, bl, 0, s, mb); break;
+    case 10: hipLaunchKernelGGL((k_leaf_fuse_batch<-1, true, false>), gl, bl, 0, s, mb); break;
     default: hipLaunchKernelGGL((k_leaf_fuse_batch<0, true, false>), gl, bl, 0, s, mb); break;
     }
 }

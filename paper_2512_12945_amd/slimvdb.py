@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libslimvdb.so")
 
 OK, ERR_INVALID, ERR_CAPACITY, ERR_DEVICE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4
-SEM_NONE, SEM_CLOSED, SEM_OPEN = 0, 1, 2
+SEM_NONE, SEM_CLOSED, SEM_OPEN, SEM_CLOSED_LAST, SEM_OPEN_LAST = 0, 1, 2, 3, 4
 IN_NONE, IN_LABEL_I32, IN_PROB_F32, IN_LOGIT_F32, IN_EMB_BF16, IN_EMB_F32 = range(6)
 KERNELS = ("ray_walk_emit", "leaf_plan", "pair_bucket", "leaf_fuse", "frame_commit")
 
@@ -116,7 +116,8 @@ class Map:
         self.cfg = MapConfig(voxel_size, sdf_trunc, min_range, max_range, sem_mode, num_classes, embed_dim, device,
                              max_leaves, max_voxels)
         self.sem_mode = sem_mode
-        self.nsem = num_classes if sem_mode == SEM_CLOSED else (2 * embed_dim if sem_mode == SEM_OPEN else 0)
+        self.nsem = {SEM_CLOSED: num_classes, SEM_OPEN: 2 * embed_dim, SEM_CLOSED_LAST: 1,
+                     SEM_OPEN_LAST: embed_dim}.get(sem_mode, 0)
         h = ctypes.c_void_p()
         _check(self._L.slim_map_create(ctypes.byref(self.cfg), ctypes.byref(h)))
         self.h = h

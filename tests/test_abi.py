@@ -48,6 +48,9 @@ def _cfg(**kw):
     (dict(max_range=0.0), sv.ERR_INVALID),
     (dict(max_range=1e6), sv.ERR_INVALID),
     (dict(sem_mode=7), sv.ERR_INVALID),
+    (dict(sem_mode=5), sv.ERR_INVALID),
+    (dict(sem_mode=sv.SEM_CLOSED_LAST, num_classes=0), sv.ERR_INVALID),
+    (dict(sem_mode=sv.SEM_OPEN_LAST, embed_dim=0), sv.ERR_INVALID),
     (dict(num_classes=0), sv.ERR_INVALID),
     (dict(num_classes=257), sv.ERR_INVALID),
     (dict(sem_mode=sv.SEM_OPEN, embed_dim=0), sv.ERR_INVALID),
