@@ -136,7 +136,8 @@ slim_status slim_map_stats(slim_map *map, slim_stats *out_host, void *stream);
  * the count is returned.  Otherwise capacity must be >= M, and the call
  * writes keys_dev (int32 [M x 3] voxel coordinates), d_dev and w_dev (float
  * [M] TSDF and weight) and, unless NULL, sem_dev (float [M x S]: the K class
- * counts, or the L means followed by the L betas; S = 0 for geometry-only
+ * counts, or the L means followed by the L betas; for the most-recent modes
+ * the class index (S = 1) or the embedding (S = L); S = 0 for geometry-only
  * maps).  Counts c are stored without prior: the Dirichlet posterior is
  * alpha0 + c and its predictive is (alpha0 + c_i) / (K alpha0 + sum c)
  * (Eq. (7)).  Any async error pending on the map is returned first. */
