@@ -151,6 +151,32 @@ slim_status slim_extract(slim_map *map, int64_t capacity, int32_t *keys_dev, flo
 slim_status slim_query(slim_map *map, const float *xyz_dev, int64_t m, float *d_dev, float *w_dev, float *sem_dev,
                        void *stream);
 
+/* Parameters of slim_predict (host struct; the prototypes live on the device). */
+typedef struct slim_predict_params {
+    float alpha0;                /* closed set: symmetric Dirichlet prior added to the counts, > 0 */
+    float temperature;           /* open set: softmax temperature over cosine similarities, > 0 */
+    float threshold;             /* largest class probability below this -> label -1 (T_p, Sec. III-D) */
+    int32_t num_prototypes;      /* open set: class prototypes, 1..1024 */
+    const float *prototypes_dev; /* open set: float [num_prototypes x L] row-major */
+} slim_predict_params;
+
+/* Semantic read-out at m world points xyz_dev (float [m x 3]), one voxel each
+ * (floor(x / voxel_size), binary32).  Closed set: prob_dev (float [m x K],
+ * unless NULL) receives the Dirichlet predictive (alpha0 + c_i) /
+ * (K alpha0 + sum c) of Eq. (7) -- the prior's 1/K for unobserved voxels.
+ * Open set: prob_dev (float [m x num_prototypes], unless NULL) receives the
+ * softmax over cos(mean, prototype_j) / temperature (0 for unobserved
+ * voxels), the mean being the location of the Student-t predictive of
+ * Eq. (15); var_dev (float [m x L], unless NULL) receives that Student-t's
+ * variance with lambda = 2 nu = W, 2 beta (W + 1) / (W (W - 2)), NaN for
+ * W <= 2.  label_dev (int32 [m], unless NULL): the first index of the largest
+ * probability, or -1 if the voxel is unobserved or that probability is below
+ * threshold.  Most-recent modes: closed -> the stored class, one-hot; open ->
+ * the prototype softmax of the stored embedding; var_dev must be NULL.
+ * Geometry-only maps: SLIM_ERR_UNSUPPORTED.  Queued on `stream`. */
+slim_status slim_predict(slim_map *map, const float *xyz_dev, int64_t m, const slim_predict_params *params,
+                         float *prob_dev, int32_t *label_dev, float *var_dev, void *stream);
+
 /* As slim_integrate, with each point given as a range along a direction:
  * point i is ranges_dev[i] * dirs_dev[3 i .. 3 i + 2] (one binary32 product per
  * component; dirs are unit vectors in the sensor frame).  A non-finite range

@@ -177,6 +177,15 @@ constexpr int kLossThreads = 256;
 hipError_t launch_extract(const MapDev &md, int nsem, long long nleaves, unsigned long long *tmp_keys,
                           int32_t *tmp_slots, uint32_t *tmp_offsets, int32_t *keys, float *d, float *w, float *sem,
                           hipStream_t s);
+// Semantic read-out (slim_predict).
+struct PredictParams {
+    float vs, alpha0, inv_temp, threshold;
+    int mode;               // SLIM_SEM_*
+    int K, L, P;            // classes, embedding dim, prototypes
+    const float *protos;    // P x L
+};
+hipError_t launch_predict(const MapDev &md, const PredictParams &pp, const float *xyz, long long m, float *prob,
+                          int32_t *label, float *var, hipStream_t s);
 hipError_t launch_query(const MapDev &md, int nsem, float vs, const float *xyz, long long m, float *d, float *w,
                         float *sem, hipStream_t s);
 

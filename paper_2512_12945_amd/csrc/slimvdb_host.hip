@@ -497,6 +497,43 @@ slim_status slim_query(slim_map *m, const float *xyz, int64_t mq, float *d, floa
     return SLIM_OK;
 }
 
+slim_status slim_predict(slim_map *m, const float *xyz, int64_t mq, const slim_predict_params *params, float *prob,
+                         int32_t *label, float *var, void *stream)
+{
+    g_err[0] = 0;
+    if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
+    if (!params) return fail(SLIM_ERR_INVALID, "params is NULL");
+    if (mq < 0) return fail(SLIM_ERR_INVALID, "m must be >= 0");
+    if (mq > 0 && !xyz) return fail(SLIM_ERR_INVALID, "xyz is NULL");
+    const int mode = m->cfg.sem_mode;
+    if (mode == SLIM_SEM_NONE) return fail(SLIM_ERR_UNSUPPORTED, "a geometry-only map has no semantics");
+    const bool open = mode == SLIM_SEM_OPEN || mode == SLIM_SEM_OPEN_LAST;
+    if (!std::isfinite(params->threshold)) return fail(SLIM_ERR_INVALID, "threshold must be finite");
+    if (mode == SLIM_SEM_CLOSED && !(params->alpha0 > 0.0f && std::isfinite(params->alpha0)))
+        return fail(SLIM_ERR_INVALID, "alpha0 must be finite and > 0");
+    if (open) {
+        if (!(params->temperature > 0.0f && std::isfinite(params->temperature)))
+            return fail(SLIM_ERR_INVALID, "temperature must be finite and > 0");
+        if (params->num_prototypes < 1 || params->num_prototypes > 1024)
+            return fail(SLIM_ERR_INVALID, "num_prototypes must be 1..1024");
+        if (!params->prototypes_dev) return fail(SLIM_ERR_INVALID, "prototypes are NULL");
+    }
+    if (var && mode != SLIM_SEM_OPEN) return fail(SLIM_ERR_UNSUPPORTED, "variances exist for open-set maps only");
+    DeviceGuard g(m->cfg.device);
+    PredictParams pp = {};
+    pp.vs = m->cfg.voxel_size;
+    pp.alpha0 = params->alpha0;
+    pp.inv_temp = open ? 1.0f / params->temperature : 0.0f;
+    pp.threshold = params->threshold;
+    pp.mode = mode;
+    pp.K = open ? 0 : m->cfg.num_classes;
+    pp.L = open ? m->cfg.embed_dim : 0;
+    pp.P = open ? params->num_prototypes : 0;
+    pp.protos = open ? params->prototypes_dev : nullptr;
+    HIP_OK(launch_predict(m->md, pp, xyz, mq, prob, label, var, (hipStream_t)stream));
+    return SLIM_OK;
+}
+
 slim_status slim_map_loss(slim_map *m, const int32_t *keys, const int32_t *labels, int64_t mv, const float *samples,
                           int64_t ns, float alpha0, float *loss, void *stream)
 {

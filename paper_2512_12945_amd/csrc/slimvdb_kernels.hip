@@ -1594,27 +1594,28 @@ hipError_t launch_extract(const MapDev &md, int nsem, long long nleaves, unsigne
     return hipGetLastError();
 }
 
+// Record of the voxel holding world point (x, y, z), floor(x / vs) in binary32;
+// -1 if unobserved, non-finite or out of the key range.
+__device__ __forceinline__ long long lookup_point(const MapDev &md, float vs, float x, float y, float z)
+{
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) return -1;
+    const float fx = floorf(x / vs), fy = floorf(y / vs), fz = floorf(z / vs);
+    const float lim = (float)kKeyLimit;
+    if (!(fabsf(fx) < lim && fabsf(fy) < lim && fabsf(fz) < lim)) return -1;
+    const int kx = (int)fx, ky = (int)fy, kz = (int)fz;
+    const int slot = map_find(md, pack_leaf(kx >> 3, ky >> 3, kz >> 3));
+    if (slot < 0) return -1;
+    const int off = ((kx & 7) << 6) | ((ky & 7) << 3) | (kz & 7);
+    if (!((md.leaf_occ[(size_t)slot * kMaskWords + (off >> 5)] >> (off & 31)) & 1u)) return -1;
+    return (long long)md.leaf_page[(size_t)slot * kLeafPages + (off >> 6)] * kPageVoxels + (off & (kPageVoxels - 1));
+}
+
 __global__ __launch_bounds__(256) void k_query(const MapDev md, int nsem, float vs, const float *xyz, long long m,
                                                float *d, float *w, float *sem)
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < m;
          i += (long long)gridDim.x * blockDim.x) {
-        long long rec = -1;
-        const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-        if (isfinite(x) && isfinite(y) && isfinite(z)) {
-            const float fx = floorf(x / vs), fy = floorf(y / vs), fz = floorf(z / vs);
-            const float lim = (float)kKeyLimit;
-            if (fabsf(fx) < lim && fabsf(fy) < lim && fabsf(fz) < lim) {
-                const int kx = (int)fx, ky = (int)fy, kz = (int)fz;
-                const int slot = map_find(md, pack_leaf(kx >> 3, ky >> 3, kz >> 3));
-                if (slot >= 0) {
-                    const int off = ((kx & 7) << 6) | ((ky & 7) << 3) | (kz & 7);
-                    if ((md.leaf_occ[(size_t)slot * kMaskWords + (off >> 5)] >> (off & 31)) & 1u)
-                        rec = (long long)md.leaf_page[(size_t)slot * kLeafPages + (off >> 6)] * kPageVoxels +
-                              (off & (kPageVoxels - 1));
-                }
-            }
-        }
+        const long long rec = lookup_point(md, vs, xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]);
         if (rec >= 0) {
             const float *R = md.vox + (size_t)rec * md.rec_stride;
             d[i] = R[0];
@@ -1636,6 +1637,119 @@ hipError_t launch_query(const MapDev &md, int nsem, float vs, const float *xyz, 
     if (m <= 0) return hipGetLastError();
     const int blocks = (int)std::min<long long>((m + 255) / 256, 4096);
     hipLaunchKernelGGL(k_query, dim3(blocks), dim3(256), 0, s, md, nsem, vs, xyz, m, d, w, sem);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// semantic read-out: Eq. (7), Eq. (15), prototype softmax and threshold
+// ---------------------------------------------------------------------------
+
+constexpr int kPredictMaxC = 1024;  // classes or prototypes
+
+// First index of the largest value across the wave: (v, i) pairs, larger v
+// wins, equal v the smaller i.
+__device__ __forceinline__ void wave_argmax(float &v, int &i)
+{
+    for (int d = 32; d > 0; d >>= 1) {
+        const float ov = __shfl_xor(v, d, 64);
+        const int oi = __shfl_xor(i, d, 64);
+        if (ov > v || (ov == v && oi < i)) {
+            v = ov;
+            i = oi;
+        }
+    }
+}
+
+// One wave per query point.  sims: per-wave LDS row of similarities (open set).
+__global__ __launch_bounds__(256) void k_predict(const MapDev md, const PredictParams pp, const float *xyz,
+                                                 long long m, float *prob, int32_t *label, float *var)
+{
+    __shared__ float sims[4][kPredictMaxC];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const long long nwaves = (long long)gridDim.x * (blockDim.x >> 6);
+    const bool open = pp.mode == SLIM_SEM_OPEN || pp.mode == SLIM_SEM_OPEN_LAST;
+    for (long long q = blockIdx.x * (long long)(blockDim.x >> 6) + wv; q < m; q += nwaves) {
+        const long long rec = lookup_point(md, pp.vs, xyz[3 * q], xyz[3 * q + 1], xyz[3 * q + 2]);
+        const float *R = rec >= 0 ? md.vox + (size_t)rec * md.rec_stride : nullptr;
+        float best = -INFINITY;
+        int arg = 0x7FFFFFFF;
+        if (pp.mode == SLIM_SEM_CLOSED) {
+            // Eq. (7): the Dirichlet predictive
+            float part = 0.0f;
+            for (int k = lane; k < pp.K; k += 64) part += R ? R[2 + k] : 0.0f;
+            const float den = (float)pp.K * pp.alpha0 + wave_sum(part);
+            for (int k = lane; k < pp.K; k += 64) {
+                const float p = (pp.alpha0 + (R ? R[2 + k] : 0.0f)) / den;
+                if (prob) prob[q * pp.K + k] = p;
+                if (p > best) {
+                    best = p;
+                    arg = k;
+                }
+            }
+        } else if (pp.mode == SLIM_SEM_CLOSED_LAST) {
+            const int cls = R ? (int)R[2] : -1;
+            for (int k = lane; k < pp.K; k += 64) {
+                const float p = k == cls ? 1.0f : 0.0f;
+                if (prob) prob[q * pp.K + k] = p;
+                if (p > best) {
+                    best = p;
+                    arg = k;
+                }
+            }
+        } else if (open && R) {
+            // cosine similarity of the predictive mean with every prototype
+            float n2 = 0.0f;
+            for (int d = lane; d < pp.L; d += 64) n2 += R[2 + d] * R[2 + d];
+            const float nm = sqrtf(wave_sum(n2));
+            for (int j = 0; j < pp.P; ++j) {
+                const float *Q = pp.protos + (size_t)j * pp.L;
+                float dot = 0.0f, q2 = 0.0f;
+                for (int d = lane; d < pp.L; d += 64) {
+                    const float qd = Q[d];
+                    dot += R[2 + d] * qd;
+                    q2 += qd * qd;
+                }
+                dot = wave_sum(dot);
+                q2 = wave_sum(q2);
+                if (lane == 0) sims[wv][j] = dot / (nm * sqrtf(q2)) * pp.inv_temp;
+            }
+            __builtin_amdgcn_wave_barrier();
+            float mx = -INFINITY;
+            for (int j = lane; j < pp.P; j += 64) mx = fmaxf(mx, sims[wv][j]);
+            mx = wave_max(mx);
+            float es = 0.0f;
+            for (int j = lane; j < pp.P; j += 64) es += expf(sims[wv][j] - mx);
+            const float den = wave_sum(es);
+            for (int j = lane; j < pp.P; j += 64) {
+                const float p = expf(sims[wv][j] - mx) / den;
+                if (prob) prob[q * pp.P + j] = p;
+                if (p > best) {
+                    best = p;
+                    arg = j;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        } else if (open) {
+            for (int j = lane; j < pp.P; j += 64)
+                if (prob) prob[q * pp.P + j] = 0.0f;
+        }
+        if (var && pp.mode == SLIM_SEM_OPEN) {
+            // Eq. (15) with lambda = 2 nu = W: variance 2 beta (W + 1) / (W (W - 2)) for W > 2
+            const float W = R ? R[1] : 0.0f;
+            for (int d = lane; d < pp.L; d += 64)
+                var[q * pp.L + d] = W > 2.0f ? 2.0f * R[2 + pp.L + d] * (W + 1.0f) / (W * (W - 2.0f)) : NAN;
+        }
+        wave_argmax(best, arg);
+        if (label && lane == 0) label[q] = (R && best >= pp.threshold) ? arg : -1;
+    }
+}
+
+hipError_t launch_predict(const MapDev &md, const PredictParams &pp, const float *xyz, long long m, float *prob,
+                          int32_t *label, float *var, hipStream_t s)
+{
+    if (m <= 0) return hipGetLastError();
+    const int blocks = (int)std::min<long long>((m + 3) / 4, 65536);
+    hipLaunchKernelGGL(k_predict, dim3(blocks), dim3(256), 0, s, md, pp, xyz, m, prob, label, var);
     return hipGetLastError();
 }
 

@@ -21,9 +21,14 @@ IN_NONE, IN_LABEL_I32, IN_PROB_F32, IN_LOGIT_F32, IN_EMB_BF16, IN_EMB_F32 = rang
 KERNELS = ("ray_walk_emit", "leaf_plan", "pair_bucket", "leaf_fuse", "frame_commit")
 
 EXPORTS = ("slim_map_create", "slim_map_destroy", "slim_map_reset", "slim_integrate", "slim_integrate_rays",
-           "slim_map_stats", "slim_extract", "slim_query", "slim_map_loss", "slim_backward_rays",
+           "slim_map_stats", "slim_extract", "slim_query", "slim_predict", "slim_map_loss", "slim_backward_rays",
            "slim_integrate_batched", "slim_set_launch_shape", "slim_profile_enable", "slim_profile_read",
            "slim_last_error")
+
+
+class PredictParams(ctypes.Structure):
+    _fields_ = [("alpha0", ctypes.c_float), ("temperature", ctypes.c_float), ("threshold", ctypes.c_float),
+                ("num_prototypes", ctypes.c_int32), ("prototypes_dev", ctypes.c_void_p)]
 
 
 class MapConfig(ctypes.Structure):
@@ -82,6 +87,7 @@ def load(path: str = LIB_PATH):
         L.slim_map_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
         L.slim_extract.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
         L.slim_query.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+        L.slim_predict.argtypes = [vp, vp, i64, ctypes.POINTER(PredictParams), vp, vp, vp, vp]
         L.slim_integrate_batched.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Frame), i32, vp]
         L.slim_set_launch_shape.argtypes = [vp, ctypes.POINTER(LaunchShape)]
         L.slim_profile_enable.argtypes = [vp, i32]
@@ -155,6 +161,22 @@ class Map:
         _check(self._L.slim_map_loss(self.h, _ptr(keys), _ptr(labels), keys.shape[0], _ptr(samples),
                                      samples.shape[0], float(alpha0), _ptr(out), _stream(self.device)))
         return out
+
+    def predict(self, xyz, alpha0=1.0, temperature=1.0, threshold=0.0, prototypes=None, prob=True, var=False):
+        """Semantic read-out at world points xyz (m, 3) (see slim_predict in include/slimvdb.h): returns
+        dict(prob=(m, C) or None, label=(m,) int32, var=(m, L) or None) as cuda tensors."""
+        m = xyz.shape[0]
+        open_set = self.cfg.sem_mode in (SEM_OPEN, SEM_OPEN_LAST)
+        C = prototypes.shape[0] if open_set else self.cfg.num_classes
+        pp = PredictParams(alpha0, temperature, threshold, C if open_set else 0,
+                           _ptr(prototypes) if open_set else None)
+        out_p = torch.empty((max(m, 1), C), dtype=torch.float32, device=self.device) if prob else None
+        out_l = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
+        out_v = torch.empty((max(m, 1), self.cfg.embed_dim), dtype=torch.float32, device=self.device) if var else None
+        _check(self._L.slim_predict(self.h, _ptr(xyz), m, ctypes.byref(pp), _ptr(out_p), _ptr(out_l), _ptr(out_v),
+                                    _stream(self.device)))
+        return dict(prob=None if out_p is None else out_p[:m], label=out_l[:m],
+                    var=None if out_v is None else out_v[:m])
 
     def backward_rays(self, ranges, dirs, pose, logits, grad_logits, grad_ranges, grad_scale=None):
         self._pose[:] = np.asarray(pose, np.float64).reshape(16)
