@@ -57,6 +57,8 @@ def lib():
         L.om_frame_pairs.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, vp, i64, vp]
         L.om_frame_pairs.restype = i64
         L.om_apply.argtypes = [vp, i64, vp, vp, vp, vp, i32, i32]
+        L.om_depth_points.argtypes = [vp, i32, i32, f32, f32, f32, f32, vp]
+        L.om_depth_points.restype = None
         L.om_apply.restype = i32
         L.om_integrate.argtypes = [vp, vp, i64, vp, vp, i32, i32]
         L.om_integrate.restype = i32
@@ -164,6 +166,16 @@ class OracleMap:
         sem = np.zeros((max(M, 1), max(self.nsem, 1)), np.float64)
         self._L.om_extract(self.h, _ptr(keys), _ptr(D), _ptr(W), _ptr(sem) if self.nsem else None, M)
         return dict(keys=keys[:M], D=D[:M], W=W[:M], sem=sem[:M, : self.nsem])
+
+
+def depth_points(depth, fx, fy, cx, cy):
+    """Sensor-frame points (H*W, 3) of a depth image (H, W), binary32 back-projection."""
+    d = np.ascontiguousarray(depth, dtype=np.float32)
+    H, W = d.shape
+    pts = np.zeros((H * W, 3), np.float32)
+    lib().om_depth_points(_ptr(d), W, H, ctypes.c_float(fx), ctypes.c_float(fy), ctypes.c_float(cx),
+                          ctypes.c_float(cy), _ptr(pts))
+    return pts
 
 
 def ray_visits(voxel_size, sdf_trunc, origin, point, cap=4096):

@@ -367,6 +367,31 @@ static int label_ok(const omap *m, const void *sem, int kind, int64_t j)
     return 1;
 }
 
+/* Back-projects a depth image (row-major height x width, metres along the
+ * optical axis) through pinhole intrinsics into sensor-frame points, point
+ * i = v * width + u: x = ((u - cx) / fx) d, y = ((v - cy) / fy) d, z = d, each
+ * operation rounded to binary32 in that order (the RGB-D input of Sec. III-A,
+ * an image turned into points).  A depth that is not finite and > 0 gives a NaN
+ * point, which integration rejects. */
+void om_depth_points(const float *depth, int width, int height, float fx, float fy, float cx, float cy,
+                     float *pts)
+{
+    for (int v = 0; v < height; ++v)
+        for (int u = 0; u < width; ++u) {
+            int64_t i = (int64_t)v * width + u;
+            float d = depth[i];
+            float *p = pts + 3 * i;
+            if (!(d > 0.0f) || !isfinite(d)) {
+                p[0] = p[1] = p[2] = NAN;
+                continue;
+            }
+            float xr = ((float)u - cx) / fx, yr = ((float)v - cy) / fy;
+            p[0] = xr * d;
+            p[1] = yr * d;
+            p[2] = d;
+        }
+}
+
 /* Enumerates the observation pairs of one frame: every (voxel, point) where
  * the voxel lies on the point's band walk and passes the gate sdf > -tau.
  * keys: P x 3 absolute voxel coordinates; pid: point index; tsdf: min(sdf,
