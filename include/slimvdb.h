@@ -125,6 +125,17 @@ slim_status slim_map_reset(slim_map *map, void *stream);
 slim_status slim_integrate(slim_map *map, const float *points_dev, int64_t n, const double *pose_host,
                            const void *sem_dev, int32_t sem_kind, void *stream);
 
+/* As slim_integrate, with the points back-projected from a depth image (the
+ * RGB-D input of Sec. III-A): depth_dev is float [height x width] row-major,
+ * metres along the optical axis; intrinsics_host = {fx, fy, cx, cy}.  Pixel
+ * (u, v) is point i = v * width + u at (((u - cx) / fx) d, ((v - cy) / fy) d,
+ * d), each operation rounded to binary32 in that order; a depth that is not
+ * finite and positive rejects the pixel.  sem_dev holds one row per pixel in
+ * the same order.  Requires width * height < 2^23. */
+slim_status slim_integrate_depth(slim_map *map, const float *depth_dev, int32_t width, int32_t height,
+                                 const float *intrinsics_host, const double *pose_host, const void *sem_dev,
+                                 int32_t sem_kind, void *stream);
+
 /* Synchronises `stream` and copies the map's counters to *out_host.  Returns
  * the first asynchronous error since the previous call (then cleared), else
  * SLIM_OK. */

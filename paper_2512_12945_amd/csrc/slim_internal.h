@@ -71,6 +71,9 @@ struct FrameParams {
     int last;          // 1: non-Bayesian mode, a voxel keeps its most recent measurement
     const float *pts;  // n x 3, or NULL when the points come as ranges and directions
     const float *ranges, *dirs;  // n and n x 3: point = range * direction
+    const float *depth;          // or a row-major depth image, n = width * height pixels
+    int width;
+    float fx, fy, cx, cy;        // pinhole intrinsics of the depth image
     const void *sem;   // per-point semantics
 };
 

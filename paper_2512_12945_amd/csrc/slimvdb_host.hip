@@ -359,6 +359,9 @@ slim_status make_frame(slim_map *m, const float *points, const float *ranges, co
     fp->pts = points;
     fp->ranges = points ? nullptr : ranges;
     fp->dirs = points ? nullptr : dirs;
+    fp->depth = nullptr;
+    fp->width = 0;
+    fp->fx = fp->fy = fp->cx = fp->cy = 0.0f;
     fp->sem = sem;
     return SLIM_OK;
 }
@@ -412,6 +415,35 @@ slim_status slim_integrate_rays(slim_map *m, const float *ranges, const float *d
     FrameParams fp;
     slim_status r = make_frame(m, nullptr, ranges, dirs, n, pose, sem, kind, &fp);
     return r ? r : integrate_frame(m, fp, stream);
+}
+
+slim_status slim_integrate_depth(slim_map *m, const float *depth, int32_t width, int32_t height,
+                                 const float *intrinsics, const double *pose, const void *sem, int32_t kind,
+                                 void *stream)
+{
+    g_err[0] = 0;
+    if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
+    if (width < 0 || height < 0) return fail(SLIM_ERR_INVALID, "width and height must be >= 0");
+    const int64_t n = (int64_t)width * height;
+    if (n >= kMaxPoints) return fail(SLIM_ERR_INVALID, "width * height must be below 2^23");
+    if (n > 0 && !depth) return fail(SLIM_ERR_INVALID, "depth is NULL");
+    if (((uintptr_t)depth & 3u) != 0) return fail(SLIM_ERR_INVALID, "depth must be 4-byte aligned");
+    if (!intrinsics) return fail(SLIM_ERR_INVALID, "intrinsics are NULL");
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(intrinsics[i])) return fail(SLIM_ERR_INVALID, "intrinsics must be finite");
+    if (!(intrinsics[0] != 0.0f && intrinsics[1] != 0.0f)) return fail(SLIM_ERR_INVALID, "fx and fy must be nonzero");
+    if (kind != SLIM_IN_NONE && n > 0 && !sem) return fail(SLIM_ERR_INVALID, "semantic input is NULL");
+    FrameParams fp;
+    slim_status r = make_frame(m, nullptr, nullptr, nullptr, 0, pose, sem, kind, &fp);
+    if (r) return r;
+    fp.n = (int)n;
+    fp.depth = depth;
+    fp.width = width;
+    fp.fx = intrinsics[0];
+    fp.fy = intrinsics[1];
+    fp.cx = intrinsics[2];
+    fp.cy = intrinsics[3];
+    return integrate_frame(m, fp, stream);
 }
 
 slim_status slim_map_stats(slim_map *m, slim_stats *out, void *stream)

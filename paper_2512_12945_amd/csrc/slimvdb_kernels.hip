@@ -156,14 +156,26 @@ __device__ __forceinline__ bool make_ray(const FrameParams &fp, float x, float y
     return true;
 }
 
-// Sensor-frame point i: given directly, or as range * unit direction (one
-// binary32 product per component).
+// Sensor-frame point i: given directly, as range * unit direction (one
+// binary32 product per component), or back-projected from pixel i of a depth
+// image, ((u - cx) / fx) d, ((v - cy) / fy) d, d, rounded in that order (a
+// depth that is not finite and positive gives a rejected point).
 __device__ __forceinline__ void load_point(const FrameParams &fp, int i, float &x, float &y, float &z)
 {
     if (fp.pts) {
         x = fp.pts[3 * i + 0];
         y = fp.pts[3 * i + 1];
         z = fp.pts[3 * i + 2];
+    } else if (fp.depth) {
+        const int v = i / fp.width, u = i - v * fp.width;
+        const float d = fp.depth[i];
+        if (!(d > 0.0f) || !isfinite(d)) {
+            x = y = z = NAN;
+            return;
+        }
+        x = (((float)u - fp.cx) / fp.fx) * d;
+        y = (((float)v - fp.cy) / fp.fy) * d;
+        z = d;
     } else {
         const float r = fp.ranges[i];
         x = r * fp.dirs[3 * i + 0];

@@ -21,6 +21,7 @@ IN_NONE, IN_LABEL_I32, IN_PROB_F32, IN_LOGIT_F32, IN_EMB_BF16, IN_EMB_F32 = rang
 KERNELS = ("ray_walk_emit", "leaf_plan", "pair_bucket", "leaf_fuse", "frame_commit")
 
 EXPORTS = ("slim_map_create", "slim_map_destroy", "slim_map_reset", "slim_integrate", "slim_integrate_rays",
+           "slim_integrate_depth",
            "slim_map_stats", "slim_extract", "slim_query", "slim_predict", "slim_map_loss", "slim_backward_rays",
            "slim_integrate_batched", "slim_set_launch_shape", "slim_profile_enable", "slim_profile_read",
            "slim_last_error")
@@ -82,6 +83,7 @@ def load(path: str = LIB_PATH):
         L.slim_map_reset.argtypes = [vp, vp]
         L.slim_integrate.argtypes = [vp, vp, i64, vp, vp, i32, vp]
         L.slim_integrate_rays.argtypes = [vp, vp, vp, i64, vp, vp, i32, vp]
+        L.slim_integrate_depth.argtypes = [vp, vp, i32, i32, vp, vp, vp, i32, vp]
         L.slim_map_loss.argtypes = [vp, vp, vp, i64, vp, i64, ctypes.c_float, vp, vp]
         L.slim_backward_rays.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.slim_map_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
@@ -154,6 +156,14 @@ class Map:
         _check(self._L.slim_integrate_rays(self.h, _ptr(ranges), _ptr(dirs), n,
                                            self._pose.ctypes.data_as(ctypes.c_void_p), _ptr(sem), kind,
                                            _stream(self.device)))
+
+    def integrate_depth(self, depth, intrinsics, pose, sem=None, kind=IN_NONE):
+        """depth: (H, W) float32 cuda tensor (metres along the optical axis); intrinsics: (fx, fy, cx, cy)."""
+        self._pose[:] = np.asarray(pose, np.float64).reshape(16)
+        H, W = depth.shape
+        k = (ctypes.c_float * 4)(*[float(v) for v in intrinsics])
+        _check(self._L.slim_integrate_depth(self.h, _ptr(depth), W, H, k, self._pose.ctypes.data_as(ctypes.c_void_p),
+                                            _ptr(sem), kind, _stream(self.device)))
 
     def loss(self, keys, labels, samples, alpha0=1.0, out=None):
         """Map loss (see include/slimvdb.h); returns a (3,) cuda tensor (total, ce, l1)."""

@@ -80,6 +80,14 @@ def test_null_arguments():
     assert L.slim_map_destroy(None) == sv.OK
 
 
+def test_read_out_and_depth_entry_points_reject_null_map():
+    L = sv.load()
+    pp = sv.PredictParams(1.0, 1.0, 0.0, 0, None)
+    assert L.slim_predict(None, None, 0, ctypes.byref(pp), None, None, None, None) == sv.ERR_INVALID
+    k = (ctypes.c_float * 4)(1.0, 1.0, 0.0, 0.0)
+    assert L.slim_integrate_depth(None, None, 0, 0, k, None, None, 0, None) == sv.ERR_INVALID
+
+
 def test_differentiation_entry_points_reject_bad_arguments():
     L = sv.load()
     assert L.slim_integrate_rays(None, None, None, 0, None, None, 0, None) == sv.ERR_INVALID
