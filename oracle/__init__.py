@@ -58,6 +58,8 @@ def lib():
         L.om_frame_pairs.restype = i64
         L.om_apply.argtypes = [vp, i64, vp, vp, vp, vp, i32, i32]
         L.om_depth_points.argtypes = [vp, i32, i32, f32, f32, f32, f32, vp]
+        L.om_render.argtypes = [vp, vp, f32, f32, f32, f32, i32, i32, f32, f32, vp, vp, vp, vp]
+        L.om_render.restype = None
         L.om_depth_points.restype = None
         L.om_apply.restype = i32
         L.om_integrate.argtypes = [vp, vp, i64, vp, vp, i32, i32]
@@ -166,6 +168,21 @@ class OracleMap:
         sem = np.zeros((max(M, 1), max(self.nsem, 1)), np.float64)
         self._L.om_extract(self.h, _ptr(keys), _ptr(D), _ptr(W), _ptr(sem) if self.nsem else None, M)
         return dict(keys=keys[:M], D=D[:M], W=W[:M], sem=sem[:M, : self.nsem])
+
+
+def render(omap, pose, fx, fy, cx, cy, width, height, near, far):
+    """First surface per pixel (see om_render in slim_oracle.c): depth (H, W) FP64 (NaN: none),
+    key (H, W, 3) of the cell behind the surface, label (H, W), margin (H, W)."""
+    pose = np.ascontiguousarray(pose, dtype=np.float64).reshape(16)
+    n = width * height
+    depth = np.zeros(n, np.float64)
+    key = np.zeros((n, 3), np.int32)
+    label = np.zeros(n, np.int32)
+    margin = np.zeros(n, np.float64)
+    lib().om_render(omap.h, _ptr(pose), fx, fy, cx, cy, width, height, near, far, _ptr(depth), _ptr(key),
+                    _ptr(label), _ptr(margin))
+    return dict(depth=depth.reshape(height, width), key=key.reshape(height, width, 3),
+                label=label.reshape(height, width), margin=margin.reshape(height, width))
 
 
 def depth_points(depth, fx, fy, cx, cy):

@@ -673,3 +673,88 @@ int64_t om_extract(const omap *m, int32_t *keys, double *D, double *W, double *s
     free(e);
     return m->nvox;
 }
+
+/* ------------------------------------------------------------------------- */
+/* render: the map seen from a camera (the role NanoVDB plays in Sec. III-E) */
+/* ------------------------------------------------------------------------- */
+
+/* Casts one ray per pixel of a pinhole camera (pose map_T_camera, FP64;
+ * intrinsics fx, fy, cx, cy) through the map and finds the first surface: the
+ * first two consecutive cells of the Amanatides-Woo walk over [near, far] that
+ * are both observed with D > 0 in front and D <= 0 behind.  The pixel direction
+ * is ((u - cx) / fx, (v - cy) / fy, 1) in binary32, turned into the unit map
+ * direction exactly as a sensor point is (same operations); the walk is the
+ * integration walk with at most 3 ceil((far - near) / vs) + 4 cells and stops
+ * at a cell outside the key range.  Outputs per pixel i = v * width + u:
+ * depth[i], the distance along the ray where D, interpolated linearly between
+ * the two cell centres' projections onto the ray, crosses zero (NaN: no
+ * surface); key[3 i ..], the cell behind the surface (the first with D <= 0);
+ * label[i], that cell's class (closed set: first largest count; most-recent
+ * closed set: the stored class; else -1; -1 without a surface); margin[i], the
+ * smallest |D| over the observed cells the walk met up to the surface (or over
+ * the whole walk), which tells how close the sign decisions came to a tie. */
+void om_render(const omap *m, const double pose[16], float fx, float fy, float cx, float cy, int width, int height,
+               float near_t, float far_t, double *depth, int32_t *key, int32_t *label, double *margin)
+{
+    oframe f;
+    frame_setup(m, pose, &f);
+    int maxsteps = 3 * (int)ceil(((double)far_t - (double)near_t) / (double)m->vs) + 4;
+    int32_t(*cells)[3] = (int32_t(*)[3])malloc((size_t)maxsteps * sizeof(*cells));
+    for (int v = 0; v < height; ++v)
+        for (int uu = 0; uu < width; ++uu) {
+            int64_t i = (int64_t)v * width + uu;
+            depth[i] = NAN;
+            key[3 * i] = key[3 * i + 1] = key[3 * i + 2] = 0;
+            label[i] = -1;
+            margin[i] = INFINITY;
+            float dc[3] = {((float)uu - cx) / fx, ((float)v - cy) / fy, 1.0f};
+            float p[3], d[3], u[3];
+            for (int a = 0; a < 3; ++a)
+                p[a] = fmaf(f.R[a * 3 + 0], dc[0], fmaf(f.R[a * 3 + 1], dc[1], fmaf(f.R[a * 3 + 2], dc[2], f.t[a])));
+            for (int a = 0; a < 3; ++a) d[a] = p[a] - f.t[a];
+            float r = sqrtf(fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0])));
+            if (!(r > 0.0f) || !isfinite(r)) continue;
+            for (int a = 0; a < 3; ++a) u[a] = d[a] / r;
+            int nv = band_walk(m->vs, maxsteps, f.t, u, near_t, far_t, cells);
+            int have_prev = 0;
+            double Dp = 0.0, sp = 0.0;
+            for (int k = 0; k < nv; ++k) {
+                int64_t ka[3];
+                int inrange = 1;
+                for (int a = 0; a < 3; ++a) {
+                    ka[a] = (int64_t)f.a[a] + cells[k][a];
+                    if (!(ka[a] > -OM_KEY_LIMIT && ka[a] < OM_KEY_LIMIT)) inrange = 0;
+                }
+                if (!inrange) break;
+                int64_t pos = table_find(m->hkey, m->hcap, pack3((int32_t)ka[0], (int32_t)ka[1], (int32_t)ka[2]));
+                if (pos < 0) {
+                    have_prev = 0;
+                    continue;
+                }
+                int64_t rec = m->hval[pos];
+                double D = m->D[rec];
+                if (fabs(D) < margin[i]) margin[i] = fabs(D);
+                double sk = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    sk += (((double)cells[k][a] + 0.5) * (double)m->vs - (double)f.t[a]) * (double)u[a];
+                if (have_prev && Dp > 0.0 && D <= 0.0) {
+                    depth[i] = sp + (sk - sp) * Dp / (Dp - D);
+                    for (int a = 0; a < 3; ++a) key[3 * i + a] = (int32_t)ka[a];
+                    if (m->sem_mode == OM_SEM_CLOSED) {
+                        const double *c = m->sem + rec * m->nsem;
+                        int best = 0;
+                        for (int q = 1; q < m->K; ++q)
+                            if (c[q] > c[best]) best = q;
+                        label[i] = best;
+                    } else if (m->sem_mode == OM_SEM_CLOSED_LAST) {
+                        label[i] = (int32_t)m->sem[rec];
+                    }
+                    break;
+                }
+                have_prev = 1;
+                Dp = D;
+                sp = sk;
+            }
+        }
+    free(cells);
+}
