@@ -188,6 +188,23 @@ typedef struct slim_predict_params {
 slim_status slim_predict(slim_map *map, const float *xyz_dev, int64_t m, const slim_predict_params *params,
                          float *prob_dev, int32_t *label_dev, float *var_dev, void *stream);
 
+/* Renders the map from a pinhole camera: pose_host is map_T_camera (4 x 4
+ * row-major FP64), intrinsics_host {fx, fy, cx, cy}.  Pixel (u, v) casts the
+ * ray through ((u - cx) / fx, (v - cy) / fy, 1) (binary32, formed as a sensor
+ * point at unit depth is), walked cell by cell as in integration over
+ * distances [near, far] along the ray.  The surface is the first pair of
+ * consecutive observed cells with D > 0 followed by D <= 0; depth_dev
+ * (float [height x width]) receives the distance along the ray where D,
+ * interpolated linearly between the two cells' centre projections onto the
+ * ray, is zero (NaN: no surface); key_dev (int32 [height x width x 3], unless
+ * NULL) the voxel behind the surface; label_dev (int32 [height x width],
+ * unless NULL) its class (closed set: first largest count; most-recent closed
+ * set: the stored class; otherwise, or without a surface, -1).  The map-
+ * viewing role NanoVDB plays in Sec. III-E.  Queued on `stream`. */
+slim_status slim_render(slim_map *map, const double *pose_host, const float *intrinsics_host, int32_t width,
+                        int32_t height, float near_dist, float far_dist, float *depth_dev, int32_t *key_dev,
+                        int32_t *label_dev, void *stream);
+
 /* As slim_integrate, with each point given as a range along a direction:
  * point i is ranges_dev[i] * dirs_dev[3 i .. 3 i + 2] (one binary32 product per
  * component; dirs are unit vectors in the sensor frame).  A non-finite range

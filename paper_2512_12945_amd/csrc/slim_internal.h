@@ -189,6 +189,16 @@ struct PredictParams {
 };
 hipError_t launch_predict(const MapDev &md, const PredictParams &pp, const float *xyz, long long m, float *prob,
                           int32_t *label, float *var, hipStream_t s);
+// Render of the map from a pinhole camera (slim_render).
+struct RenderParams {
+    float R[9], t[3];      // camera rotation (binary32) and origin relative to the anchor voxel's corner
+    int a[3];              // anchor voxel
+    float vs, fx, fy, cx, cy, t0, t1;
+    int maxsteps, width, height;
+    int mode, K;           // SLIM_SEM_* and classes, for the label
+};
+hipError_t launch_render(const MapDev &md, const RenderParams &rp, float *depth, int32_t *key, int32_t *label,
+                         hipStream_t s);
 hipError_t launch_query(const MapDev &md, int nsem, float vs, const float *xyz, long long m, float *d, float *w,
                         float *sem, hipStream_t s);
 

@@ -566,6 +566,53 @@ slim_status slim_predict(slim_map *m, const float *xyz, int64_t mq, const slim_p
     return SLIM_OK;
 }
 
+slim_status slim_render(slim_map *m, const double *pose, const float *intrinsics, int32_t width, int32_t height,
+                        float near_dist, float far_dist, float *depth, int32_t *key, int32_t *label, void *stream)
+{
+    g_err[0] = 0;
+    if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
+    if (!pose || !intrinsics) return fail(SLIM_ERR_INVALID, "pose or intrinsics are NULL");
+    if (width < 0 || height < 0 || (int64_t)width * height > (int64_t(1) << 28))
+        return fail(SLIM_ERR_INVALID, "width and height must be >= 0 with at most 2^28 pixels");
+    if ((int64_t)width * height > 0 && !depth) return fail(SLIM_ERR_INVALID, "depth is NULL");
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(intrinsics[i])) return fail(SLIM_ERR_INVALID, "intrinsics must be finite");
+    if (!(intrinsics[0] != 0.0f && intrinsics[1] != 0.0f)) return fail(SLIM_ERR_INVALID, "fx and fy must be nonzero");
+    for (int i = 0; i < 16; ++i)
+        if (!std::isfinite(pose[i])) return fail(SLIM_ERR_INVALID, "pose has a non-finite entry");
+    const float vs = m->cfg.voxel_size;
+    if (!(near_dist >= 0.0f) || !(far_dist > near_dist) || !std::isfinite(far_dist))
+        return fail(SLIM_ERR_INVALID, "need 0 <= near < far < inf");
+    if (((double)far_dist - (double)near_dist) / (double)vs >= (double)(1 << 19))
+        return fail(SLIM_ERR_INVALID, "far - near must be below 2^19 voxel sizes");
+    RenderParams rp = {};
+    const double vsd = (double)vs;
+    for (int r = 0; r < 3; ++r) {
+        const double ta = pose[4 * r + 3];
+        const double q = std::floor(ta / vsd);
+        if (!(std::fabs(q) < (double)(1 << 19)))
+            return fail(SLIM_ERR_INVALID, "pose translation beyond 2^19 voxel sizes");
+        rp.a[r] = (int)q;
+        rp.t[r] = (float)(ta - (double)rp.a[r] * vsd);
+        for (int k = 0; k < 3; ++k) rp.R[3 * r + k] = (float)pose[4 * r + k];
+    }
+    rp.vs = vs;
+    rp.fx = intrinsics[0];
+    rp.fy = intrinsics[1];
+    rp.cx = intrinsics[2];
+    rp.cy = intrinsics[3];
+    rp.t0 = near_dist;
+    rp.t1 = far_dist;
+    rp.maxsteps = 3 * (int)std::ceil(((double)far_dist - (double)near_dist) / vsd) + 4;
+    rp.width = width;
+    rp.height = height;
+    rp.mode = m->cfg.sem_mode;
+    rp.K = m->cfg.num_classes;
+    DeviceGuard g(m->cfg.device);
+    HIP_OK(launch_render(m->md, rp, depth, key, label, (hipStream_t)stream));
+    return SLIM_OK;
+}
+
 slim_status slim_map_loss(slim_map *m, const int32_t *keys, const int32_t *labels, int64_t mv, const float *samples,
                           int64_t ns, float alpha0, float *loss, void *stream)
 {

@@ -1765,4 +1765,131 @@ hipError_t launch_predict(const MapDev &md, const PredictParams &pp, const float
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// render: first surface per pixel (the map-viewing role of Sec. III-E)
+// ---------------------------------------------------------------------------
+
+// One thread per pixel.  The ray is formed as a sensor point at unit depth is
+// (same binary32 operations), walked with the integration walk's stepping rule
+// over [t0, t1], and stops at the first pair of consecutive observed cells with
+// D > 0 then D <= 0; the depth interpolates the cell centres' projections onto
+// the ray linearly in D.  The leaf slot is cached while the walk stays in a leaf.
+__global__ __launch_bounds__(256) void k_render(const MapDev md, const RenderParams rp, float *depth, int32_t *key,
+                                                int32_t *label)
+{
+    const int px = blockIdx.x * 64 + (threadIdx.x & 63), py = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (px >= rp.width || py >= rp.height) return;
+    const long long i = (long long)py * rp.width + px;
+    float out_d = NAN;
+    int ok[3] = {0, 0, 0}, out_l = -1;
+    const float dc0 = ((float)px - rp.cx) / rp.fx, dc1 = ((float)py - rp.cy) / rp.fy, dc2 = 1.0f;
+    float p[3], u[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        p[a] = fmaf(rp.R[3 * a + 0], dc0, fmaf(rp.R[3 * a + 1], dc1, fmaf(rp.R[3 * a + 2], dc2, rp.t[a])));
+    const float d0 = p[0] - rp.t[0], d1 = p[1] - rp.t[1], d2 = p[2] - rp.t[2];
+    const float r = sqrtf(fmaf(d2, d2, fmaf(d1, d1, d0 * d0)));
+    if (r > 0.0f && isfinite(r)) {
+        u[0] = d0 / r;
+        u[1] = d1 / r;
+        u[2] = d2 / r;
+        const float vs = rp.vs, t0 = rp.t0, h = 0.5f * vs;
+        int c[3], stp[3];
+        float tm[3], td[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float s = fmaf(t0, u[a], rp.t[a]);
+            c[a] = (int)floorf(s / vs);
+            if (u[a] > 0.0f) {
+                stp[a] = 1;
+                tm[a] = t0 + fmaf((float)(c[a] + 1), vs, -s) / u[a];
+                td[a] = vs / u[a];
+            } else if (u[a] < 0.0f) {
+                stp[a] = -1;
+                tm[a] = t0 + fmaf((float)c[a], vs, -s) / u[a];
+                td[a] = -vs / u[a];
+            } else {
+                stp[a] = 0;
+                tm[a] = INFINITY;
+                td[a] = INFINITY;
+            }
+        }
+        unsigned long long cur = kEmptyKey;
+        int slot = -1;
+        bool have_prev = false;
+        float Dp = 0.0f, sp = 0.0f;
+        for (int it = 0; it < rp.maxsteps; ++it) {
+            const int kx = rp.a[0] + c[0], ky = rp.a[1] + c[1], kz = rp.a[2] + c[2];
+            if (!(key_ok(kx) && key_ok(ky) && key_ok(kz))) break;
+            const unsigned long long lk = pack_leaf(kx >> 3, ky >> 3, kz >> 3);
+            if (lk != cur) {
+                cur = lk;
+                slot = map_find(md, lk);
+            }
+            long long rec = -1;
+            if (slot >= 0) {
+                const int off = ((kx & 7) << 6) | ((ky & 7) << 3) | (kz & 7);
+                if ((md.leaf_occ[(size_t)slot * kMaskWords + (off >> 5)] >> (off & 31)) & 1u)
+                    rec = (long long)md.leaf_page[(size_t)slot * kLeafPages + (off >> 6)] * kPageVoxels +
+                          (off & (kPageVoxels - 1));
+            }
+            if (rec < 0) {
+                have_prev = false;
+            } else {
+                const float *R = md.vox + (size_t)rec * md.rec_stride;
+                const float D = R[0];
+                const float qx = fmaf((float)c[0], vs, h) - rp.t[0];
+                const float qy = fmaf((float)c[1], vs, h) - rp.t[1];
+                const float qz = fmaf((float)c[2], vs, h) - rp.t[2];
+                const float sk = fmaf(qz, u[2], fmaf(qy, u[1], qx * u[0]));
+                if (have_prev && Dp > 0.0f && D <= 0.0f) {
+                    out_d = sp + (sk - sp) * (Dp / (Dp - D));
+                    ok[0] = kx;
+                    ok[1] = ky;
+                    ok[2] = kz;
+                    if (rp.mode == SLIM_SEM_CLOSED) {
+                        float best = R[2];
+                        out_l = 0;
+                        for (int k = 1; k < rp.K; ++k)
+                            if (R[2 + k] > best) {
+                                best = R[2 + k];
+                                out_l = k;
+                            }
+                    } else if (rp.mode == SLIM_SEM_CLOSED_LAST) {
+                        out_l = (int)R[2];
+                    }
+                    break;
+                }
+                have_prev = true;
+                Dp = D;
+                sp = sk;
+            }
+            const bool xy = tm[0] <= tm[1];
+            const int ax = xy ? (tm[0] <= tm[2] ? 0 : 2) : (tm[1] <= tm[2] ? 1 : 2);
+            const float tnext = ax == 0 ? tm[0] : (ax == 1 ? tm[1] : tm[2]);
+            if (tnext > rp.t1) break;
+            if (ax == 0) { c[0] += stp[0]; tm[0] += td[0]; }
+            else if (ax == 1) { c[1] += stp[1]; tm[1] += td[1]; }
+            else { c[2] += stp[2]; tm[2] += td[2]; }
+        }
+    }
+    depth[i] = out_d;
+    if (key) {
+        key[3 * i + 0] = ok[0];
+        key[3 * i + 1] = ok[1];
+        key[3 * i + 2] = ok[2];
+    }
+    if (label) label[i] = out_l;
+}
+
+hipError_t launch_render(const MapDev &md, const RenderParams &rp, float *depth, int32_t *key, int32_t *label,
+                         hipStream_t s)
+{
+    if (rp.width <= 0 || rp.height <= 0) return hipGetLastError();
+    const dim3 grid((rp.width + 63) / 64, (rp.height + 3) / 4);
+    hipLaunchKernelGGL(k_render, grid, dim3(256), 0, s, md, rp, depth, key, label);
+    return hipGetLastError();
+}
+
 }  // namespace slim

@@ -22,7 +22,8 @@ KERNELS = ("ray_walk_emit", "leaf_plan", "pair_bucket", "leaf_fuse", "frame_comm
 
 EXPORTS = ("slim_map_create", "slim_map_destroy", "slim_map_reset", "slim_integrate", "slim_integrate_rays",
            "slim_integrate_depth",
-           "slim_map_stats", "slim_extract", "slim_query", "slim_predict", "slim_map_loss", "slim_backward_rays",
+           "slim_map_stats", "slim_extract", "slim_query", "slim_predict", "slim_render", "slim_map_loss",
+           "slim_backward_rays",
            "slim_integrate_batched", "slim_set_launch_shape", "slim_profile_enable", "slim_profile_read",
            "slim_last_error")
 
@@ -90,6 +91,7 @@ def load(path: str = LIB_PATH):
         L.slim_extract.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
         L.slim_query.argtypes = [vp, vp, i64, vp, vp, vp, vp]
         L.slim_predict.argtypes = [vp, vp, i64, ctypes.POINTER(PredictParams), vp, vp, vp, vp]
+        L.slim_render.argtypes = [vp, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]
         L.slim_integrate_batched.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Frame), i32, vp]
         L.slim_set_launch_shape.argtypes = [vp, ctypes.POINTER(LaunchShape)]
         L.slim_profile_enable.argtypes = [vp, i32]
@@ -187,6 +189,18 @@ class Map:
                                     _stream(self.device)))
         return dict(prob=None if out_p is None else out_p[:m], label=out_l[:m],
                     var=None if out_v is None else out_v[:m])
+
+    def render(self, pose, intrinsics, width, height, near, far, keys=True, labels=True):
+        """First surface per pixel (see slim_render in include/slimvdb.h): dict(depth (H, W), key (H, W, 3)
+        or None, label (H, W) or None) as cuda tensors."""
+        pose = np.ascontiguousarray(pose, np.float64).reshape(16)
+        k = (ctypes.c_float * 4)(*[float(v) for v in intrinsics])
+        depth = torch.empty((height, width), dtype=torch.float32, device=self.device)
+        key = torch.empty((height, width, 3), dtype=torch.int32, device=self.device) if keys else None
+        lab = torch.empty((height, width), dtype=torch.int32, device=self.device) if labels else None
+        _check(self._L.slim_render(self.h, pose.ctypes.data_as(ctypes.c_void_p), k, width, height, float(near),
+                                   float(far), _ptr(depth), _ptr(key), _ptr(lab), _stream(self.device)))
+        return dict(depth=depth, key=key, label=lab)
 
     def backward_rays(self, ranges, dirs, pose, logits, grad_logits, grad_ranges, grad_scale=None):
         self._pose[:] = np.asarray(pose, np.float64).reshape(16)
