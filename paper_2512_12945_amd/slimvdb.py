@@ -184,7 +184,8 @@ class Map:
                            _ptr(prototypes) if open_set else None)
         out_p = torch.empty((max(m, 1), C), dtype=torch.float32, device=self.device) if prob else None
         out_l = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
-        out_v = torch.empty((max(m, 1), self.cfg.embed_dim), dtype=torch.float32, device=self.device) if var else None
+        out_v = torch.empty((max(m, 1), max(self.cfg.embed_dim, 1)), dtype=torch.float32,
+                            device=self.device) if var else None
         _check(self._L.slim_predict(self.h, _ptr(xyz), m, ctypes.byref(pp), _ptr(out_p), _ptr(out_l), _ptr(out_v),
                                     _stream(self.device)))
         return dict(prob=None if out_p is None else out_p[:m], label=out_l[:m],
