@@ -603,7 +603,8 @@ __device__ __forceinline__ float wave_sum(float v)
 // record moves as 16-byte vectors.
 template <int KMAX, bool ROWS>
 __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
-                                             const float *vals, uint32_t n, long long rec, bool existed)
+                                             const float *vals, const int32_t *labs, uint32_t n, long long rec,
+                                             bool existed)
 {
     constexpr int KA = KMAX > 0 ? KMAX : 1;
     constexpr int NV = (2 + KMAX + 3) / 4;
@@ -619,7 +620,8 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
         if (KMAX > 0 && !ROWS) {
             int lab[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) lab[q] = c0 + q < n ? ((const int32_t *)fp.sem)[kk[q] & kPidMask] : -1;
+            for (int q = 0; q < 8; ++q)
+                lab[q] = c0 + q < n ? (labs ? labs[c0 + q] : ((const int32_t *)fp.sem)[kk[q] & kPidMask]) : -1;
 #pragma unroll
             for (int q = 0; q < 8; ++q)
 #pragma unroll
@@ -679,7 +681,14 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
 // One voxel, one wave: lane l owns components l, l + 64, ... of the open-set
 // statistics (L <= 1024) or of the class counts (K <= 1024).
 constexpr int kWaveComps = 16;
+constexpr int kWaveBatch = 4;  // observations whose rows are in flight at once
 
+// One voxel, one wave: lane l owns components l, l + 64, ... of the open-set
+// statistics (L <= 1024) or of the class counts (K <= 1024).  The rows of
+// kWaveBatch observations are loaded before any is used.  Open set: one pass
+// over the observations with sums shifted by the first one, s1 = sum (z - z_0),
+// s2 = sum (z - z_0)^2, so the batch mean is z_0 + s1 / n and the scatter
+// s2 - s1^2 / n (the shift keeps the subtraction well conditioned).
 __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
                                              const float *vals, uint32_t n, long long rec, bool existed)
 {
@@ -687,35 +696,97 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
     const bool open = fp.L > 0;
     const int C = open ? fp.L : fp.K;
     float *R = md.vox + (size_t)rec * md.rec_stride;
-    float s1[kWaveComps];
+    float s1[kWaveComps], s2[kWaveComps];
 #pragma unroll
-    for (int j = 0; j < kWaveComps; ++j) s1[j] = 0.0f;
+    for (int j = 0; j < kWaveComps; ++j) {
+        s1[j] = 0.0f;
+        s2[j] = 0.0f;
+    }
     float sum_t = 0.0f;
-    for (uint32_t q = 0; q < n; ++q) {
-        const uint32_t pid = keys[q] & kPidMask;
-        sum_t += vals[q];
-        if (open) {
+    for (uint32_t q = 0; q < n; ++q) sum_t += vals[q];
+    if (open) {
+        float z0[kWaveComps];
+        const uint32_t p0 = keys[0] & kPidMask;
 #pragma unroll
-            for (int j = 0; j < kWaveComps; ++j) {
-                const int comp = lane + 64 * j;
-                if (comp < C) s1[j] += load_emb(fp, pid, comp);
+        for (int j = 0; j < kWaveComps; ++j) z0[j] = (lane + 64 * j < C) ? load_emb(fp, p0, lane + 64 * j) : 0.0f;
+        for (uint32_t q = 1; q < n; q += kWaveBatch) {
+            float z[kWaveBatch][kWaveComps];
+#pragma unroll
+            for (int b = 0; b < kWaveBatch; ++b) {
+                const bool has = q + b < n;
+                const uint32_t pid = has ? keys[q + b] & kPidMask : p0;
+#pragma unroll
+                for (int j = 0; j < kWaveComps; ++j)
+                    z[b][j] = (has && lane + 64 * j < C) ? load_emb(fp, pid, lane + 64 * j) : z0[j];
             }
-        } else if (fp.sem_kind == SLIM_IN_LABEL_I32) {
-            const int lab = ((const int32_t *)fp.sem)[pid];
 #pragma unroll
-            for (int j = 0; j < kWaveComps; ++j) s1[j] += (lab == lane + 64 * j) ? 1.0f : 0.0f;
-        } else if (fp.sem_kind == SLIM_IN_PROB_F32) {
+            for (int b = 0; b < kWaveBatch; ++b)
 #pragma unroll
-            for (int j = 0; j < kWaveComps; ++j) {
-                const int comp = lane + 64 * j;
-                if (comp < C) s1[j] += ((const float *)fp.sem)[(size_t)pid * C + comp];
+                for (int j = 0; j < kWaveComps; ++j) {
+                    const float d = z[b][j] - z0[j];
+                    s1[j] += d;
+                    s2[j] += d * d;
+                }
+        }
+        // Eqs. (11)-(14) with lambda = W, nu = W / 2
+        const float nf = (float)n;
+        const float W0 = existed ? R[1] : 0.0f, W1 = W0 + nf;
+        const float cross = W0 * nf / W1;
+        float *M = R + 2, *B = R + 2 + fp.L;
+#pragma unroll
+        for (int j = 0; j < kWaveComps; ++j) {
+            const int comp = lane + 64 * j;
+            if (comp < C) {
+                const float zbar = z0[j] + s1[j] / nf;
+                const float scat = fmaxf(s2[j] - s1[j] * s1[j] / nf, 0.0f);
+                const float m0 = existed ? M[comp] : 0.0f, b0 = existed ? B[comp] : 0.0f;
+                const float dm = zbar - m0;
+                B[comp] = b0 + 0.5f * scat + cross * dm * dm * 0.5f;
+                M[comp] = (W0 * m0 + nf * zbar) / W1;
             }
-        } else {
-            // logits, K <= 64: softmax across the wave
-            const float l = lane < C ? ((const float *)fp.sem)[(size_t)pid * C + lane] : -INFINITY;
-            const float mx = wave_max(l);
-            const float e = lane < C ? expf(l - mx) : 0.0f;
-            s1[0] += e / wave_sum(e);
+        }
+    } else if (fp.sem_kind == SLIM_IN_LABEL_I32) {
+        for (uint32_t q = 0; q < n; q += 2 * kWaveBatch) {
+            int lab[2 * kWaveBatch];
+#pragma unroll
+            for (int b = 0; b < 2 * kWaveBatch; ++b)
+                lab[b] = q + b < n ? ((const int32_t *)fp.sem)[keys[q + b] & kPidMask] : -1;
+#pragma unroll
+            for (int b = 0; b < 2 * kWaveBatch; ++b)
+#pragma unroll
+                for (int j = 0; j < kWaveComps; ++j) s1[j] += (lab[b] == lane + 64 * j) ? 1.0f : 0.0f;
+        }
+    } else if (fp.sem_kind == SLIM_IN_PROB_F32) {
+        for (uint32_t q = 0; q < n; q += kWaveBatch) {
+            float x[kWaveBatch][kWaveComps];
+#pragma unroll
+            for (int b = 0; b < kWaveBatch; ++b) {
+                const bool has = q + b < n;
+                const size_t row = has ? (size_t)(keys[q + b] & kPidMask) * C : 0;
+#pragma unroll
+                for (int j = 0; j < kWaveComps; ++j)
+                    x[b][j] = (has && lane + 64 * j < C) ? ((const float *)fp.sem)[row + lane + 64 * j] : 0.0f;
+            }
+#pragma unroll
+            for (int b = 0; b < kWaveBatch; ++b)
+#pragma unroll
+                for (int j = 0; j < kWaveComps; ++j) s1[j] += x[b][j];
+        }
+    } else {
+        // logits, K <= 64: softmax across the wave
+        for (uint32_t q = 0; q < n; q += kWaveBatch) {
+            float l[kWaveBatch];
+#pragma unroll
+            for (int b = 0; b < kWaveBatch; ++b)
+                l[b] = (q + b < n && lane < C) ? ((const float *)fp.sem)[(size_t)(keys[q + b] & kPidMask) * C + lane]
+                                               : -INFINITY;
+#pragma unroll
+            for (int b = 0; b < kWaveBatch; ++b) {
+                if (q + b >= n) break;
+                const float mx = wave_max(l[b]);
+                const float e = lane < C ? expf(l[b] - mx) : 0.0f;
+                s1[0] += e / wave_sum(e);
+            }
         }
     }
     const float nf = (float)n;
@@ -726,38 +797,6 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
         for (int j = 0; j < kWaveComps; ++j) {
             const int comp = lane + 64 * j;
             if (comp < C) R[2 + comp] = (existed ? R[2 + comp] : 0.0f) + s1[j];
-        }
-    } else {
-        // second pass: squared deviations from the batch mean
-        float zbar[kWaveComps], s2[kWaveComps];
-#pragma unroll
-        for (int j = 0; j < kWaveComps; ++j) {
-            zbar[j] = s1[j] / nf;
-            s2[j] = 0.0f;
-        }
-        for (uint32_t q = 0; q < n; ++q) {
-            const uint32_t pid = keys[q] & kPidMask;
-#pragma unroll
-            for (int j = 0; j < kWaveComps; ++j) {
-                const int comp = lane + 64 * j;
-                if (comp < C) {
-                    const float dz = load_emb(fp, pid, comp) - zbar[j];
-                    s2[j] += dz * dz;
-                }
-            }
-        }
-        // Eqs. (11)-(14) with lambda = W, nu = W / 2
-        const float cross = W0 * nf / W1;
-        float *M = R + 2, *B = R + 2 + fp.L;
-#pragma unroll
-        for (int j = 0; j < kWaveComps; ++j) {
-            const int comp = lane + 64 * j;
-            if (comp < C) {
-                const float m0 = existed ? M[comp] : 0.0f, b0 = existed ? B[comp] : 0.0f;
-                const float dm = zbar[j] - m0;
-                B[comp] = b0 + 0.5f * s2[j] + cross * dm * dm * 0.5f;
-                M[comp] = (W0 * m0 + nf * zbar[j]) / W1;
-            }
         }
     }
     if (lane == 0) {
@@ -825,7 +864,7 @@ __device__ __forceinline__ void combine_last_wave(const FrameParams &fp, const M
 // bin o sit at keys[bin0[o] - base] / vals[bin0[o] - base] (LDS or global).
 template <int KMAX, bool WAVE, bool ROWS>
 __device__ void combine_range(const FrameParams &fp, const MapDev &md, LeafShared &sh, const uint32_t *keys,
-                              const float *vals, uint32_t o0, uint32_t o1, uint32_t base)
+                              const float *vals, const int32_t *labs, uint32_t o0, uint32_t o1, uint32_t base)
 {
     if (!WAVE) {
         for (uint32_t o = o0 + threadIdx.x; o < o1; o += blockDim.x) {
@@ -837,7 +876,9 @@ __device__ void combine_range(const FrameParams &fp, const MapDev &md, LeafShare
                 combine_last_lane(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base), n, rec, existed);
             else
                 combine_lane<(KMAX < 0 ? 0 : KMAX), ROWS>(fp, md, keys + (sh.bin0[o] - base),
-                                                          vals + (sh.bin0[o] - base), n, rec, existed);
+                                                          vals + (sh.bin0[o] - base),
+                                                          labs ? labs + (sh.bin0[o] - base) : nullptr, n, rec,
+                                                          existed);
         }
     } else {
         const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -1019,11 +1060,19 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
                 }
             }
             __syncthreads();
+            const int32_t *labs = nullptr;
+            if (KMAX > 0 && !ROWS && !WAVE && fits && ok) {
+                // the labels of the sorted pairs, gathered once into the free binning array
+                for (uint32_t t = tid; t < hi - lo; t += blockDim.x)
+                    sh.b_key[t] = (uint32_t)((const int32_t *)fp.sem)[sh.a_key[t] & kPidMask];
+                __syncthreads();
+                labs = (const int32_t *)sh.b_key;
+            }
             if (ok) {
                 // sorted pairs of bin o sit at keys[bin0[o] - base]
                 const uint32_t *ck = fits ? sh.a_key : md.srt_key + plan.z;
                 const float *cv = fits ? sh.a_val : md.srt_tsdf + plan.z;
-                combine_range<KMAX, WAVE, ROWS>(fp, md, sh, ck, cv, o0, o1, fits ? lo : 0u);
+                combine_range<KMAX, WAVE, ROWS>(fp, md, sh, ck, cv, labs, o0, o1, fits ? lo : 0u);
             }
             __syncthreads();
             o0 = o1;
