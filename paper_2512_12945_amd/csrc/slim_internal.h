@@ -17,8 +17,9 @@ constexpr int kLeafVoxels = 512;
 constexpr int kMaskWords = kLeafVoxels / 32; // 16 words of occupied bits per leaf
 constexpr int kPageVoxels = 64;              // records are allocated per x-slab (8 x 8 voxels) of a leaf
 constexpr int kLeafPages = kLeafVoxels / kPageVoxels;
-constexpr int kWalkThreads = 256;
-constexpr int kWalkTable = 2048;             // block-local leaf table of the walk kernel
+constexpr int kWalkThreads = 64;             // one wave per walk block: its barriers are cheap, and
+                                             // several blocks per CU hide each other's memory latency
+constexpr int kWalkTable = 8 * kWalkThreads; // block-local leaf table: at most 8 leaf runs per ray
 constexpr int kLeafThreads = 256;
 constexpr int kLeafBatch = 8;                // loads in flight per thread in the leaf kernel
 constexpr int kLeafLdsPairs = kLeafBatch * kLeafThreads;  // pairs a leaf holds in LDS at once

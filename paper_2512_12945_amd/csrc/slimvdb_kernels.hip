@@ -238,7 +238,7 @@ __device__ __forceinline__ float cell_sdf(const FrameParams &fp, const Ray &ry, 
 __device__ __forceinline__ bool key_ok(int k) { return k > -kKeyLimit && k < kKeyLimit; }
 
 // ---------------------------------------------------------------------------
-// block-wide helpers (blockDim.x = 256)
+// block-wide helpers (blockDim.x a multiple of 64, at most 256)
 // ---------------------------------------------------------------------------
 
 // Exclusive prefix sum over the block of one value per thread; *total gets
@@ -250,10 +250,11 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, 
     if (lane == 63) wsum[w] = incl;
     __syncthreads();
     uint32_t before = 0, tot = 0;
+    const int nw = (int)(blockDim.x >> 6);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (q < w) before += wsum[q];
-        tot += wsum[q];
+        if (q < nw) tot += wsum[q];
     }
     __syncthreads();
     *total = tot;
@@ -277,6 +278,7 @@ __device__ void block_scan512(const uint32_t *in, uint32_t *out, uint32_t *wsum)
 // ---------------------------------------------------------------------------
 
 constexpr int kMaxRuns = 8;  // leaf runs per ray; sdf_trunc <= 6 voxel_size keeps a ray within this
+static_assert(kWalkTable >= kWalkThreads * kMaxRuns, "the walk table must hold every run of a block");
 
 __device__ __forceinline__ uint32_t lds_hash(unsigned long long k)
 {
