@@ -46,6 +46,7 @@ struct DevState {
     Line new_leaves;  // leaves to create
     Line new_pages;   // record pages to create
     Line pair_cursor; // bucket allocation cursor
+    Line work_big;    // slab work items of large leaves
     Line frame_err;   // nonzero: do not apply this frame
     // persistent
     unsigned long long leaves_used;
@@ -126,6 +127,8 @@ struct MapDev {
     uint32_t *tmp_key;    // scratch of large leaves: pairs binned by voxel offset
     float *tmp_tsdf;
     uint32_t pair_cap;
+    int2 *work;           // slab work items (staging position, slab) of large leaves
+    uint32_t work_cap;
     uint2 *blk_stats;     // per leaf-kernel block: (voxels updated that existed, voxels created)
     int leaf_blocks;      // grid of the leaf kernel of the current frame (<= kMaxLeafBlocksPerCu * CUs)
     DevState *st;

@@ -178,8 +178,8 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s)
     size_t cap = std::max<size_t>(need, m->pair_cap + m->pair_cap / 2);
     cap = std::min<size_t>(cap, 0xFFFFFFF0ull);
     MapDev &md = m->md;
-    void *ptrs[8] = {md.pair_pos, md.pair_rank, md.pair_key, md.pair_tsdf,
-                     md.srt_key,  md.srt_tsdf,  md.tmp_key,  md.tmp_tsdf};
+    void *ptrs[9] = {md.pair_pos, md.pair_rank, md.pair_key, md.pair_tsdf, md.srt_key,
+                     md.srt_tsdf, md.tmp_key,   md.tmp_tsdf, md.work};
     for (void *p : ptrs) {
         if (!p) continue;
         (void)hipFree(p);
@@ -187,17 +187,23 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s)
     }
     md.pair_pos = md.pair_rank = md.pair_key = md.srt_key = md.tmp_key = nullptr;
     md.pair_tsdf = md.srt_tsdf = md.tmp_tsdf = nullptr;
+    md.work = nullptr;
+    // a large leaf has more than kLeafLdsPairs pairs and at most 8 slab items
+    const size_t wcap = cap / (kLeafLdsPairs / kLeafPages) + kLeafPages;
     slim_status r;
     if ((r = dalloc(m, &md.pair_pos, cap)) || (r = dalloc(m, &md.pair_rank, cap)) ||
         (r = dalloc(m, &md.pair_key, cap)) || (r = dalloc(m, &md.pair_tsdf, cap)) ||
         (r = dalloc(m, &md.srt_key, cap)) || (r = dalloc(m, &md.srt_tsdf, cap)) ||
-        (r = dalloc(m, &md.tmp_key, cap)) || (r = dalloc(m, &md.tmp_tsdf, cap))) {
+        (r = dalloc(m, &md.tmp_key, cap)) || (r = dalloc(m, &md.tmp_tsdf, cap)) ||
+        (r = dalloc(m, &md.work, wcap))) {
         m->pair_cap = 0;
         md.pair_cap = 0;
+        md.work_cap = 0;
         return r;
     }
     m->pair_cap = cap;
     md.pair_cap = (uint32_t)cap;
+    md.work_cap = (uint32_t)wcap;
     return SLIM_OK;
 }
 

@@ -518,6 +518,20 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
         const uint32_t newleaf = wave_reserve(&md.st->new_leaves.v, (act && slot < 0) ? 1u : 0u);
         const uint32_t pbase = wave_reserve(&md.st->new_pages.v, __popc(need));
         const uint32_t bstart = wave_reserve(&md.st->pair_cursor.v, npairs);
+        // a leaf with more pairs than the leaf kernel holds in LDS becomes one
+        // work item per touched x-slab
+        const uint32_t tslabs = act ? md.pos_slab[pos] & 0xFFu : 0u;
+        const bool big = act && npairs > (uint32_t)kLeafLdsPairs;
+        const uint32_t ibase = wave_reserve(&md.st->work_big.v, big ? __popc(tslabs) : 0u);
+        if (big) {
+            uint32_t r = 0;
+            for (int q = 0; q < kLeafPages; ++q)
+                if ((tslabs >> q) & 1u) {
+                    if (ibase + r < md.work_cap) md.work[ibase + r] = make_int2((int)pos, q);
+                    else atomicOr(&md.st->frame_err.v, 1u);
+                    r++;
+                }
+        }
         if (act) {
             uint32_t r = 0;
 #pragma unroll
@@ -914,43 +928,86 @@ __device__ __forceinline__ void rank_bins(LeafShared &sh, KP bk, VP bv, uint32_t
     }
 }
 
-// Leaves blk, blk + nblk, ... of one map's frame; block statistics go to
-// md.blk_stats[blk].
+// One work item of the leaf kernel: the touched leaf at staging position pos,
+// all of it (slab < 0) or, for a leaf with more pairs than LDS holds, the
+// voxels of one x-slab (offsets 64 slab .. 64 slab + 63), so that the slabs
+// of a large leaf run in different workgroups.  Reads every pair of the leaf
+// for the offset histogram, keeps those of its offsets, orders them by point
+// index inside each voxel and combines the voxels.
 template <int KMAX, bool WAVE, bool ROWS>
-__device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const MapDev &md, LeafShared &sh,
-                                                uint32_t blk, uint32_t nblk)
+__device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &md, LeafShared &sh, uint32_t pos,
+                                          int slab, unsigned long long lused, bool ok)
 {
-    const DevState *st = md.st;
-    const uint32_t nt = st->n_touched.v;
-    const unsigned long long lused = st->leaves_used;
-    const bool ok = st->frame_err.v == 0 && lused + st->new_leaves.v <= (unsigned long long)md.max_leaves &&
-                    st->pages_used + st->new_pages.v <= (unsigned long long)md.max_pages;
     const int tid = threadIdx.x;
+    const int4 plan = md.pos_plan[pos];
+    const uint32_t n = md.pos_count[pos];
+    const int slot = plan.x >= 0 ? plan.x : (int)(lused + (unsigned long long)plan.y);
+    const uint32_t ob = slab < 0 ? 0u : 64u * (uint32_t)slab, oe = slab < 0 ? (uint32_t)kLeafVoxels : ob + 64u;
+    for (int o = tid; o < kLeafVoxels; o += blockDim.x) sh.hist[o] = 0;
+    if (tid < kMaskWords) sh.occ0[tid] = plan.x >= 0 ? md.leaf_occ[(size_t)plan.x * kMaskWords + tid] : 0u;
+    if (tid < kLeafPages) sh.pages[tid] = ((const int *)md.pos_pages)[8 * (size_t)pos + tid];
+    __syncthreads();
+
+    const uint32_t *gk = md.srt_key + plan.z;
+    const float *gv = md.srt_tsdf + plan.z;
+    uint32_t *tk = md.tmp_key + plan.z;
+    float *tv = md.tmp_tsdf + plan.z;
+    const bool whole_small = slab < 0 && n <= (uint32_t)kLeafLdsPairs;
+
+    // histogram of the voxel offsets of every pair of the leaf; kLeafBatch loads
+    // in flight per thread, and a whole leaf that fits LDS stays in registers
+    uint32_t rk[kLeafBatch];
+    float rv[kLeafBatch];
+    for (uint32_t t0 = 0; t0 < n; t0 += kLeafLdsPairs) {
+#pragma unroll
+        for (int u = 0; u < kLeafBatch; ++u) {
+            const uint32_t t = t0 + u * kLeafThreads + tid;
+            rk[u] = t < n ? gk[t] : 0u;
+            rv[u] = t < n ? gv[t] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kLeafBatch; ++u)
+            if (t0 + u * kLeafThreads + tid < n) atomicAdd(&sh.hist[rk[u] >> kPidBits], 1u);
+    }
+    __syncthreads();
+    block_scan512(sh.hist, sh.bin0, sh.wsum);
+    for (int o = tid; o < kLeafVoxels; o += blockDim.x) sh.cur[o] = sh.bin0[o];
+    {
+        // touched offsets: wave w covers bins 64w + [0, 64) and 256 + 64w + [0, 64)
+        const int w = tid >> 6;
+        const unsigned long long b0 = __ballot(sh.hist[tid] != 0u);
+        const unsigned long long b1 = __ballot(sh.hist[tid + 256] != 0u);
+        if (lane_id() == 0) {
+            sh.touch[2 * w] = (uint32_t)b0;
+            sh.touch[2 * w + 1] = (uint32_t)(b0 >> 32);
+            sh.touch[8 + 2 * w] = (uint32_t)b1;
+            sh.touch[9 + 2 * w] = (uint32_t)(b1 >> 32);
+        }
+    }
+    __syncthreads();
+    const uint32_t lo_all = sh.bin0[ob], hi_all = oe < (uint32_t)kLeafVoxels ? sh.bin0[oe] : n;
+    const bool small = whole_small || (slab >= 0 && hi_all - lo_all <= (uint32_t)kLeafLdsPairs);
     if (tid == 0) {
-        sh.uold = 0;
-        sh.unew = 0;
+        uint32_t uo = 0, un = 0;
+        for (uint32_t w = ob >> 5; w < (oe >> 5); ++w) {
+            uo += __popc(sh.touch[w] & sh.occ0[w]);
+            un += __popc(sh.touch[w] & ~sh.occ0[w]);
+        }
+        sh.uold += uo;
+        sh.unew += un;
     }
 
-    for (uint32_t j = blk; j < nt; j += nblk) {
-        const uint32_t pos = md.touched[j];
-        const int4 plan = md.pos_plan[pos];
-        const uint32_t n = md.pos_count[pos];
-        const int slot = plan.x >= 0 ? plan.x : (int)(lused + (unsigned long long)plan.y);
-        for (int o = tid; o < kLeafVoxels; o += blockDim.x) sh.hist[o] = 0;
-        if (tid < kMaskWords) sh.occ0[tid] = plan.x >= 0 ? md.leaf_occ[(size_t)plan.x * kMaskWords + tid] : 0u;
-        if (tid < kLeafPages) sh.pages[tid] = ((const int *)md.pos_pages)[8 * (size_t)pos + tid];
-        __syncthreads();
-
-        const uint32_t *gk = md.srt_key + plan.z;
-        const float *gv = md.srt_tsdf + plan.z;
-        uint32_t *tk = md.tmp_key + plan.z;
-        float *tv = md.tmp_tsdf + plan.z;
-        const bool small = n <= (uint32_t)kLeafLdsPairs;
-
-        // histogram of voxel offsets; kLeafBatch loads in flight per thread, and
-        // a bucket that fits LDS stays in registers until its scatter
-        uint32_t rk[kLeafBatch];
-        float rv[kLeafBatch];
+    // bin by offset (order inside a bin arbitrary): in LDS if the item fits,
+    // else in the scratch buffer
+    if (whole_small) {
+#pragma unroll
+        for (int u = 0; u < kLeafBatch; ++u)
+            if ((uint32_t)(u * kLeafThreads + tid) < n) {
+                const uint32_t p = atomicAdd(&sh.cur[rk[u] >> kPidBits], 1u);
+                sh.b_key[p] = rk[u];
+                sh.b_val[p] = rv[u];
+            }
+    } else {
         for (uint32_t t0 = 0; t0 < n; t0 += kLeafLdsPairs) {
 #pragma unroll
             for (int u = 0; u < kLeafBatch; ++u) {
@@ -959,146 +1016,141 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
                 rv[u] = t < n ? gv[t] : 0.0f;
             }
 #pragma unroll
-            for (int u = 0; u < kLeafBatch; ++u)
-                if (t0 + u * kLeafThreads + tid < n) atomicAdd(&sh.hist[rk[u] >> kPidBits], 1u);
-        }
-        __syncthreads();
-        block_scan512(sh.hist, sh.bin0, sh.wsum);
-        for (int o = tid; o < kLeafVoxels; o += blockDim.x) sh.cur[o] = sh.bin0[o];
-        {
-            // touched offsets: wave w covers bins 64w + [0, 64) and 256 + 64w + [0, 64)
-            const int w = tid >> 6;
-            const unsigned long long b0 = __ballot(sh.hist[tid] != 0u);
-            const unsigned long long b1 = __ballot(sh.hist[tid + 256] != 0u);
-            if (lane_id() == 0) {
-                sh.touch[2 * w] = (uint32_t)b0;
-                sh.touch[2 * w + 1] = (uint32_t)(b0 >> 32);
-                sh.touch[8 + 2 * w] = (uint32_t)b1;
-                sh.touch[9 + 2 * w] = (uint32_t)(b1 >> 32);
-            }
-        }
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t uo = 0, un = 0;
-            for (int w = 0; w < kMaskWords; ++w) {
-                uo += __popc(sh.touch[w] & sh.occ0[w]);
-                un += __popc(sh.touch[w] & ~sh.occ0[w]);
-            }
-            sh.uold += uo;
-            sh.unew += un;
-        }
-
-        // bin by offset (order inside a bin arbitrary): in LDS if the bucket fits,
-        // else in the scratch buffer
-        if (small) {
-#pragma unroll
-            for (int u = 0; u < kLeafBatch; ++u)
-                if ((uint32_t)(u * kLeafThreads + tid) < n) {
-                    const uint32_t p = atomicAdd(&sh.cur[rk[u] >> kPidBits], 1u);
-                    sh.b_key[p] = rk[u];
-                    sh.b_val[p] = rv[u];
-                }
-        } else {
-            for (uint32_t t0 = 0; t0 < n; t0 += kLeafLdsPairs) {
-#pragma unroll
-                for (int u = 0; u < kLeafBatch; ++u) {
-                    const uint32_t t = t0 + u * kLeafThreads + tid;
-                    rk[u] = t < n ? gk[t] : 0u;
-                    rv[u] = t < n ? gv[t] : 0.0f;
-                }
-#pragma unroll
-                for (int u = 0; u < kLeafBatch; ++u)
-                    if (t0 + u * kLeafThreads + tid < n) {
-                        const uint32_t p = atomicAdd(&sh.cur[rk[u] >> kPidBits], 1u);
+            for (int u = 0; u < kLeafBatch; ++u) {
+                const uint32_t o = rk[u] >> kPidBits;
+                if (t0 + u * kLeafThreads + tid < n && o >= ob && o < oe) {
+                    const uint32_t p = atomicAdd(&sh.cur[o], 1u);
+                    if (small) {
+                        sh.b_key[p - lo_all] = rk[u];
+                        sh.b_val[p - lo_all] = rv[u];
+                    } else {
                         tk[p] = rk[u];
                         tv[p] = rv[u];
                     }
-            }
-        }
-        __syncthreads();
-
-        // runs of whole bins that fit LDS: order each bin by point index, then
-        // combine its voxels (a small bucket is one run, already in LDS)
-        uint32_t o0 = 0;
-        while (o0 < (uint32_t)kLeafVoxels) {
-            uint32_t o1 = kLeafVoxels;
-            if (!small) {
-                if (tid == 0) {
-                    // bin ends are non-decreasing: first o1 > o0 whose end passes
-                    // bin0[o0] + capacity (at least o0 + 1)
-                    const uint32_t lim = sh.bin0[o0] + (uint32_t)kLeafLdsPairs;
-                    uint32_t lo = o0 + 1, hi = kLeafVoxels;
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (sh.bin0[mid] + sh.hist[mid] <= lim) lo = mid + 1;
-                        else hi = mid;
-                    }
-                    sh.chunk_end = lo;
-                }
-                __syncthreads();
-                o1 = sh.chunk_end;
-            }
-            const uint32_t lo = sh.bin0[o0], hi = (o1 < (uint32_t)kLeafVoxels) ? sh.bin0[o1] : n;
-            const bool fits = hi - lo <= (uint32_t)kLeafLdsPairs;
-            if (fits) {
-                if (!small) {
-                    for (uint32_t t = lo + tid; t < hi; t += blockDim.x) {
-                        sh.b_key[t - lo] = tk[t];
-                        sh.b_val[t - lo] = tv[t];
-                    }
-                    __syncthreads();
-                }
-                rank_bins(sh, sh.b_key, sh.b_val, lo, hi);
-            } else {
-                // one bin larger than LDS: order it in the bucket itself
-                uint32_t *bk = md.srt_key + plan.z;
-                float *bv = md.srt_tsdf + plan.z;
-                for (uint32_t t = lo + tid; t < hi; t += blockDim.x) {
-                    const uint32_t k = tk[t];
-                    uint32_t r = 0;
-                    for (uint32_t u = lo; u < hi; ++u) r += tk[u] < k;
-                    bk[lo + r] = k;
-                    bv[lo + r] = tv[t];
                 }
             }
-            __syncthreads();
-            const int32_t *labs = nullptr;
-            if (KMAX > 0 && !ROWS && !WAVE && fits && ok) {
-                // the labels of the sorted pairs, gathered once into the free binning array
-                for (uint32_t t = tid; t < hi - lo; t += blockDim.x)
-                    sh.b_key[t] = (uint32_t)((const int32_t *)fp.sem)[sh.a_key[t] & kPidMask];
-                __syncthreads();
-                labs = (const int32_t *)sh.b_key;
-            }
-            if (ok) {
-                // sorted pairs of bin o sit at keys[bin0[o] - base]
-                const uint32_t *ck = fits ? sh.a_key : md.srt_key + plan.z;
-                const float *cv = fits ? sh.a_val : md.srt_tsdf + plan.z;
-                combine_range<KMAX, WAVE, ROWS>(fp, md, sh, ck, cv, labs, o0, o1, fits ? lo : 0u);
-            }
-            __syncthreads();
-            o0 = o1;
-        }
-
-        // leaf bookkeeping, then the staging entry is clean for the next frame
-        if (ok) {
-            if (tid == 0 && plan.x < 0) {
-                const unsigned long long key = md.skeys[pos];
-                map_insert(md, key, slot);
-                md.leaf_key[slot] = key;
-            }
-            if (tid < kLeafPages) md.leaf_page[(size_t)slot * kLeafPages + tid] = sh.pages[tid];
-            if (tid < kMaskWords) md.leaf_occ[(size_t)slot * kMaskWords + tid] = sh.occ0[tid] | sh.touch[tid];
-        }
-        __syncthreads();
-        if (tid == 0) {
-            md.skeys[pos] = kEmptyKey;
-            md.pos_count[pos] = 0u;
-            md.pos_slab[pos] = 0u;
         }
     }
     __syncthreads();
-    if (tid == 0) md.blk_stats[blk] = make_uint2(sh.uold, sh.unew);
+
+    // runs of whole bins that fit LDS: order each bin by point index, then
+    // combine its voxels (a small item is one run, already in LDS)
+    uint32_t o0 = ob;
+    while (o0 < oe) {
+        uint32_t o1 = oe;
+        if (!small) {
+            if (tid == 0) {
+                // bin ends are non-decreasing: first o1 > o0 whose end passes
+                // bin0[o0] + capacity (at least o0 + 1)
+                const uint32_t lim = sh.bin0[o0] + (uint32_t)kLeafLdsPairs;
+                uint32_t lo = o0 + 1, hi = oe;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (sh.bin0[mid] + sh.hist[mid] <= lim) lo = mid + 1;
+                    else hi = mid;
+                }
+                sh.chunk_end = lo;
+            }
+            __syncthreads();
+            o1 = sh.chunk_end;
+        }
+        const uint32_t lo = sh.bin0[o0], hi = (o1 < (uint32_t)kLeafVoxels) ? sh.bin0[o1] : n;
+        const bool fits = hi - lo <= (uint32_t)kLeafLdsPairs;
+        if (fits) {
+            if (!small) {
+                for (uint32_t t = lo + tid; t < hi; t += blockDim.x) {
+                    sh.b_key[t - lo] = tk[t];
+                    sh.b_val[t - lo] = tv[t];
+                }
+                __syncthreads();
+            }
+            rank_bins(sh, sh.b_key, sh.b_val, lo, hi);
+        } else {
+            // one bin larger than LDS: order it into the walk's pair buffers
+            // (consumed by the bucketing, free now), at the bin's own range of
+            // the leaf's bucket, which no other item touches
+            uint32_t *bk = md.pair_key + plan.z;
+            float *bv = md.pair_tsdf + plan.z;
+            for (uint32_t t = lo + tid; t < hi; t += blockDim.x) {
+                const uint32_t k = tk[t];
+                uint32_t r = 0;
+                for (uint32_t u = lo; u < hi; ++u) r += tk[u] < k;
+                bk[lo + r] = k;
+                bv[lo + r] = tv[t];
+            }
+        }
+        __syncthreads();
+        const int32_t *labs = nullptr;
+        if (KMAX > 0 && !ROWS && !WAVE && fits && ok) {
+            // the labels of the sorted pairs, gathered once into the free binning array
+            for (uint32_t t = tid; t < hi - lo; t += blockDim.x)
+                sh.b_key[t] = (uint32_t)((const int32_t *)fp.sem)[sh.a_key[t] & kPidMask];
+            __syncthreads();
+            labs = (const int32_t *)sh.b_key;
+        }
+        if (ok) {
+            // sorted pairs of bin o sit at keys[bin0[o] - base]
+            const uint32_t *ck = fits ? sh.a_key : md.pair_key + plan.z;
+            const float *cv = fits ? sh.a_val : md.pair_tsdf + plan.z;
+            combine_range<KMAX, WAVE, ROWS>(fp, md, sh, ck, cv, labs, o0, o1, fits ? lo : 0u);
+        }
+        __syncthreads();
+        o0 = o1;
+    }
+
+    // leaf bookkeeping: an item owns the page entry and the occupancy words of
+    // its offsets; the item of the leaf's lowest touched slab (or the whole-leaf
+    // item) also inserts a new leaf and writes the entries of untouched slabs
+    if (ok) {
+        const uint32_t tslabs = md.pos_slab[pos] & 0xFFu;
+        const bool lead = slab < 0 || (uint32_t)slab == (uint32_t)(__ffs(tslabs) - 1);
+        if (tid == 0 && lead && plan.x < 0) {
+            const unsigned long long key = md.skeys[pos];
+            map_insert(md, key, slot);
+            md.leaf_key[slot] = key;
+        }
+        if (tid < kLeafPages) {
+            const bool mine = slab < 0 || tid == slab || (lead && !((tslabs >> tid) & 1u));
+            if (mine) md.leaf_page[(size_t)slot * kLeafPages + tid] = sh.pages[tid];
+        }
+        if (tid < kMaskWords) {
+            const int sl = tid >> 1;
+            const bool mine = slab < 0 || sl == slab || (lead && !((tslabs >> sl) & 1u));
+            if (mine) md.leaf_occ[(size_t)slot * kMaskWords + tid] = sh.occ0[tid] | sh.touch[tid];
+        }
+    }
+    __syncthreads();
+}
+
+// The leaf kernel's work of one map's frame for blocks blk, blk + nblk, ...:
+// first the slab items of large leaves (the longest work, started first), then
+// every other touched leaf whole.  Block statistics go to md.blk_stats[blk];
+// the staging entries are cleared by the commit.
+template <int KMAX, bool WAVE, bool ROWS>
+__device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const MapDev &md, LeafShared &sh,
+                                                uint32_t blk, uint32_t nblk)
+{
+    const DevState *st = md.st;
+    const uint32_t nt = st->n_touched.v;
+    const uint32_t nbig = min(st->work_big.v, md.work_cap);
+    const unsigned long long lused = st->leaves_used;
+    const bool ok = st->frame_err.v == 0 && lused + st->new_leaves.v <= (unsigned long long)md.max_leaves &&
+                    st->pages_used + st->new_pages.v <= (unsigned long long)md.max_pages;
+    if (threadIdx.x == 0) {
+        sh.uold = 0;
+        sh.unew = 0;
+    }
+    for (uint32_t w = blk; w < nbig; w += nblk) {
+        const int2 it = md.work[w];
+        fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, (uint32_t)it.x, it.y, lused, ok);
+    }
+    for (uint32_t j = blk; j < nt; j += nblk) {
+        const uint32_t pos = md.touched[j];
+        if (md.pos_count[pos] > (uint32_t)kLeafLdsPairs) continue;
+        fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, pos, -1, lused, ok);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) md.blk_stats[blk] = make_uint2(sh.uold, sh.unew);
     __syncthreads();
 }
 
@@ -1129,6 +1181,14 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
 {
     __shared__ unsigned long long s_old[256], s_new[256];
     DevState *st = md.st;
+    // the staging entries of this frame are clean for the next one
+    const uint32_t nt = st->n_touched.v;
+    for (uint32_t j = threadIdx.x; j < nt; j += blockDim.x) {
+        const uint32_t pos = md.touched[j];
+        md.skeys[pos] = kEmptyKey;
+        md.pos_count[pos] = 0u;
+        md.pos_slab[pos] = 0u;
+    }
     unsigned long long uo = 0, un = 0;
     for (int b = threadIdx.x; b < md.leaf_blocks; b += blockDim.x) {
         const uint2 v = md.blk_stats[b];
@@ -1170,6 +1230,7 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
         st->new_leaves.v = 0;
         st->new_pages.v = 0;
         st->pair_cursor.v = 0;
+        st->work_big.v = 0;
         st->frame_err.v = 0;
     }
 }

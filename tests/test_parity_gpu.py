@@ -158,6 +158,33 @@ def test_large_leaf_bucket():
     compare_maps(extract_np(g), o.extract(), 0.06, sv.SEM_CLOSED, K=5)
 
 
+@pytest.mark.parametrize("mode", [sv.SEM_CLOSED, sv.SEM_CLOSED_LAST])
+def test_huge_voxel_and_slab(mode):
+    """Thousands of duplicated points put more pairs in one voxel, and in one
+    x-slab of a leaf, than the leaf kernel holds in LDS (the split of a large
+    leaf by slab, the chunked slab and the in-memory order of one bin)."""
+    _say(f"huge voxel bin and slab, mode {mode}")
+    rng = np.random.default_rng(17)
+    g, o = make_pair(0.1, 0.3, 0.0, 50.0, mode, K=6)
+    pose = np.eye(4)
+    pose[:3, 3] = (0.05, 0.05, 0.05)
+    base = np.array([3.037, 0.412, 0.227], np.float32)
+    pts = np.concatenate([np.repeat(base[None], 3000, 0),
+                          base + rng.normal(0, 0.12, (4000, 3)).astype(np.float32),
+                          rng.uniform(-4, 4, (500, 3)).astype(np.float32)]).astype(np.float32)
+    lab = rng.integers(0, 6, len(pts)).astype(np.int32)
+    pr = o.frame_pairs(pts, pose, lab, oracle.IN_LABEL_I32)
+    _, per_vox = np.unique(pr["keys"], axis=0, return_counts=True)
+    assert per_vox.max() > 2048
+    for rep in range(2):
+        gst, ost = integrate_both(g, o, pts, pose, lab, sv.IN_LABEL_I32)
+        assert_stats_equal(gst, ost)
+    gx, ox = extract_np(g), o.extract()
+    compare_maps(gx, ox, 0.3, mode, K=6, exact_counts=mode == sv.SEM_CLOSED)
+    if mode == sv.SEM_CLOSED_LAST:
+        assert np.array_equal(gx["sem"].astype(np.float64), ox["sem"])
+
+
 def test_capacity_all_or_nothing():
     _say("capacity: a frame that does not fit leaves the map unchanged")
     frames = synth.room_sequence(2, seed=6, yaw_span=2.0, width=64, height=48, f=40.0, cx=32.0, cy=24.0)
