@@ -17,9 +17,11 @@ constexpr int kLeafVoxels = 512;
 constexpr int kMaskWords = kLeafVoxels / 32; // 16 words of occupied bits per leaf
 constexpr int kPageVoxels = 64;              // records are allocated per x-slab (8 x 8 voxels) of a leaf
 constexpr int kLeafPages = kLeafVoxels / kPageVoxels;
-constexpr int kWalkThreads = 64;             // one wave per walk block: its barriers are cheap, and
-                                             // several blocks per CU hide each other's memory latency
-constexpr int kWalkTable = 8 * kWalkThreads; // block-local leaf table: at most 8 leaf runs per ray
+#ifndef SLIM_WALK_THREADS
+#define SLIM_WALK_THREADS 256
+#endif
+constexpr int kWalkThreads = SLIM_WALK_THREADS;  // rays per walk block
+constexpr int kWalkTable = 8 * kWalkThreads;     // block-local leaf table: at most 8 leaf runs per ray
 constexpr int kLeafThreads = 256;
 constexpr int kLeafBatch = 8;                // loads in flight per thread in the leaf kernel
 constexpr int kLeafLdsPairs = kLeafBatch * kLeafThreads;  // pairs a leaf holds in LDS at once
@@ -161,7 +163,7 @@ struct BatchPlan {
     int group_begin[16], group_size[16];  // slice of the device subset array
 };
 
-constexpr int kLeafKinds = 11;  // variants of the leaf kernel (leaf_kernel_kind)
+constexpr int kLeafKinds = 16;  // variants of the leaf kernel (leaf_kernel_kind)
 int leaf_kernel_kind(const FrameParams &fp);
 hipError_t launch_integrate_batched(const MapBatch &mb, const BatchPlan &plan, const LaunchShape &shape,
                                     hipStream_t s);

@@ -592,6 +592,7 @@ struct LeafShared {
     uint32_t touch[kMaskWords], occ0[kMaskWords], wsum[4];
     int pages[kLeafPages];
     uint32_t chunk_end, uold, unew;
+    uint32_t gpos[4], gn[4];  // the block's current group of leaves (one per wave)
 };
 
 __device__ __forceinline__ float load_emb(const FrameParams &fp, uint32_t pid, int comp)
@@ -613,6 +614,30 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+// Orders the wave's LDS accesses before the barrier ahead of those after it
+// (lanes of one wave exchanging data through LDS).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Eq. (1)-(2) with unit weights: the frame's n truncated distances are summed
+// in point order in binary64 (a voxel can gather thousands), and the running
+// mean is formed in binary64 before rounding to the stored binary32.
+__device__ __forceinline__ double tsdf_sum(const float *vals, uint32_t n)
+{
+    double sum_t = 0.0;
+    for (uint32_t q = 0; q < n; ++q) sum_t += (double)vals[q];
+    return sum_t;
+}
+
+__device__ __forceinline__ float tsdf_mean(float D0, float W0, float W1, double sum_t)
+{
+    return (float)(((double)W0 * (double)D0 + sum_t) / (double)W1);
+}
+
 // One voxel, one lane: its n observations sit at keys[0..n) / vals[0..n) in
 // point order.  Closed set with K <= KMAX classes in registers (KMAX = 0:
 // geometry only); ROWS: probability or logit rows, else int32 labels.  The
@@ -628,7 +653,6 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
     float acc[KA];
 #pragma unroll
     for (int k = 0; k < KA; ++k) acc[k] = 0.0f;
-    float sum_t = 0.0f;
     for (uint32_t c0 = 0; c0 < n; c0 += 8) {
         uint32_t kk[8];
 #pragma unroll
@@ -645,7 +669,6 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
         }
         for (int q = 0; q < 8; ++q) {
             if (c0 + q >= n) break;
-            sum_t += vals[c0 + q];
             if (KMAX > 0 && ROWS) {
                 const float *row = (const float *)fp.sem + (size_t)(kk[q] & kPidMask) * K;
                 float x[KA];
@@ -683,7 +706,7 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
     }
     // Eq. (1)-(2) with unit weights
     const float nf = (float)n, W0 = r[1], W1 = W0 + nf;
-    r[0] = (W0 * r[0] + sum_t) / W1;
+    r[0] = tsdf_mean(r[0], W0, W1, tsdf_sum(vals, n));
     r[1] = W1;
     // Eq. (6): concentrations grow by the (expected) class counts
 #pragma unroll
@@ -696,6 +719,102 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
 
 // One voxel, one wave: lane l owns components l, l + 64, ... of the open-set
 // statistics (L <= 1024) or of the class counts (K <= 1024).
+// Open-set row of observation pid, the V consecutive components lane * V ..
+// of an L = 64 V embedding, read as whole 4- to 16-byte words.
+template <int V>
+__device__ __forceinline__ void load_row(const FrameParams &fp, bool bf, uint32_t pid, int lane, float (&z)[V])
+{
+    if (bf) {
+        const uint16_t *row = (const uint16_t *)fp.sem + (size_t)pid * (64 * V) + lane * V;
+        if constexpr (V % 8 == 0) {
+#pragma unroll
+            for (int c = 0; c < V / 8; ++c) {
+                const uint4 u = ((const uint4 *)row)[c];
+                const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    z[8 * c + 2 * e] = __uint_as_float(w[e] << 16);
+                    z[8 * c + 2 * e + 1] = __uint_as_float(w[e] & 0xFFFF0000u);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < V / 2; ++e) {
+                const uint32_t w = ((const uint32_t *)row)[e];
+                z[2 * e] = __uint_as_float(w << 16);
+                z[2 * e + 1] = __uint_as_float(w & 0xFFFF0000u);
+            }
+        }
+    } else {
+        const float *row = (const float *)fp.sem + (size_t)pid * (64 * V) + lane * V;
+        if constexpr (V % 4 == 0) {
+#pragma unroll
+            for (int c = 0; c < V / 4; ++c) {
+                const float4 f = ((const float4 *)row)[c];
+                z[4 * c] = f.x;
+                z[4 * c + 1] = f.y;
+                z[4 * c + 2] = f.z;
+                z[4 * c + 3] = f.w;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) z[e] = row[e];
+        }
+    }
+}
+
+// Open set with L = 64 V, one wave per voxel: lane l owns components l V ..
+// l V + V - 1, so one observation's row is one or two wide loads per lane and
+// many observations are in flight at once.  Sums as in combine_wave.
+template <int V>
+__device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
+                                                 const float *vals, uint32_t n, long long rec, bool existed)
+{
+    constexpr int B = V >= 16 ? 4 : 8;
+    const int lane = lane_id();
+    const bool bf = fp.sem_kind == SLIM_IN_EMB_BF16;
+    float *R = md.vox + (size_t)rec * md.rec_stride;
+    const uint32_t p0 = keys[0] & kPidMask;
+    float z0[V], s1[V], s2[V];
+    load_row<V>(fp, bf, p0, lane, z0);
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        s1[i] = 0.0f;
+        s2[i] = 0.0f;
+    }
+    for (uint32_t q = 1; q < n; q += B) {
+        float z[B][V];
+#pragma unroll
+        for (int b = 0; b < B; ++b) load_row<V>(fp, bf, q + b < n ? keys[q + b] & kPidMask : p0, lane, z[b]);
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                const float d = z[b][i] - z0[i];  // 0 for the padding (the first row again)
+                s1[i] += d;
+                s2[i] += d * d;
+            }
+    }
+    // Eqs. (11)-(14) with lambda = W, nu = W / 2
+    const float nf = (float)n;
+    const float W0 = existed ? R[1] : 0.0f, W1 = W0 + nf, D0 = existed ? R[0] : 0.0f;
+    const float cross = W0 * nf / W1;
+    float *M = R + 2 + lane * V, *Bt = R + 2 + 64 * V + lane * V;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        const float zbar = z0[i] + s1[i] / nf;
+        const float scat = fmaxf(s2[i] - s1[i] * s1[i] / nf, 0.0f);
+        const float m0 = existed ? M[i] : 0.0f, b0 = existed ? Bt[i] : 0.0f;
+        const float dm = zbar - m0;
+        Bt[i] = b0 + 0.5f * scat + cross * dm * dm * 0.5f;
+        M[i] = (W0 * m0 + nf * zbar) / W1;
+    }
+    if (lane == 0) {
+        R[0] = tsdf_mean(D0, W0, W1, tsdf_sum(vals, n));
+        R[1] = W1;
+    }
+}
+
 constexpr int kWaveComps = 16;
 constexpr int kWaveBatch = 4;  // observations whose rows are in flight at once
 
@@ -718,8 +837,6 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
         s1[j] = 0.0f;
         s2[j] = 0.0f;
     }
-    float sum_t = 0.0f;
-    for (uint32_t q = 0; q < n; ++q) sum_t += vals[q];
     if (open) {
         float z0[kWaveComps];
         const uint32_t p0 = keys[0] & kPidMask;
@@ -816,8 +933,7 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
         }
     }
     if (lane == 0) {
-        // Eq. (1)-(2) with unit weights
-        R[0] = (W0 * D0 + sum_t) / W1;
+        R[0] = tsdf_mean(D0, W0, W1, tsdf_sum(vals, n));
         R[1] = W1;
     }
 }
@@ -825,13 +941,6 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
 // Non-Bayesian mode (SLIM-VDB*, Sec. IV): D and W as Eq. (1)-(2); the voxel's
 // semantics become those of its most recent measurement, the last pair in point
 // order (a ray visits a voxel at most once, so point indices are distinct).
-__device__ __forceinline__ float last_sum_tsdf(const float *vals, uint32_t n)
-{
-    float sum_t = 0.0f;
-    for (uint32_t q = 0; q < n; ++q) sum_t += vals[q];
-    return sum_t;
-}
-
 // Closed set, one lane per voxel: the class the measurement names -- its label,
 // or the first index of the largest probability or logit of its row.
 __device__ __forceinline__ void combine_last_lane(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
@@ -853,11 +962,10 @@ __device__ __forceinline__ void combine_last_lane(const FrameParams &fp, const M
             }
         }
     }
-    const float sum_t = last_sum_tsdf(vals, n);
     float4 *R = (float4 *)(md.vox + (size_t)rec * md.rec_stride);
     const float4 r = existed ? R[0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float nf = (float)n, W1 = r.y + nf;
-    R[0] = make_float4((r.y * r.x + sum_t) / W1, W1, (float)cls, 0.0f);
+    R[0] = make_float4(tsdf_mean(r.x, r.y, W1, tsdf_sum(vals, n)), W1, (float)cls, 0.0f);
 }
 
 // Open set, one wave per voxel: lane l copies components l, l + 64, ... of the
@@ -869,9 +977,8 @@ __device__ __forceinline__ void combine_last_wave(const FrameParams &fp, const M
     float *R = md.vox + (size_t)rec * md.rec_stride;
     for (int comp = lane_id(); comp < fp.L; comp += 64) R[2 + comp] = load_emb(fp, pid, comp);
     if (lane_id() == 0) {
-        const float sum_t = last_sum_tsdf(vals, n);
         const float W0 = existed ? R[1] : 0.0f, D0 = existed ? R[0] : 0.0f, W1 = W0 + (float)n;
-        R[0] = (W0 * D0 + sum_t) / W1;
+        R[0] = tsdf_mean(D0, W0, W1, tsdf_sum(vals, n));
         R[1] = W1;
     }
 }
@@ -905,6 +1012,9 @@ __device__ void combine_range(const FrameParams &fp, const MapDev &md, LeafShare
             const bool existed = (sh.occ0[o >> 5] >> (o & 31)) & 1u;
             if (KMAX < 0)
                 combine_last_wave(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base), n, rec, existed);
+            else if (KMAX > 0)  // wave kernels: KMAX is the components per lane of a word-aligned embedding
+                combine_wave_vec<(KMAX > 0 ? KMAX : 1)>(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base),
+                                                        n, rec, existed);
             else
                 combine_wave(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base), n, rec, existed);
         }
@@ -1120,12 +1230,143 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
         }
     }
     __syncthreads();
+    if (slab < 0 && tid == 0) {
+        // a whole-leaf item is the only reader of its staging entry: clean it
+        // for the next frame (the commit cleans those of split leaves)
+        md.skeys[pos] = kEmptyKey;
+        md.pos_count[pos] = 0u;
+        md.pos_slab[pos] = 0u;
+    }
+}
+
+// A touched leaf with at most kWaveItemPairs pairs is the work of one wave:
+// its pairs are sorted in the wave's quarter of the block's LDS by the full
+// key (offset, point index), which groups them by voxel in point order; lanes
+// then take one voxel each.  Waves run such leaves independently (no block
+// barrier), four per block.
+constexpr int kWaveItemPairs = 256;
+constexpr int kWaveLds = kLeafLdsPairs / 4;  // LDS pairs per wave
+static_assert(kWaveItemPairs <= kWaveLds, "a wave item must fit its LDS quarter");
+
+template <int KMAX, bool WAVE, bool ROWS>
+__device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapDev &md, LeafShared &sh,
+                                               uint32_t pos, uint32_t n, unsigned long long lused, bool ok)
+{
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t *wk = sh.a_key + w * kWaveLds;
+    float *wv = sh.a_val + w * kWaveLds;
+    uint32_t *seg = sh.b_key + w * kWaveLds;     // voxel segment starts
+    int32_t *wl = (int32_t *)sh.b_val + w * kWaveLds;  // labels of the sorted pairs
+    uint32_t *wt = sh.hist + w * 16;             // touched-offset mask (16 words)
+    uint32_t *wo = sh.bin0 + w * 16;             // occupancy words of the leaf before this frame
+    int *wp = (int *)sh.cur + w * 8;             // record pages of the leaf's slabs
+    const int4 plan = md.pos_plan[pos];
+    const int slot = plan.x >= 0 ? plan.x : (int)(lused + (unsigned long long)plan.y);
+    // power-of-two sort size >= n (at least one element per lane)
+    uint32_t m2 = 64;
+    while (m2 < n) m2 <<= 1;
+    const uint32_t per = m2 >> 6;
+    for (uint32_t q = 0; q < per; ++q) {
+        const uint32_t i = lane + 64 * q;
+        wk[i] = i < n ? md.srt_key[plan.z + i] : 0xFFFFFFFFu;  // padding sorts last
+        wv[i] = i < n ? md.srt_tsdf[plan.z + i] : 0.0f;
+    }
+    const uint32_t occ = (lane < kMaskWords && plan.x >= 0) ? md.leaf_occ[(size_t)plan.x * kMaskWords + lane] : 0u;
+    const int page = lane < kLeafPages ? ((const int *)md.pos_pages)[8 * (size_t)pos + lane] : -1;
+    if (lane < 16) {
+        wt[lane] = 0u;
+        wo[lane] = occ;
+    }
+    if (lane < kLeafPages) wp[lane] = page;
+    wave_sync();
+    // bitonic sort, ascending; each lane owns the lower element of its compare-exchanges
+    for (uint32_t k = 2; k <= m2; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t q = 0; q < (per >> 1) + (per == 1 ? 1u : 0u); ++q) {
+                // the m2 / 2 lower indices, spread over the lanes
+                const uint32_t t = lane + 64 * q;
+                if (t >= (m2 >> 1)) continue;
+                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // i has bit j clear
+                const uint32_t l = i | j;
+                const uint32_t a = wk[i], b = wk[l];
+                const bool up = (i & k) == 0;
+                if ((a > b) == up) {
+                    wk[i] = b;
+                    wk[l] = a;
+                    const float va = wv[i];
+                    wv[i] = wv[l];
+                    wv[l] = va;
+                }
+            }
+            wave_sync();
+        }
+    // voxel segments: starts where the offset changes
+    uint32_t nseg = 0;
+    for (uint32_t q = 0; q < per; ++q) {
+        const uint32_t i = lane + 64 * q;
+        const bool start = i < n && (i == 0 || (wk[i] >> kPidBits) != (wk[i - 1] >> kPidBits));
+        const unsigned long long b = __ballot(start);
+        if (start) seg[nseg + __popcll(b & ((1ull << lane) - 1ull))] = i;
+        nseg += (uint32_t)__popcll(b);
+    }
+    if (KMAX > 0 && !ROWS && !WAVE && ok)
+        for (uint32_t q = 0; q < per; ++q) {
+            const uint32_t i = lane + 64 * q;
+            if (i < n) wl[i] = ((const int32_t *)fp.sem)[wk[i] & kPidMask];
+        }
+    wave_sync();
+    for (uint32_t sgi = lane; sgi < nseg; sgi += 64) {
+        const uint32_t o = wk[seg[sgi]] >> kPidBits;
+        atomicOr(&wt[o >> 5], 1u << (o & 31));
+    }
+    wave_sync();
+    if (ok) {
+        for (uint32_t sgi = lane; sgi < nseg; sgi += 64) {
+            const uint32_t b0 = seg[sgi], b1 = sgi + 1 < nseg ? seg[sgi + 1] : n;
+            const uint32_t o = wk[b0] >> kPidBits;
+            const int pg = wp[o >> 6];
+            const uint32_t ow = wo[o >> 5];
+            const long long rec = (long long)pg * kPageVoxels + (o & (kPageVoxels - 1));
+            const bool existed = (ow >> (o & 31)) & 1u;
+            if (KMAX < 0)
+                combine_last_lane(fp, md, wk + b0, wv + b0, b1 - b0, rec, existed);
+            else
+                combine_lane<(KMAX < 0 ? 0 : KMAX), ROWS>(fp, md, wk + b0, wv + b0,
+                                                          (KMAX > 0 && !ROWS) ? wl + b0 : nullptr, b1 - b0, rec,
+                                                          existed);
+        }
+    }
+    // statistics and leaf bookkeeping
+    const uint32_t tw = lane < kMaskWords ? wt[lane] : 0u;
+    uint32_t uo = __popc(tw & occ), un = __popc(tw & ~occ);
+    for (int d = 32; d > 0; d >>= 1) {
+        uo += __shfl_xor(uo, d, 64);
+        un += __shfl_xor(un, d, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&sh.uold, uo);
+        atomicAdd(&sh.unew, un);
+    }
+    if (ok) {
+        if (lane == 0 && plan.x < 0) {
+            const unsigned long long key = md.skeys[pos];
+            map_insert(md, key, slot);
+            md.leaf_key[slot] = key;
+        }
+        if (lane < kLeafPages) md.leaf_page[(size_t)slot * kLeafPages + lane] = page;
+        if (lane < kMaskWords) md.leaf_occ[(size_t)slot * kMaskWords + lane] = occ | tw;
+    }
+    if (lane == 0) {
+        md.skeys[pos] = kEmptyKey;
+        md.pos_count[pos] = 0u;
+        md.pos_slab[pos] = 0u;
+    }
+    wave_sync();
 }
 
 // The leaf kernel's work of one map's frame for blocks blk, blk + nblk, ...:
 // first the slab items of large leaves (the longest work, started first), then
-// every other touched leaf whole.  Block statistics go to md.blk_stats[blk];
-// the staging entries are cleared by the commit.
+// every other touched leaf whole.  Block statistics go to md.blk_stats[blk].
 template <int KMAX, bool WAVE, bool ROWS>
 __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const MapDev &md, LeafShared &sh,
                                                 uint32_t blk, uint32_t nblk)
@@ -1140,14 +1381,34 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
         sh.uold = 0;
         sh.unew = 0;
     }
+    __syncthreads();
     for (uint32_t w = blk; w < nbig; w += nblk) {
         const int2 it = md.work[w];
         fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, (uint32_t)it.x, it.y, lused, ok);
     }
-    for (uint32_t j = blk; j < nt; j += nblk) {
-        const uint32_t pos = md.touched[j];
-        if (md.pos_count[pos] > (uint32_t)kLeafLdsPairs) continue;
-        fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, pos, -1, lused, ok);
+    // the other touched leaves: this block owns j = blk + nblk * i.  Four at a
+    // time: small ones go to one wave each, the rest are done block-wide after
+    // them.  A leaf's staging entry is read and cleared by its owner only.
+    const uint32_t w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (uint32_t base = blk; base < nt; base += nw * nblk) {
+        const uint32_t j = base + w * nblk;
+        uint32_t pos = 0, n = 0;
+        if (j < nt) {
+            pos = md.touched[j];
+            n = md.pos_count[pos];
+        }
+        if (lane_id() == 0) {
+            sh.gpos[w] = pos;
+            sh.gn[w] = (j < nt) ? n : 0u;
+        }
+        if (!WAVE && j < nt && n <= (uint32_t)kWaveItemPairs) fuse_wave_item<KMAX, WAVE, ROWS>(fp, md, sh, pos, n, lused, ok);
+        __syncthreads();
+        for (uint32_t q = 0; q < nw; ++q) {
+            const uint32_t nq = sh.gn[q];
+            if (nq == 0 || nq > (uint32_t)kLeafLdsPairs || (!WAVE && nq <= (uint32_t)kWaveItemPairs)) continue;
+            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, sh.gpos[q], -1, lused, ok);
+        }
+        __syncthreads();
     }
     __syncthreads();
     if (threadIdx.x == 0) md.blk_stats[blk] = make_uint2(sh.uold, sh.unew);
@@ -1181,10 +1442,11 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
 {
     __shared__ unsigned long long s_old[256], s_new[256];
     DevState *st = md.st;
-    // the staging entries of this frame are clean for the next one
-    const uint32_t nt = st->n_touched.v;
-    for (uint32_t j = threadIdx.x; j < nt; j += blockDim.x) {
-        const uint32_t pos = md.touched[j];
+    // the staging entries of leaves split into slab items are clean for the
+    // next frame (a leaf appears once per slab item; clearing twice is harmless)
+    const uint32_t nbig = min(st->work_big.v, md.work_cap);
+    for (uint32_t w = threadIdx.x; w < nbig; w += blockDim.x) {
+        const uint32_t pos = (uint32_t)md.work[w].x;
         md.skeys[pos] = kEmptyKey;
         md.pos_count[pos] = 0u;
         md.pos_slab[pos] = 0u;
@@ -1252,10 +1514,21 @@ __global__ __launch_bounds__(256) void k_frame_commit_batch(MapBatch mb)
 // Variant of the leaf kernel a frame needs: 0 geometry; 1..4 labels with
 // 8/16/24/32 classes in registers; 5..7 probability or logit rows with 8/16/32;
 // 8 one wave per voxel (open set, or more than 32 classes); 9 and 10 the
-// most-recent-measurement modes (closed: lane per voxel; open: wave per voxel).
+// most-recent-measurement modes (closed: lane per voxel; open: wave per voxel);
+// 11..15 the open set with L = 64, 128, 256, 512, 1024 read as whole words.
 int leaf_kernel_kind(const FrameParams &fp)
 {
     if (fp.last) return fp.L > 0 ? 10 : 9;
+    if (fp.L > 0 && (fp.L & 63) == 0 && ((uintptr_t)fp.sem & 15u) == 0) {
+        // embeddings whose rows split into whole 4- to 16-byte words per lane
+        const int v = fp.L >> 6;
+        const bool bf = fp.sem_kind == SLIM_IN_EMB_BF16;
+        if (v == 1 && !bf) return 11;
+        if (v == 2) return 12;
+        if (v == 4) return 13;
+        if (v == 8) return 14;
+        if (v == 16) return 15;
+    }
     if (fp.L > 0 || fp.K > 32) return 8;
     if (fp.K == 0) return 0;
     const bool rows = fp.sem_kind == SLIM_IN_PROB_F32 || fp.sem_kind == SLIM_IN_LOGIT_F32;
@@ -1277,6 +1550,11 @@ static void launch_leaf(int kind, const FrameParams &fp, const MapDev &md, int b
     case 7: hipLaunchKernelGGL((k_leaf_fuse<32, false, true>), gl, bl, 0, s, fp, md); break;
     case 9: hipLaunchKernelGGL((k_leaf_fuse<-1, false, false>), gl, bl, 0, s, fp, md); break;
     case 10: hipLaunchKernelGGL((k_leaf_fuse<-1, true, false>), gl, bl, 0, s, fp, md); break;
+    case 11: hipLaunchKernelGGL((k_leaf_fuse<1, true, false>), gl, bl, 0, s, fp, md); break;
+    case 12: hipLaunchKernelGGL((k_leaf_fuse<2, true, false>), gl, bl, 0, s, fp, md); break;
+    case 13: hipLaunchKernelGGL((k_leaf_fuse<4, true, false>), gl, bl, 0, s, fp, md); break;
+    case 14: hipLaunchKernelGGL((k_leaf_fuse<8, true, false>), gl, bl, 0, s, fp, md); break;
+    case 15: hipLaunchKernelGGL((k_leaf_fuse<16, true, false>), gl, bl, 0, s, fp, md); break;
     default: hipLaunchKernelGGL((k_leaf_fuse<0, true, false>), gl, bl, 0, s, fp, md); break;
     }
 }
@@ -1295,6 +1573,11 @@ static void launch_leaf_batch(int kind, const MapBatch &mb, int blocks, hipStrea
     case 7: hipLaunchKernelGGL((k_leaf_fuse_batch<32, false, true>), gl, bl, 0, s, mb); break;
     case 9: hipLaunchKernelGGL((k_leaf_fuse_batch<-1, false, false>), gl, bl, 0, s, mb); break;
     case 10: hipLaunchKernelGGL((k_leaf_fuse_batch<-1, true, false>), gl, bl, 0, s, mb); break;
+    case 11: hipLaunchKernelGGL((k_leaf_fuse_batch<1, true, false>), gl, bl, 0, s, mb); break;
+    case 12: hipLaunchKernelGGL((k_leaf_fuse_batch<2, true, false>), gl, bl, 0, s, mb); break;
+    case 13: hipLaunchKernelGGL((k_leaf_fuse_batch<4, true, false>), gl, bl, 0, s, mb); break;
+    case 14: hipLaunchKernelGGL((k_leaf_fuse_batch<8, true, false>), gl, bl, 0, s, mb); break;
+    case 15: hipLaunchKernelGGL((k_leaf_fuse_batch<16, true, false>), gl, bl, 0, s, mb); break;
     default: hipLaunchKernelGGL((k_leaf_fuse_batch<0, true, false>), gl, bl, 0, s, mb); break;
     }
 }
@@ -1837,7 +2120,7 @@ __global__ __launch_bounds__(256) void k_predict(const MapDev md, const PredictP
                 q2 = wave_sum(q2);
                 if (lane == 0) sims[wv][j] = dot / (nm * sqrtf(q2)) * pp.inv_temp;
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
             float mx = -INFINITY;
             for (int j = lane; j < pp.P; j += 64) mx = fmaxf(mx, sims[wv][j]);
             mx = wave_max(mx);
@@ -1852,7 +2135,7 @@ __global__ __launch_bounds__(256) void k_predict(const MapDev md, const PredictP
                     arg = j;
                 }
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
         } else if (open) {
             for (int j = lane; j < pp.P; j += 64)
                 if (prob) prob[q * pp.P + j] = 0.0f;

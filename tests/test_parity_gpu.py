@@ -105,6 +105,23 @@ def test_open_set(kind, L):
     _say(f"  errors {err}")
 
 
+@pytest.mark.parametrize("kind,L", [(sv.IN_EMB_BF16, 128), (sv.IN_EMB_F32, 64), (sv.IN_EMB_BF16, 256),
+                                    (sv.IN_EMB_F32, 256), (sv.IN_EMB_BF16, 512), (sv.IN_EMB_BF16, 1024)])
+def test_open_set_wide(kind, L):
+    """Embedding sizes that are multiples of 64 (rows read as whole words per lane)."""
+    _say(f"open set wide L={L} kind {kind}")
+    sc = synth.OpenRoomScene(seed=9, L=L, width=64, height=48, f=52.5, cx=31.5, cy=23.5, nboxes=12,
+                             deg_per_frame=8.0)
+    g, o = make_pair(0.05, 0.15, 0.0, 100.0, sv.SEM_OPEN, L=L)
+    for t in range(3):
+        fr = sc.frame(t)
+        z = fr["emb"] if kind == sv.IN_EMB_BF16 else synth.bf16_bits_to_float(fr["emb"]) * np.float32(0.999)
+        gst, ost = integrate_both(g, o, fr["points"], fr["pose"], z, kind)
+        assert_stats_equal(gst, ost)
+    err = compare_maps(extract_np(g), o.extract(), 0.15, sv.SEM_OPEN, L=L)
+    _say(f"  errors {err}")
+
+
 # ---------------------------------------------------------------------------
 # edge cases
 # ---------------------------------------------------------------------------
