@@ -97,6 +97,22 @@ struct LossParams {
     int32_t *part_cnt;       // block partial sample counts
 };
 
+// Everything the leaf kernel needs of one touched leaf, written by the plan
+// kernel at the leaf's index in the touched list, so that one 128-byte read
+// starts its work.
+struct alignas(16) LeafItem {
+    uint32_t pos;             // staging position
+    uint32_t n;               // pairs
+    uint32_t bstart;          // first pair of its bucket
+    int32_t slot;             // leaf slot, or -1 - (index among this frame's new leaves)
+    uint32_t slabs;           // x-slabs touched this frame (8 bits)
+    uint32_t pad;
+    unsigned long long key;   // packed leaf key
+    int32_t pages[8];         // record page of each slab (-1: none)
+    uint32_t occ[16];         // voxels with W > 0 before this frame
+};
+static_assert(sizeof(LeafItem) == 128, "a leaf item is 128 bytes");
+
 // Device pointers of one map.
 struct MapDev {
     // leaf table: packed leaf key -> leaf slot, open addressing, cap = hmask + 1
@@ -111,6 +127,7 @@ struct MapDev {
     uint32_t *pos_slab;  // x-slabs of the leaf the frame touches (8 bits)
     int4 *pos_plan;      // (slot or -1, new-leaf index, bucket start, 0)
     int4 *pos_pages;     // 2 per position: record page of each of the 8 slabs (-1: none)
+    LeafItem *items;     // per touched index: the leaf kernel's view of the leaf
     // leaves
     unsigned long long *leaf_key; // packed key per slot
     int32_t *leaf_page;           // 8 record pages per slot (-1: none)
@@ -126,10 +143,11 @@ struct MapDev {
     float *pair_tsdf;     // truncated signed distance (FP32)
     uint32_t *srt_key;    // pairs grouped by leaf
     float *srt_tsdf;
+    int32_t *srt_lab;     // int32 label of each bucketed pair (closed set with labels)
     uint32_t *tmp_key;    // scratch of large leaves: pairs binned by voxel offset
     float *tmp_tsdf;
     uint32_t pair_cap;
-    int2 *work;           // slab work items (staging position, slab) of large leaves
+    int2 *work;           // slab work items (touched index, slab) of large leaves
     uint32_t work_cap;
     uint2 *blk_stats;     // per leaf-kernel block: (voxels updated that existed, voxels created)
     int leaf_blocks;      // grid of the leaf kernel of the current frame (<= kMaxLeafBlocksPerCu * CUs)

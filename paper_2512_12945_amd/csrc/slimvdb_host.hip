@@ -178,8 +178,8 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s)
     size_t cap = std::max<size_t>(need, m->pair_cap + m->pair_cap / 2);
     cap = std::min<size_t>(cap, 0xFFFFFFF0ull);
     MapDev &md = m->md;
-    void *ptrs[9] = {md.pair_pos, md.pair_rank, md.pair_key, md.pair_tsdf, md.srt_key,
-                     md.srt_tsdf, md.tmp_key,   md.tmp_tsdf, md.work};
+    void *ptrs[10] = {md.pair_pos, md.pair_rank, md.pair_key, md.pair_tsdf, md.srt_key,
+                      md.srt_tsdf, md.srt_lab,  md.tmp_key,  md.tmp_tsdf,  md.work};
     for (void *p : ptrs) {
         if (!p) continue;
         (void)hipFree(p);
@@ -187,6 +187,7 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s)
     }
     md.pair_pos = md.pair_rank = md.pair_key = md.srt_key = md.tmp_key = nullptr;
     md.pair_tsdf = md.srt_tsdf = md.tmp_tsdf = nullptr;
+    md.srt_lab = nullptr;
     md.work = nullptr;
     // a large leaf has more than kLeafLdsPairs pairs and at most 8 slab items
     const size_t wcap = cap / (kLeafLdsPairs / kLeafPages) + kLeafPages;
@@ -194,7 +195,8 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s)
     if ((r = dalloc(m, &md.pair_pos, cap)) || (r = dalloc(m, &md.pair_rank, cap)) ||
         (r = dalloc(m, &md.pair_key, cap)) || (r = dalloc(m, &md.pair_tsdf, cap)) ||
         (r = dalloc(m, &md.srt_key, cap)) || (r = dalloc(m, &md.srt_tsdf, cap)) ||
-        (r = dalloc(m, &md.tmp_key, cap)) || (r = dalloc(m, &md.tmp_tsdf, cap)) ||
+        (r = dalloc(m, &md.srt_lab, cap)) || (r = dalloc(m, &md.tmp_key, cap)) ||
+        (r = dalloc(m, &md.tmp_tsdf, cap)) ||
         (r = dalloc(m, &md.work, wcap))) {
         m->pair_cap = 0;
         md.pair_cap = 0;
@@ -259,7 +261,7 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, config->device) == hipSuccess && prop.multiProcessorCount > 0)
         m->cus = prop.multiProcessorCount;
-    m->shape = {m->cus, m->cus * 16, m->cus * 8};
+    m->shape = {m->cus, m->cus * 16, m->cus * 16};
 
     MapDev &md = m->md;
     md.hmask = (uint32_t)(cap - 1);
@@ -271,7 +273,8 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
     if ((r = dalloc(m, &md.hkeys, cap)) || (r = dalloc(m, &md.hvals, cap)) || (r = dalloc(m, &md.skeys, cap)) ||
         (r = dalloc(m, &md.touched, cap)) || (r = dalloc(m, &md.pos_count, cap)) ||
         (r = dalloc(m, &md.pos_slab, cap)) || (r = dalloc(m, &md.pos_plan, cap)) ||
-        (r = dalloc(m, &md.pos_pages, 2 * cap)) || (r = dalloc(m, &md.leaf_key, L)) ||
+        (r = dalloc(m, &md.pos_pages, 2 * cap)) || (r = dalloc(m, &md.items, cap)) ||
+        (r = dalloc(m, &md.leaf_key, L)) ||
         (r = dalloc(m, &md.leaf_page, L * kLeafPages)) || (r = dalloc(m, &md.leaf_occ, L * kMaskWords)) ||
         (r = dalloc(m, &md.vox, NP * kPageVoxels * (size_t)md.rec_stride)) ||
         (r = dalloc(m, &md.blk_stats, (size_t)m->cus * kMaxLeafBlocksPerCu)) || (r = dalloc(m, &md.st, 1))) {
@@ -699,7 +702,7 @@ slim_status slim_set_launch_shape(slim_map *m, const slim_launch_shape *shape)
     g_err[0] = 0;
     if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
     if (!shape) {
-        m->shape = {m->cus, m->cus * 16, m->cus * 8};
+        m->shape = {m->cus, m->cus * 16, m->cus * 16};
         return SLIM_OK;
     }
     if (shape->plan_blocks < 1 || shape->bucket_blocks < 1 || shape->leaf_blocks_per_cu < 1 ||

@@ -129,6 +129,26 @@ __device__ __forceinline__ uint32_t wave_reserve(unsigned int *counter, uint32_t
     return base + incl - v;
 }
 
+// Four independent reservations at once (their atomics are in flight together).
+__device__ __forceinline__ void wave_reserve4(unsigned int *c0, unsigned int *c1, unsigned int *c2, unsigned int *c3,
+                                              const uint32_t (&v)[4], uint32_t (&out)[4])
+{
+    uint32_t incl[4], total[4], base[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        incl[q] = wave_incl_scan(v[q]);
+        total[q] = __shfl(incl[q], 63, 64);
+    }
+    if (lane_id() == 63) {
+        if (total[0]) base[0] = atomicAdd(c0, total[0]);
+        if (total[1]) base[1] = atomicAdd(c1, total[1]);
+        if (total[2]) base[2] = atomicAdd(c2, total[2]);
+        if (total[3]) base[3] = atomicAdd(c3, total[3]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = __shfl(base[q], 63, 64) + incl[q] - v[q];
+}
+
 // ---------------------------------------------------------------------------
 // geometry (binary32, fixed operation order)
 // ---------------------------------------------------------------------------
@@ -515,19 +535,21 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
             }
             need = md.pos_slab[pos] & ~have & 0xFFu;
         }
-        const uint32_t newleaf = wave_reserve(&md.st->new_leaves.v, (act && slot < 0) ? 1u : 0u);
-        const uint32_t pbase = wave_reserve(&md.st->new_pages.v, __popc(need));
-        const uint32_t bstart = wave_reserve(&md.st->pair_cursor.v, npairs);
         // a leaf with more pairs than the leaf kernel holds in LDS becomes one
         // work item per touched x-slab
         const uint32_t tslabs = act ? md.pos_slab[pos] & 0xFFu : 0u;
         const bool big = act && npairs > (uint32_t)kLeafLdsPairs;
-        const uint32_t ibase = wave_reserve(&md.st->work_big.v, big ? __popc(tslabs) : 0u);
+        const uint32_t want[4] = {(act && slot < 0) ? 1u : 0u, (uint32_t)__popc(need), npairs,
+                                  big ? (uint32_t)__popc(tslabs) : 0u};
+        uint32_t got[4];
+        wave_reserve4(&md.st->new_leaves.v, &md.st->new_pages.v, &md.st->pair_cursor.v, &md.st->work_big.v, want,
+                      got);
+        const uint32_t newleaf = got[0], pbase = got[1], bstart = got[2], ibase = got[3];
         if (big) {
             uint32_t r = 0;
             for (int q = 0; q < kLeafPages; ++q)
                 if ((tslabs >> q) & 1u) {
-                    if (ibase + r < md.work_cap) md.work[ibase + r] = make_int2((int)pos, q);
+                    if (ibase + r < md.work_cap) md.work[ibase + r] = make_int2((int)j, q);
                     else atomicOr(&md.st->frame_err.v, 1u);
                     r++;
                 }
@@ -540,6 +562,16 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
             md.pos_pages[2 * pos] = make_int4(pg[0], pg[1], pg[2], pg[3]);
             md.pos_pages[2 * pos + 1] = make_int4(pg[4], pg[5], pg[6], pg[7]);
             md.pos_plan[pos] = make_int4(slot, slot < 0 ? (int)newleaf : -1, (int)bstart, 0);
+            // the leaf kernel's item: header, pages, occupancy before this frame
+            uint4 *it = (uint4 *)&md.items[j];
+            const unsigned long long key = md.skeys[pos];
+            it[0] = make_uint4(pos, npairs, bstart, (uint32_t)(slot >= 0 ? slot : -1 - (int)newleaf));
+            it[1] = make_uint4(tslabs, 0u, (uint32_t)key, (uint32_t)(key >> 32));
+            it[2] = make_uint4((uint32_t)pg[0], (uint32_t)pg[1], (uint32_t)pg[2], (uint32_t)pg[3]);
+            it[3] = make_uint4((uint32_t)pg[4], (uint32_t)pg[5], (uint32_t)pg[6], (uint32_t)pg[7]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                it[4 + q] = slot >= 0 ? ((const uint4 *)md.leaf_occ)[(size_t)slot * 4 + q] : make_uint4(0u, 0u, 0u, 0u);
         }
     }
 }
@@ -558,27 +590,32 @@ __global__ __launch_bounds__(256) void k_leaf_plan_batch(MapBatch mb)
 // 3. pair bucketing
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void pair_bucket_range(const MapDev &md, uint32_t blk, uint32_t nblk)
+__device__ __forceinline__ void pair_bucket_range(const FrameParams &fp, const MapDev &md, uint32_t blk,
+                                                  uint32_t nblk)
 {
     const uint32_t P = min(md.st->pairs.v, md.pair_cap);
     const uint32_t stride = nblk * blockDim.x;
+    const bool labels = fp.K > 0 && fp.sem_kind == SLIM_IN_LABEL_I32;
     for (uint32_t i = blk * blockDim.x + threadIdx.x; i < P; i += stride) {
         const uint32_t pos = md.pair_pos[i];
         if (pos == kNoPos) continue;
         const uint32_t dst = (uint32_t)md.pos_plan[pos].z + md.pair_rank[i];
-        md.srt_key[dst] = md.pair_key[i];
+        const uint32_t key = md.pair_key[i];
+        md.srt_key[dst] = key;
         md.srt_tsdf[dst] = md.pair_tsdf[i];
+        // the leaf kernel's small items find the label beside the pair
+        if (labels) md.srt_lab[dst] = ((const int32_t *)fp.sem)[key & kPidMask];
     }
 }
 
-__global__ __launch_bounds__(256) void k_pair_bucket(MapDev md)
+__global__ __launch_bounds__(256) void k_pair_bucket(FrameParams fp, MapDev md)
 {
-    pair_bucket_range(md, blockIdx.x, gridDim.x);
+    pair_bucket_range(fp, md, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void k_pair_bucket_batch(MapBatch mb)
 {
-    for (int i = 0; i < mb.nmaps; ++i) pair_bucket_range(mb.mds[i], blockIdx.x, gridDim.x);
+    for (int i = 0; i < mb.nmaps; ++i) pair_bucket_range(mb.fps[i], mb.mds[i], blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -592,7 +629,8 @@ struct LeafShared {
     uint32_t touch[kMaskWords], occ0[kMaskWords], wsum[4];
     int pages[kLeafPages];
     uint32_t chunk_end, uold, unew;
-    uint32_t gpos[4], gn[4];  // the block's current group of leaves (one per wave)
+    uint32_t gn[4];           // pairs of the block's current group of leaves (one per wave)
+    uint32_t item[32];        // the current block item
 };
 
 __device__ __forceinline__ float load_emb(const FrameParams &fp, uint32_t pid, int comp)
@@ -1038,30 +1076,31 @@ __device__ __forceinline__ void rank_bins(LeafShared &sh, KP bk, VP bv, uint32_t
     }
 }
 
-// One work item of the leaf kernel: the touched leaf at staging position pos,
-// all of it (slab < 0) or, for a leaf with more pairs than LDS holds, the
-// voxels of one x-slab (offsets 64 slab .. 64 slab + 63), so that the slabs
-// of a large leaf run in different workgroups.  Reads every pair of the leaf
-// for the offset histogram, keeps those of its offsets, orders them by point
-// index inside each voxel and combines the voxels.
+// One work item of the leaf kernel: the touched leaf of touched index j, all
+// of it (slab < 0) or, for a leaf with more pairs than LDS holds, the voxels
+// of one x-slab (offsets 64 slab .. 64 slab + 63), so that the slabs of a
+// large leaf run in different workgroups.  Reads every pair of the leaf for
+// the offset histogram, keeps those of its offsets, orders them by point index
+// inside each voxel and combines the voxels.
 template <int KMAX, bool WAVE, bool ROWS>
-__device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &md, LeafShared &sh, uint32_t pos,
+__device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &md, LeafShared &sh, uint32_t j,
                                           int slab, unsigned long long lused, bool ok)
 {
     const int tid = threadIdx.x;
-    const int4 plan = md.pos_plan[pos];
-    const uint32_t n = md.pos_count[pos];
-    const int slot = plan.x >= 0 ? plan.x : (int)(lused + (unsigned long long)plan.y);
-    const uint32_t ob = slab < 0 ? 0u : 64u * (uint32_t)slab, oe = slab < 0 ? (uint32_t)kLeafVoxels : ob + 64u;
+    if (tid < 32) sh.item[tid] = ((const uint32_t *)&md.items[j])[tid];
     for (int o = tid; o < kLeafVoxels; o += blockDim.x) sh.hist[o] = 0;
-    if (tid < kMaskWords) sh.occ0[tid] = plan.x >= 0 ? md.leaf_occ[(size_t)plan.x * kMaskWords + tid] : 0u;
-    if (tid < kLeafPages) sh.pages[tid] = ((const int *)md.pos_pages)[8 * (size_t)pos + tid];
     __syncthreads();
+    const uint32_t pos = sh.item[0], n = sh.item[1], bstart = sh.item[2];
+    const int islot = (int)sh.item[3];
+    const int slot = islot >= 0 ? islot : (int)(lused + (unsigned long long)(-1 - islot));
+    const uint32_t ob = slab < 0 ? 0u : 64u * (uint32_t)slab, oe = slab < 0 ? (uint32_t)kLeafVoxels : ob + 64u;
+    if (tid < kMaskWords) sh.occ0[tid] = sh.item[16 + tid];
+    if (tid < kLeafPages) sh.pages[tid] = (int)sh.item[8 + tid];
 
-    const uint32_t *gk = md.srt_key + plan.z;
-    const float *gv = md.srt_tsdf + plan.z;
-    uint32_t *tk = md.tmp_key + plan.z;
-    float *tv = md.tmp_tsdf + plan.z;
+    const uint32_t *gk = md.srt_key + bstart;
+    const float *gv = md.srt_tsdf + bstart;
+    uint32_t *tk = md.tmp_key + bstart;
+    float *tv = md.tmp_tsdf + bstart;
     const bool whole_small = slab < 0 && n <= (uint32_t)kLeafLdsPairs;
 
     // histogram of the voxel offsets of every pair of the leaf; kLeafBatch loads
@@ -1179,8 +1218,8 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
             // one bin larger than LDS: order it into the walk's pair buffers
             // (consumed by the bucketing, free now), at the bin's own range of
             // the leaf's bucket, which no other item touches
-            uint32_t *bk = md.pair_key + plan.z;
-            float *bv = md.pair_tsdf + plan.z;
+            uint32_t *bk = md.pair_key + bstart;
+            float *bv = md.pair_tsdf + bstart;
             for (uint32_t t = lo + tid; t < hi; t += blockDim.x) {
                 const uint32_t k = tk[t];
                 uint32_t r = 0;
@@ -1200,8 +1239,8 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
         }
         if (ok) {
             // sorted pairs of bin o sit at keys[bin0[o] - base]
-            const uint32_t *ck = fits ? sh.a_key : md.pair_key + plan.z;
-            const float *cv = fits ? sh.a_val : md.pair_tsdf + plan.z;
+            const uint32_t *ck = fits ? sh.a_key : md.pair_key + bstart;
+            const float *cv = fits ? sh.a_val : md.pair_tsdf + bstart;
             combine_range<KMAX, WAVE, ROWS>(fp, md, sh, ck, cv, labs, o0, o1, fits ? lo : 0u);
         }
         __syncthreads();
@@ -1212,10 +1251,10 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
     // its offsets; the item of the leaf's lowest touched slab (or the whole-leaf
     // item) also inserts a new leaf and writes the entries of untouched slabs
     if (ok) {
-        const uint32_t tslabs = md.pos_slab[pos] & 0xFFu;
+        const uint32_t tslabs = sh.item[4] & 0xFFu;
         const bool lead = slab < 0 || (uint32_t)slab == (uint32_t)(__ffs(tslabs) - 1);
-        if (tid == 0 && lead && plan.x < 0) {
-            const unsigned long long key = md.skeys[pos];
+        if (tid == 0 && lead && islot < 0) {
+            const unsigned long long key = ((unsigned long long)sh.item[7] << 32) | sh.item[6];
             map_insert(md, key, slot);
             md.leaf_key[slot] = key;
         }
@@ -1230,17 +1269,21 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
         }
     }
     __syncthreads();
-    if (slab < 0 && tid == 0) {
-        // a whole-leaf item is the only reader of its staging entry: clean it
-        // for the next frame (the commit cleans those of split leaves)
-        md.skeys[pos] = kEmptyKey;
-        md.pos_count[pos] = 0u;
-        md.pos_slab[pos] = 0u;
+    if (tid == 0) {
+        // the staging entry is clean for the next frame once the leaf's last
+        // item is done (a whole-leaf item is the only one; slab items count
+        // themselves in the item's spare word, which the plan kernel zeroes)
+        const bool last = slab < 0 || atomicAdd(&md.items[j].pad, 1u) + 1u == (uint32_t)__popc(sh.item[4] & 0xFFu);
+        if (last) {
+            md.skeys[pos] = kEmptyKey;
+            md.pos_count[pos] = 0u;
+            md.pos_slab[pos] = 0u;
+        }
     }
 }
 
 // A touched leaf with at most kWaveItemPairs pairs is the work of one wave:
-// its pairs are sorted in the wave's quarter of the block's LDS by the full
+// its pairs are ordered in the wave's quarter of the block's LDS by the full
 // key (offset, point index), which groups them by voxel in point order; lanes
 // then take one voxel each.  Waves run such leaves independently (no block
 // barrier), four per block.
@@ -1250,7 +1293,7 @@ static_assert(kWaveItemPairs <= kWaveLds, "a wave item must fit its LDS quarter"
 
 template <int KMAX, bool WAVE, bool ROWS>
 __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapDev &md, LeafShared &sh,
-                                               uint32_t pos, uint32_t n, unsigned long long lused, bool ok)
+                                               uint32_t j, unsigned long long lused, bool ok)
 {
     const int lane = lane_id(), w = threadIdx.x >> 6;
     uint32_t *wk = sh.a_key + w * kWaveLds;
@@ -1260,48 +1303,57 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
     uint32_t *wt = sh.hist + w * 16;             // touched-offset mask (16 words)
     uint32_t *wo = sh.bin0 + w * 16;             // occupancy words of the leaf before this frame
     int *wp = (int *)sh.cur + w * 8;             // record pages of the leaf's slabs
-    const int4 plan = md.pos_plan[pos];
-    const int slot = plan.x >= 0 ? plan.x : (int)(lused + (unsigned long long)plan.y);
-    // power-of-two sort size >= n (at least one element per lane)
-    uint32_t m2 = 64;
-    while (m2 < n) m2 <<= 1;
-    const uint32_t per = m2 >> 6;
-    for (uint32_t q = 0; q < per; ++q) {
+    uint32_t *wi = sh.cur + 64 + w * 32;         // the leaf's item
+    if (lane < 32) wi[lane] = ((const uint32_t *)&md.items[j])[lane];
+    wave_sync();
+    const uint32_t pos = wi[0], n = wi[1], bstart = wi[2];
+    const int islot = (int)wi[3];
+    const int slot = islot >= 0 ? islot : (int)(lused + (unsigned long long)(-1 - islot));
+    const bool labels = KMAX > 0 && !ROWS && !WAVE;
+    // the pairs in registers (four per lane), their keys also in LDS; keys are
+    // distinct (a ray visits a voxel once), so a pair's rank is the number of
+    // smaller keys, and writing each pair at its rank sorts them by (offset,
+    // point index)
+    uint32_t *uk = sh.b_key + w * kWaveLds;  // unsorted keys, padded to a multiple of 4
+    uint32_t kq[4];
+    float vq[4];
+    int32_t lq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
         const uint32_t i = lane + 64 * q;
-        wk[i] = i < n ? md.srt_key[plan.z + i] : 0xFFFFFFFFu;  // padding sorts last
-        wv[i] = i < n ? md.srt_tsdf[plan.z + i] : 0.0f;
+        const bool has = i < n;
+        kq[q] = has ? md.srt_key[bstart + i] : 0xFFFFFFFFu;
+        vq[q] = has ? md.srt_tsdf[bstart + i] : 0.0f;
+        lq[q] = (has && labels) ? md.srt_lab[bstart + i] : 0;
+        if (i < ((n + 3u) & ~3u)) uk[i] = kq[q];
     }
-    const uint32_t occ = (lane < kMaskWords && plan.x >= 0) ? md.leaf_occ[(size_t)plan.x * kMaskWords + lane] : 0u;
-    const int page = lane < kLeafPages ? ((const int *)md.pos_pages)[8 * (size_t)pos + lane] : -1;
+    const uint32_t occ = lane < kMaskWords ? wi[16 + lane] : 0u;
+    const int page = lane < kLeafPages ? (int)wi[8 + lane] : -1;
     if (lane < 16) {
         wt[lane] = 0u;
         wo[lane] = occ;
     }
     if (lane < kLeafPages) wp[lane] = page;
     wave_sync();
-    // bitonic sort, ascending; each lane owns the lower element of its compare-exchanges
-    for (uint32_t k = 2; k <= m2; k <<= 1)
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t q = 0; q < (per >> 1) + (per == 1 ? 1u : 0u); ++q) {
-                // the m2 / 2 lower indices, spread over the lanes
-                const uint32_t t = lane + 64 * q;
-                if (t >= (m2 >> 1)) continue;
-                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));  // i has bit j clear
-                const uint32_t l = i | j;
-                const uint32_t a = wk[i], b = wk[l];
-                const bool up = (i & k) == 0;
-                if ((a > b) == up) {
-                    wk[i] = b;
-                    wk[l] = a;
-                    const float va = wv[i];
-                    wv[i] = wv[l];
-                    wv[l] = va;
-                }
-            }
-            wave_sync();
+    uint32_t rq[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t s4 = 0; s4 < n; s4 += 4) {
+        const uint4 c = *(const uint4 *)(uk + s4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            rq[q] += (uint32_t)(c.x < kq[q]) + (uint32_t)(c.y < kq[q]) + (uint32_t)(c.z < kq[q]) +
+                     (uint32_t)(c.w < kq[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (lane + 64 * q < n) {
+            wk[rq[q]] = kq[q];
+            wv[rq[q]] = vq[q];
+            wl[rq[q]] = lq[q];
         }
+    wave_sync();
     // voxel segments: starts where the offset changes
     uint32_t nseg = 0;
+    const uint32_t per = (n + 63u) >> 6;
     for (uint32_t q = 0; q < per; ++q) {
         const uint32_t i = lane + 64 * q;
         const bool start = i < n && (i == 0 || (wk[i] >> kPidBits) != (wk[i - 1] >> kPidBits));
@@ -1309,11 +1361,6 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
         if (start) seg[nseg + __popcll(b & ((1ull << lane) - 1ull))] = i;
         nseg += (uint32_t)__popcll(b);
     }
-    if (KMAX > 0 && !ROWS && !WAVE && ok)
-        for (uint32_t q = 0; q < per; ++q) {
-            const uint32_t i = lane + 64 * q;
-            if (i < n) wl[i] = ((const int32_t *)fp.sem)[wk[i] & kPidMask];
-        }
     wave_sync();
     for (uint32_t sgi = lane; sgi < nseg; sgi += 64) {
         const uint32_t o = wk[seg[sgi]] >> kPidBits;
@@ -1331,9 +1378,8 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
             if (KMAX < 0)
                 combine_last_lane(fp, md, wk + b0, wv + b0, b1 - b0, rec, existed);
             else
-                combine_lane<(KMAX < 0 ? 0 : KMAX), ROWS>(fp, md, wk + b0, wv + b0,
-                                                          (KMAX > 0 && !ROWS) ? wl + b0 : nullptr, b1 - b0, rec,
-                                                          existed);
+                combine_lane<(KMAX < 0 ? 0 : KMAX), ROWS>(fp, md, wk + b0, wv + b0, labels ? wl + b0 : nullptr,
+                                                          b1 - b0, rec, existed);
         }
     }
     // statistics and leaf bookkeeping
@@ -1348,8 +1394,8 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
         atomicAdd(&sh.unew, un);
     }
     if (ok) {
-        if (lane == 0 && plan.x < 0) {
-            const unsigned long long key = md.skeys[pos];
+        if (lane == 0 && islot < 0) {
+            const unsigned long long key = ((unsigned long long)wi[7] << 32) | wi[6];
             map_insert(md, key, slot);
             md.leaf_key[slot] = key;
         }
@@ -1392,21 +1438,14 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
     const uint32_t w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (uint32_t base = blk; base < nt; base += nw * nblk) {
         const uint32_t j = base + w * nblk;
-        uint32_t pos = 0, n = 0;
-        if (j < nt) {
-            pos = md.touched[j];
-            n = md.pos_count[pos];
-        }
-        if (lane_id() == 0) {
-            sh.gpos[w] = pos;
-            sh.gn[w] = (j < nt) ? n : 0u;
-        }
-        if (!WAVE && j < nt && n <= (uint32_t)kWaveItemPairs) fuse_wave_item<KMAX, WAVE, ROWS>(fp, md, sh, pos, n, lused, ok);
+        const uint32_t n = j < nt ? md.items[j].n : 0u;
+        if (lane_id() == 0) sh.gn[w] = n;
+        if (!WAVE && n > 0 && n <= (uint32_t)kWaveItemPairs) fuse_wave_item<KMAX, WAVE, ROWS>(fp, md, sh, j, lused, ok);
         __syncthreads();
         for (uint32_t q = 0; q < nw; ++q) {
             const uint32_t nq = sh.gn[q];
             if (nq == 0 || nq > (uint32_t)kLeafLdsPairs || (!WAVE && nq <= (uint32_t)kWaveItemPairs)) continue;
-            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, sh.gpos[q], -1, lused, ok);
+            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, base + q * nblk, -1, lused, ok);
         }
         __syncthreads();
     }
@@ -1416,7 +1455,7 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
 }
 
 template <int KMAX, bool WAVE, bool ROWS>
-__global__ __launch_bounds__(kLeafThreads) void k_leaf_fuse(FrameParams fp, MapDev md)
+__global__ __launch_bounds__(kLeafThreads, WAVE ? 1 : 4) void k_leaf_fuse(FrameParams fp, MapDev md)
 {
     __shared__ LeafShared sh;
     leaf_fuse_range<KMAX, WAVE, ROWS>(fp, md, sh, blockIdx.x, gridDim.x);
@@ -1442,20 +1481,19 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
 {
     __shared__ unsigned long long s_old[256], s_new[256];
     DevState *st = md.st;
-    // the staging entries of leaves split into slab items are clean for the
-    // next frame (a leaf appears once per slab item; clearing twice is harmless)
-    const uint32_t nbig = min(st->work_big.v, md.work_cap);
-    for (uint32_t w = threadIdx.x; w < nbig; w += blockDim.x) {
-        const uint32_t pos = (uint32_t)md.work[w].x;
-        md.skeys[pos] = kEmptyKey;
-        md.pos_count[pos] = 0u;
-        md.pos_slab[pos] = 0u;
-    }
     unsigned long long uo = 0, un = 0;
-    for (int b = threadIdx.x; b < md.leaf_blocks; b += blockDim.x) {
-        const uint2 v = md.blk_stats[b];
-        uo += v.x;
-        un += v.y;
+    for (int b0 = threadIdx.x; b0 < md.leaf_blocks; b0 += 8 * blockDim.x) {
+        uint2 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int b = b0 + q * blockDim.x;
+            v[q] = b < md.leaf_blocks ? md.blk_stats[b] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            uo += v[q].x;
+            un += v[q].y;
+        }
     }
     s_old[threadIdx.x] = uo;
     s_new[threadIdx.x] = un;
@@ -1600,7 +1638,7 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const La
     rec(4);
     const long long want = ((long long)fp.n * fp.maxsteps + 255) / 256;
     const int bb = (int)std::max<long long>(1, std::min<long long>(want, shape.bucket_blocks));
-    hipLaunchKernelGGL(k_pair_bucket, dim3(bb), dim3(256), 0, s, md);
+    hipLaunchKernelGGL(k_pair_bucket, dim3(bb), dim3(256), 0, s, fp, md);
     rec(5);
     rec(6);
     launch_leaf(leaf_kernel_kind(fp), fp, md, shape.leaf_blocks, s);
