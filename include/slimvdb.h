@@ -267,6 +267,15 @@ typedef struct slim_frame {
 slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const slim_frame *frames, int32_t use_graph,
                                    void *stream);
 
+/* Integrates `count` frames into one map, in order: the result is the same as
+ * count calls of slim_integrate / slim_integrate_rays (bit for bit), but the
+ * ray walk of frame t + 1 runs on an internal stream beside the rest of frame t
+ * (a second staging buffer makes them independent; the walk reads no map
+ * state).  Every frame's inputs must be ready in `stream` order when the call
+ * is made.  frames[i] as for slim_integrate_batched.  Queued on `stream`;
+ * kernel timing (slim_profile_enable) covers single-frame calls only. */
+slim_status slim_integrate_sequence(slim_map *map, const slim_frame *frames_host, int32_t count, void *stream);
+
 /* Grid sizes of the grid-stride kernels of integration: leaf planning and pair
  * bucketing blocks, and leaf-kernel blocks per compute unit (1 .. 32).  Results
  * do not depend on them (each voxel is reduced in point order); they only move

@@ -38,10 +38,9 @@ struct alignas(128) Line {
     unsigned int pad[31];
 };
 
-// Device-resident counters of one map.  Frame counters are zero between
-// frames: the commit kernel clears them.
-struct DevState {
-    // frame counters
+// Counters of the frame in flight on one staging buffer.  They are zero
+// between frames: the commit kernel clears them.
+struct FrameState {
     Line pairs;       // (voxel, point) observations emitted
     Line n_touched;   // leaves touched (staging-table entries)
     Line rejected;    // points rejected
@@ -50,7 +49,10 @@ struct DevState {
     Line pair_cursor; // bucket allocation cursor
     Line work_big;    // slab work items of large leaves
     Line frame_err;   // nonzero: do not apply this frame
-    // persistent
+};
+
+// Device-resident counters of one map.
+struct DevState {
     unsigned long long leaves_used;
     unsigned long long pages_used;
     unsigned long long voxels_used;  // voxels with W > 0
@@ -152,6 +154,7 @@ struct MapDev {
     uint2 *blk_stats;     // per leaf-kernel block: (voxels updated that existed, voxels created)
     int leaf_blocks;      // grid of the leaf kernel of the current frame (<= kMaxLeafBlocksPerCu * CUs)
     DevState *st;
+    FrameState *fs;       // the staging buffer's frame counters
     long long max_leaves, max_pages;
 };
 
@@ -197,6 +200,9 @@ __host__ __device__ inline unsigned long long pack_leaf(int lx, int ly, int lz)
 hipError_t launch_integrate(const FrameParams &fp, const MapDev &md, const LaunchShape &shape, hipStream_t s,
                             hipEvent_t *ev /* 2 * kNumProfiled events or nullptr */);
 hipError_t launch_reset(const MapDev &md, hipStream_t s);
+hipError_t launch_reset_staging(const MapDev &md, hipStream_t s);
+hipError_t launch_walk(const FrameParams &fp, const MapDev &md, hipStream_t s);
+hipError_t launch_after_walk(const FrameParams &fp, const MapDev &md, const LaunchShape &shape, hipStream_t s);
 hipError_t launch_loss(const FrameParams &fp, const MapDev &md, const LossParams &lp, hipStream_t s);
 hipError_t launch_backward(const FrameParams &fp, const MapDev &md, const LossParams &lp, const float *grad_scale,
                            float *grad_logits, float *grad_ranges, hipStream_t s);

@@ -78,6 +78,14 @@ struct slim_map {
     MapDev md = {};
     size_t hcap = 0;
     size_t pair_cap = 0;
+    // second staging buffer and walk stream of slim_integrate_sequence: the
+    // walk of frame t + 1 runs beside the rest of frame t
+    MapDev md1 = {};
+    bool have1 = false;
+    size_t pair_cap1 = 0;
+    hipStream_t wstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_free[2] = {nullptr, nullptr}, ev_walk[2] = {nullptr, nullptr};
+    bool used[2] = {false, false};
     // extraction scratch
     unsigned long long *ext_keys = nullptr;
     int32_t *ext_slots = nullptr;
@@ -130,6 +138,12 @@ void free_batch(slim_map *m)
 void free_all(slim_map *m)
 {
     free_batch(m);
+    if (m->wstream) (void)hipStreamDestroy(m->wstream);
+    m->wstream = nullptr;
+    for (hipEvent_t *e : {&m->ev_in, &m->ev_free[0], &m->ev_free[1], &m->ev_walk[0], &m->ev_walk[1]}) {
+        if (*e) (void)hipEventDestroy(*e);
+        *e = nullptr;
+    }
     for (void *p : m->allocs) (void)hipFree(p);
     m->allocs.clear();
     for (hipEvent_t e : m->ev) (void)hipEventDestroy(e);
@@ -170,14 +184,16 @@ int max_steps(float vs, float tau)
     return 3 * (int)std::ceil((2.0 * (double)tau) / (double)vs) + 4;
 }
 
-slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s)
+slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s, int buf = 0)
 {
-    if (need <= m->pair_cap) return SLIM_OK;
+    size_t &pcap = buf ? m->pair_cap1 : m->pair_cap;
+    if (need <= pcap) return SLIM_OK;
     if (need > 0xFFFFFFF0ull) return fail(SLIM_ERR_INVALID, "frame needs more than 2^32 pair slots");
     HIP_OK(hipStreamSynchronize(s));
-    size_t cap = std::max<size_t>(need, m->pair_cap + m->pair_cap / 2);
+    if (m->wstream) HIP_OK(hipStreamSynchronize(m->wstream));
+    size_t cap = std::max<size_t>(need, pcap + pcap / 2);
     cap = std::min<size_t>(cap, 0xFFFFFFF0ull);
-    MapDev &md = m->md;
+    MapDev &md = buf ? m->md1 : m->md;
     void *ptrs[10] = {md.pair_pos, md.pair_rank, md.pair_key, md.pair_tsdf, md.srt_key,
                       md.srt_tsdf, md.srt_lab,  md.tmp_key,  md.tmp_tsdf,  md.work};
     for (void *p : ptrs) {
@@ -198,12 +214,12 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s)
         (r = dalloc(m, &md.srt_lab, cap)) || (r = dalloc(m, &md.tmp_key, cap)) ||
         (r = dalloc(m, &md.tmp_tsdf, cap)) ||
         (r = dalloc(m, &md.work, wcap))) {
-        m->pair_cap = 0;
+        pcap = 0;
         md.pair_cap = 0;
         md.work_cap = 0;
         return r;
     }
-    m->pair_cap = cap;
+    pcap = cap;
     md.pair_cap = (uint32_t)cap;
     md.work_cap = (uint32_t)wcap;
     return SLIM_OK;
@@ -277,7 +293,8 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
         (r = dalloc(m, &md.leaf_key, L)) ||
         (r = dalloc(m, &md.leaf_page, L * kLeafPages)) || (r = dalloc(m, &md.leaf_occ, L * kMaskWords)) ||
         (r = dalloc(m, &md.vox, NP * kPageVoxels * (size_t)md.rec_stride)) ||
-        (r = dalloc(m, &md.blk_stats, (size_t)m->cus * kMaxLeafBlocksPerCu)) || (r = dalloc(m, &md.st, 1))) {
+        (r = dalloc(m, &md.blk_stats, (size_t)m->cus * kMaxLeafBlocksPerCu)) || (r = dalloc(m, &md.st, 1)) ||
+        (r = dalloc(m, &md.fs, 1))) {
         free_all(m);
         delete m;
         return r;
@@ -310,6 +327,13 @@ slim_status slim_map_reset(slim_map *m, void *stream)
     if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
     DeviceGuard g(m->cfg.device);
     HIP_OK(launch_reset(m->md, (hipStream_t)stream));
+    if (m->have1) {
+        // the second buffer's last walk and commit are done before it is cleared
+        if (m->used[1]) HIP_OK(hipStreamWaitEvent((hipStream_t)stream, m->ev_free[1], 0));
+        HIP_OK(launch_reset_staging(m->md1, (hipStream_t)stream));
+        HIP_OK(hipEventRecord(m->ev_free[1], (hipStream_t)stream));
+        m->used[1] = true;
+    }
     return SLIM_OK;
 }
 
@@ -402,9 +426,85 @@ slim_status integrate_frame(slim_map *m, const FrameParams &fp, void *stream)
     return SLIM_OK;
 }
 
+// The second staging buffer: its own staging table, counts, plans, items and
+// frame counters (pair buffers come from ensure_pairs), the map's arrays shared.
+slim_status ensure_buffer1(slim_map *m, hipStream_t s)
+{
+    if (m->have1) return SLIM_OK;
+    MapDev md = m->md;
+    md.skeys = nullptr;
+    md.touched = md.pos_count = md.pos_slab = nullptr;
+    md.pos_plan = md.pos_pages = nullptr;
+    md.items = nullptr;
+    md.fs = nullptr;
+    md.pair_pos = md.pair_rank = md.pair_key = md.srt_key = md.tmp_key = nullptr;
+    md.pair_tsdf = md.srt_tsdf = md.tmp_tsdf = nullptr;
+    md.srt_lab = nullptr;
+    md.work = nullptr;
+    md.pair_cap = 0;
+    md.work_cap = 0;
+    const size_t cap = m->hcap;
+    slim_status r;
+    if ((r = dalloc(m, &md.skeys, cap)) || (r = dalloc(m, &md.touched, cap)) || (r = dalloc(m, &md.pos_count, cap)) ||
+        (r = dalloc(m, &md.pos_slab, cap)) || (r = dalloc(m, &md.pos_plan, cap)) ||
+        (r = dalloc(m, &md.pos_pages, 2 * cap)) || (r = dalloc(m, &md.items, cap)) || (r = dalloc(m, &md.fs, 1)))
+        return r;
+    HIP_OK(hipStreamCreateWithFlags(&m->wstream, hipStreamNonBlocking));
+    for (hipEvent_t *e : {&m->ev_in, &m->ev_free[0], &m->ev_free[1], &m->ev_walk[0], &m->ev_walk[1]})
+        HIP_OK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    HIP_OK(launch_reset_staging(md, s));
+    m->md1 = md;
+    m->pair_cap1 = 0;
+    m->used[0] = m->used[1] = false;
+    m->have1 = true;
+    return SLIM_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+slim_status slim_integrate_sequence(slim_map *m, const slim_frame *frames, int32_t count, void *stream)
+{
+    g_err[0] = 0;
+    if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
+    if (count < 0 || (count > 0 && !frames)) return fail(SLIM_ERR_INVALID, "need count >= 0 and frames");
+    if (count == 0) return SLIM_OK;
+    DeviceGuard g(m->cfg.device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<FrameParams> fps(count);
+    int64_t nmax = 1;
+    for (int i = 0; i < count; ++i) {
+        const slim_frame &f = frames[i];
+        if (f.points && (f.ranges || f.dirs)) return fail(SLIM_ERR_INVALID, "frame %d has points and rays", i);
+        if (f.n > 0 && !f.points && !(f.ranges && f.dirs)) return fail(SLIM_ERR_INVALID, "frame %d has no points", i);
+        slim_status r = make_frame(m, f.points, f.ranges, f.dirs, f.n, f.pose, f.sem, f.sem_kind, &fps[i]);
+        if (r) return r;
+        nmax = std::max<int64_t>(nmax, f.n);
+    }
+    if (count == 1) return integrate_frame(m, fps[0], stream);
+    slim_status r = ensure_buffer1(m, s);
+    if (r) return r;
+    const size_t need = (size_t)nmax * (size_t)m->maxsteps;
+    if ((r = ensure_pairs(m, need, s, 0)) || (r = ensure_pairs(m, need, s, 1))) return r;
+    // every frame's inputs, and all earlier work on the stream, come first
+    HIP_OK(hipEventRecord(m->ev_in, s));
+    HIP_OK(hipStreamWaitEvent(m->wstream, m->ev_in, 0));
+    for (int t = 0; t < count; ++t) {
+        const int b = t & 1;
+        const MapDev &md = b ? m->md1 : m->md;
+        // the walk of frame t (on the walk stream) needs only its buffer back
+        // from frame t - 2; the rest of the frame follows frame t - 1 in order
+        if (m->used[b]) HIP_OK(hipStreamWaitEvent(m->wstream, m->ev_free[b], 0));
+        HIP_OK(launch_walk(fps[t], md, m->wstream));
+        HIP_OK(hipEventRecord(m->ev_walk[b], m->wstream));
+        HIP_OK(hipStreamWaitEvent(s, m->ev_walk[b], 0));
+        HIP_OK(launch_after_walk(fps[t], md, m->shape, s));
+        HIP_OK(hipEventRecord(m->ev_free[b], s));
+        m->used[b] = true;
+    }
+    return SLIM_OK;
+}
 
 slim_status slim_integrate(slim_map *m, const float *points, int64_t n, const double *pose, const void *sem,
                            int32_t kind, void *stream)

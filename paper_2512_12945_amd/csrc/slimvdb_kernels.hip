@@ -415,7 +415,7 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
                 rloc[q] = atomicAdd(&t_cnt[h], rlen[q]);
                 atomicOr(&t_slab[h], rslab[q]);
             } else {
-                atomicOr(&md.st->frame_err.v, 1u);  // pairs of this run are dropped, frame rejected
+                atomicOr(&md.fs->frame_err.v, 1u);  // pairs of this run are dropped, frame rejected
             }
         }
     }
@@ -433,7 +433,7 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
             atomicOr(&md.pos_slab[pos], t_slab[h]);
             if (fresh) t_fresh[atomicAdd(&s_nfresh, 1u)] = pos;
         } else {
-            atomicOr(&md.st->frame_err.v, 1u);
+            atomicOr(&md.fs->frame_err.v, 1u);
         }
     }
     __syncthreads();
@@ -441,9 +441,9 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
     uint32_t total;
     const uint32_t off = block_excl_scan(cnt, wsum, &total);
     if (tid == 0) {
-        if (s_nfresh) s_fresh_base = atomicAdd(&md.st->n_touched.v, s_nfresh);
-        if (total) s_pair_base = atomicAdd(&md.st->pairs.v, total);
-        if (rejected_block) atomicAdd(&md.st->rejected.v, rejected_block);
+        if (s_nfresh) s_fresh_base = atomicAdd(&md.fs->n_touched.v, s_nfresh);
+        if (total) s_pair_base = atomicAdd(&md.fs->pairs.v, total);
+        if (rejected_block) atomicAdd(&md.fs->rejected.v, rejected_block);
     }
     __syncthreads();
     for (uint32_t e = tid; e < s_nfresh; e += blockDim.x) md.touched[s_fresh_base + e] = t_fresh[e];
@@ -510,7 +510,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit_batch(MapBatch m
 
 __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, uint32_t nblk)
 {
-    const uint32_t nt = md.st->n_touched.v;
+    const uint32_t nt = md.fs->n_touched.v;
     const unsigned long long pused = md.st->pages_used;
     const uint32_t stride = nblk * blockDim.x;
     for (uint32_t jb = blk * blockDim.x; jb < nt; jb += stride) {
@@ -542,7 +542,7 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
         const uint32_t want[4] = {(act && slot < 0) ? 1u : 0u, (uint32_t)__popc(need), npairs,
                                   big ? (uint32_t)__popc(tslabs) : 0u};
         uint32_t got[4];
-        wave_reserve4(&md.st->new_leaves.v, &md.st->new_pages.v, &md.st->pair_cursor.v, &md.st->work_big.v, want,
+        wave_reserve4(&md.fs->new_leaves.v, &md.fs->new_pages.v, &md.fs->pair_cursor.v, &md.fs->work_big.v, want,
                       got);
         const uint32_t newleaf = got[0], pbase = got[1], bstart = got[2], ibase = got[3];
         if (big) {
@@ -550,7 +550,7 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
             for (int q = 0; q < kLeafPages; ++q)
                 if ((tslabs >> q) & 1u) {
                     if (ibase + r < md.work_cap) md.work[ibase + r] = make_int2((int)j, q);
-                    else atomicOr(&md.st->frame_err.v, 1u);
+                    else atomicOr(&md.fs->frame_err.v, 1u);
                     r++;
                 }
         }
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(256) void k_leaf_plan_batch(MapBatch mb)
 __device__ __forceinline__ void pair_bucket_range(const FrameParams &fp, const MapDev &md, uint32_t blk,
                                                   uint32_t nblk)
 {
-    const uint32_t P = min(md.st->pairs.v, md.pair_cap);
+    const uint32_t P = min(md.fs->pairs.v, md.pair_cap);
     const uint32_t stride = nblk * blockDim.x;
     const bool labels = fp.K > 0 && fp.sem_kind == SLIM_IN_LABEL_I32;
     for (uint32_t i = blk * blockDim.x + threadIdx.x; i < P; i += stride) {
@@ -1418,11 +1418,11 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
                                                 uint32_t blk, uint32_t nblk)
 {
     const DevState *st = md.st;
-    const uint32_t nt = st->n_touched.v;
-    const uint32_t nbig = min(st->work_big.v, md.work_cap);
+    const uint32_t nt = md.fs->n_touched.v;
+    const uint32_t nbig = min(md.fs->work_big.v, md.work_cap);
     const unsigned long long lused = st->leaves_used;
-    const bool ok = st->frame_err.v == 0 && lused + st->new_leaves.v <= (unsigned long long)md.max_leaves &&
-                    st->pages_used + st->new_pages.v <= (unsigned long long)md.max_pages;
+    const bool ok = md.fs->frame_err.v == 0 && lused + md.fs->new_leaves.v <= (unsigned long long)md.max_leaves &&
+                    st->pages_used + md.fs->new_pages.v <= (unsigned long long)md.max_pages;
     if (threadIdx.x == 0) {
         sh.uold = 0;
         sh.unew = 0;
@@ -1506,8 +1506,8 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const unsigned long long nl = st->new_leaves.v, np = st->new_pages.v;
-        const bool ok = st->frame_err.v == 0 && st->leaves_used + nl <= (unsigned long long)md.max_leaves &&
+        const unsigned long long nl = md.fs->new_leaves.v, np = md.fs->new_pages.v;
+        const bool ok = md.fs->frame_err.v == 0 && st->leaves_used + nl <= (unsigned long long)md.max_leaves &&
                         st->pages_used + np <= (unsigned long long)md.max_pages;
         if (ok) {
             st->leaves_used += nl;
@@ -1517,21 +1517,21 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
             st->status = SLIM_ERR_CAPACITY;
         }
         st->last_points = fp.n;
-        st->last_rejected = st->rejected.v;
-        st->last_pairs = st->pairs.v;
-        st->last_touched = st->n_touched.v;
+        st->last_rejected = md.fs->rejected.v;
+        st->last_pairs = md.fs->pairs.v;
+        st->last_touched = md.fs->n_touched.v;
         st->last_new_leaves = nl;
         st->last_u_old = (long long)s_old[0];
         st->last_u_new = (long long)s_new[0];
         st->last_status = ok ? SLIM_OK : SLIM_ERR_CAPACITY;
-        st->n_touched.v = 0;
-        st->pairs.v = 0;
-        st->rejected.v = 0;
-        st->new_leaves.v = 0;
-        st->new_pages.v = 0;
-        st->pair_cursor.v = 0;
-        st->work_big.v = 0;
-        st->frame_err.v = 0;
+        md.fs->n_touched.v = 0;
+        md.fs->pairs.v = 0;
+        md.fs->rejected.v = 0;
+        md.fs->new_leaves.v = 0;
+        md.fs->new_pages.v = 0;
+        md.fs->pair_cursor.v = 0;
+        md.fs->work_big.v = 0;
+        md.fs->frame_err.v = 0;
     }
 }
 
@@ -1646,6 +1646,26 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const La
     rec(8);
     hipLaunchKernelGGL(k_frame_commit, dim3(1), dim3(256), 0, s, fp, md);
     rec(9);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk(const FrameParams &fp, const MapDev &md, hipStream_t s)
+{
+    const int bw = (fp.n + kWalkThreads - 1) / kWalkThreads;
+    hipLaunchKernelGGL(k_ray_walk_emit, dim3(bw > 0 ? bw : 1), dim3(kWalkThreads), 0, s, fp, md);
+    return hipGetLastError();
+}
+
+hipError_t launch_after_walk(const FrameParams &fp, const MapDev &md_in, const LaunchShape &shape, hipStream_t s)
+{
+    MapDev md = md_in;
+    md.leaf_blocks = shape.leaf_blocks;
+    hipLaunchKernelGGL(k_leaf_plan, dim3(shape.plan_blocks), dim3(256), 0, s, md);
+    const long long want = ((long long)fp.n * fp.maxsteps + 255) / 256;
+    const int bb = (int)std::max<long long>(1, std::min<long long>(want, shape.bucket_blocks));
+    hipLaunchKernelGGL(k_pair_bucket, dim3(bb), dim3(256), 0, s, fp, md);
+    launch_leaf(leaf_kernel_kind(fp), fp, md, shape.leaf_blocks, s);
+    hipLaunchKernelGGL(k_frame_commit, dim3(1), dim3(256), 0, s, fp, md);
     return hipGetLastError();
 }
 
@@ -1896,11 +1916,15 @@ __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v)
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ void k_reset_state(DevState *st)
+__global__ void k_reset_state(DevState *st, FrameState *fs)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        DevState z = {};
-        *st = z;
+        if (st) {
+            DevState z = {};
+            *st = z;
+        }
+        FrameState f = {};
+        *fs = f;
     }
 }
 
@@ -1911,7 +1935,18 @@ hipError_t launch_reset(const MapDev &md, hipStream_t s)
     hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, s, md.skeys, cap, kEmptyKey);
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, md.pos_count, cap, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, md.pos_slab, cap, 0u);
-    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, md.st);
+    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, md.st, md.fs);
+    return hipGetLastError();
+}
+
+// Clears a second staging buffer (its table, counts and frame counters).
+hipError_t launch_reset_staging(const MapDev &md, hipStream_t s)
+{
+    const size_t cap = (size_t)md.hmask + 1;
+    hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, s, md.skeys, cap, kEmptyKey);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, md.pos_count, cap, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, md.pos_slab, cap, 0u);
+    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, (DevState *)nullptr, md.fs);
     return hipGetLastError();
 }
 

@@ -24,7 +24,8 @@ EXPORTS = ("slim_map_create", "slim_map_destroy", "slim_map_reset", "slim_integr
            "slim_integrate_depth",
            "slim_map_stats", "slim_extract", "slim_query", "slim_predict", "slim_render", "slim_map_loss",
            "slim_backward_rays",
-           "slim_integrate_batched", "slim_set_launch_shape", "slim_profile_enable", "slim_profile_read",
+           "slim_integrate_batched", "slim_integrate_sequence", "slim_set_launch_shape", "slim_profile_enable",
+           "slim_profile_read",
            "slim_last_error")
 
 
@@ -93,6 +94,7 @@ def load(path: str = LIB_PATH):
         L.slim_predict.argtypes = [vp, vp, i64, ctypes.POINTER(PredictParams), vp, vp, vp, vp]
         L.slim_render.argtypes = [vp, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]
         L.slim_integrate_batched.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(Frame), i32, vp]
+        L.slim_integrate_sequence.argtypes = [vp, ctypes.POINTER(Frame), i32, vp]
         L.slim_set_launch_shape.argtypes = [vp, ctypes.POINTER(LaunchShape)]
         L.slim_profile_enable.argtypes = [vp, i32]
         L.slim_profile_read.argtypes = [vp, vp, vp, i32, vp]
@@ -258,12 +260,8 @@ class Map:
         return {k: (float(a), int(b)) for k, a, b in zip(KERNELS, ms, n)}
 
 
-def integrate_batched(maps, frames, use_graph=False):
-    """frames[i] = dict(points=cuda (n,3) | ranges=..., dirs=..., pose=4x4, sem=cuda tensor, kind=IN_*)
-    integrated into maps[i], all in one batched launch sequence (see include/slimvdb.h)."""
-    L = load()
-    n = len(maps)
-    arr = (Frame * n)()
+def _frames(frames):
+    arr = (Frame * len(frames))()
     for i, f in enumerate(frames):
         pts = f.get("points")
         arr[i].points = pts.data_ptr() if pts is not None else None
@@ -273,5 +271,21 @@ def integrate_batched(maps, frames, use_graph=False):
         arr[i].pose[:] = [float(v) for v in np.asarray(f["pose"], np.float64).reshape(16)]
         arr[i].sem = f["sem"].data_ptr() if f.get("sem") is not None else None
         arr[i].sem_kind = f.get("kind", IN_NONE)
+    return arr
+
+
+def integrate_sequence(m, frames):
+    """Integrates frames (dicts as for integrate_batched) into map m in order, the ray walk of each next
+    frame overlapping the rest of the current one (see include/slimvdb.h)."""
+    arr = _frames(frames)
+    _check(m._L.slim_integrate_sequence(m.h, arr, len(frames), _stream(m.device)))
+
+
+def integrate_batched(maps, frames, use_graph=False):
+    """frames[i] = dict(points=cuda (n,3) | ranges=..., dirs=..., pose=4x4, sem=cuda tensor, kind=IN_*)
+    integrated into maps[i], all in one batched launch sequence (see include/slimvdb.h)."""
+    L = load()
+    n = len(maps)
+    arr = _frames(frames)
     handles = (ctypes.c_void_p * n)(*[m.h.value for m in maps])
     _check(L.slim_integrate_batched(handles, n, arr, 1 if use_graph else 0, _stream(maps[0].device)))

@@ -87,6 +87,7 @@ def test_read_out_and_depth_entry_points_reject_null_map():
     k = (ctypes.c_float * 4)(1.0, 1.0, 0.0, 0.0)
     assert L.slim_integrate_depth(None, None, 0, 0, k, None, None, 0, None) == sv.ERR_INVALID
     assert L.slim_render(None, None, k, 0, 0, 0.0, 1.0, None, None, None, None) == sv.ERR_INVALID
+    assert L.slim_integrate_sequence(None, None, 0, None) == sv.ERR_INVALID
 
 
 def test_differentiation_entry_points_reject_bad_arguments():
