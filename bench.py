@@ -237,6 +237,27 @@ def account(timed, n_pts, b_sem, S_v):
                 b_alg=bytes_points + bytes_sem + bytes_state)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/leaf_fuse_lidar_street_hbm_traffic.md), or None when the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        text = open(os.path.join(root, "profiles", "leaf_fuse_lidar_street_hbm_traffic.md")).read()
+        line = [ln for ln in text.splitlines() if ln.startswith("TRAFFIC-JSON ")][0]
+        rec = json.loads(line[len("TRAFFIC-JSON "):])
+        h = hashlib.sha256()
+        for f in ("slimvdb_kernels.hip", "slim_internal.h"):
+            h.update(open(os.path.join(root, "paper_2512_12945_amd", "csrc", f), "rb").read())
+        if h.hexdigest() != rec["kernel_source_sha256"]:
+            return None
+        return rec["per_launch_bytes"].get(kernel)
+    except (OSError, IndexError, ValueError, KeyError):
+        return None
+
+
 def dominant(kern, kalg, K):
     """Kernel with the most time, its achieved algorithmic GB/s (bytes per
     launch over its average event-timed duration) and its bytes per launch."""
@@ -350,7 +371,7 @@ def main():
         "path_roofline_frac": (b_alg / elapsed_noev / 1e9) / HBM_PEAK_GBS,
         "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in run["kern"].items()},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": dom_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "alg_bytes_per_launch": dom_bytes},
     }
 
