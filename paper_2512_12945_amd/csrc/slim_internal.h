@@ -48,6 +48,7 @@ struct FrameState {
     Line new_pages;   // record pages to create
     Line pair_cursor; // bucket allocation cursor
     Line work_big;    // slab work items of large leaves
+    Line n_vox;       // voxel descriptors for the wave combine
     Line frame_err;   // nonzero: do not apply this frame
 };
 
@@ -151,6 +152,7 @@ struct MapDev {
     uint32_t pair_cap;
     int2 *work;           // slab work items (touched index, slab) of large leaves
     uint32_t work_cap;
+    uint4 *vox_list;      // wave-combine voxels: (record, pairs | existed << 31, first sorted pair, 0)
     uint2 *blk_stats;     // per leaf-kernel block: (voxels updated that existed, voxels created)
     int leaf_blocks;      // grid of the leaf kernel of the current frame (<= kMaxLeafBlocksPerCu * CUs)
     DevState *st;

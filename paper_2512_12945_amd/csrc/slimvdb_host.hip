@@ -194,8 +194,8 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s, int buf = 0)
     size_t cap = std::max<size_t>(need, pcap + pcap / 2);
     cap = std::min<size_t>(cap, 0xFFFFFFF0ull);
     MapDev &md = buf ? m->md1 : m->md;
-    void *ptrs[10] = {md.pair_pos, md.pair_rank, md.pair_key, md.pair_tsdf, md.srt_key,
-                      md.srt_tsdf, md.srt_lab,  md.tmp_key,  md.tmp_tsdf,  md.work};
+    void *ptrs[11] = {md.pair_pos, md.pair_rank, md.pair_key, md.pair_tsdf, md.srt_key, md.srt_tsdf,
+                      md.srt_lab,  md.tmp_key,   md.tmp_tsdf, md.work,      md.vox_list};
     for (void *p : ptrs) {
         if (!p) continue;
         (void)hipFree(p);
@@ -205,6 +205,7 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s, int buf = 0)
     md.pair_tsdf = md.srt_tsdf = md.tmp_tsdf = nullptr;
     md.srt_lab = nullptr;
     md.work = nullptr;
+    md.vox_list = nullptr;
     // a large leaf has more than kLeafLdsPairs pairs and at most 8 slab items
     const size_t wcap = cap / (kLeafLdsPairs / kLeafPages) + kLeafPages;
     slim_status r;
@@ -213,7 +214,7 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s, int buf = 0)
         (r = dalloc(m, &md.srt_key, cap)) || (r = dalloc(m, &md.srt_tsdf, cap)) ||
         (r = dalloc(m, &md.srt_lab, cap)) || (r = dalloc(m, &md.tmp_key, cap)) ||
         (r = dalloc(m, &md.tmp_tsdf, cap)) ||
-        (r = dalloc(m, &md.work, wcap))) {
+        (r = dalloc(m, &md.work, wcap)) || (r = dalloc(m, &md.vox_list, cap))) {
         pcap = 0;
         md.pair_cap = 0;
         md.work_cap = 0;
@@ -441,6 +442,7 @@ slim_status ensure_buffer1(slim_map *m, hipStream_t s)
     md.pair_tsdf = md.srt_tsdf = md.tmp_tsdf = nullptr;
     md.srt_lab = nullptr;
     md.work = nullptr;
+    md.vox_list = nullptr;
     md.pair_cap = 0;
     md.work_cap = 0;
     const size_t cap = m->hcap;

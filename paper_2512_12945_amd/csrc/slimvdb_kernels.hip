@@ -1237,7 +1237,41 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
             __syncthreads();
             labs = (const int32_t *)sh.b_key;
         }
-        if (ok) {
+        if (ok && WAVE) {
+            // wave combines run in their own kernel over every voxel of the frame:
+            // the sorted pairs go to the pair buffers at their bucket positions,
+            // and each touched voxel of the run gets a descriptor
+            if (fits)
+                for (uint32_t t = tid; t < hi - lo; t += blockDim.x) {
+                    md.pair_key[bstart + lo + t] = sh.a_key[t];
+                    md.pair_tsdf[bstart + lo + t] = sh.a_val[t];
+                }
+            uint32_t cnt = 0;
+            for (uint32_t w32 = o0 >> 5; w32 <= ((o1 - 1) >> 5); ++w32) {
+                uint32_t bits = sh.touch[w32];
+                if ((w32 << 5) < o0) bits &= ~0u << (o0 & 31);
+                if (((w32 + 1) << 5) > o1) bits &= (o1 & 31) ? ((1u << (o1 & 31)) - 1u) : ~0u;
+                cnt += __popc(bits);
+            }
+            if (tid == 0) sh.chunk_end = atomicAdd(&md.fs->n_vox.v, cnt);
+            __syncthreads();
+            const uint32_t vbase = sh.chunk_end;
+            for (uint32_t o = o0 + tid; o < o1; o += blockDim.x) {
+                const uint32_t n_o = sh.hist[o];
+                if (!n_o) continue;
+                // rank of o among the touched offsets of [o0, o1)
+                uint32_t r = 0;
+                for (uint32_t w32 = o0 >> 5; w32 <= (o >> 5); ++w32) {
+                    uint32_t bits = sh.touch[w32];
+                    if ((w32 << 5) < o0) bits &= ~0u << (o0 & 31);
+                    if (w32 == (o >> 5)) bits &= (1u << (o & 31)) - 1u;
+                    r += __popc(bits);
+                }
+                const uint32_t rec = (uint32_t)sh.pages[o >> 6] * kPageVoxels + (o & (kPageVoxels - 1));
+                const uint32_t existed = (sh.occ0[o >> 5] >> (o & 31)) & 1u;
+                md.vox_list[vbase + r] = make_uint4(rec, n_o | (existed << 31), bstart + sh.bin0[o], 0u);
+            }
+        } else if (ok) {
             // sorted pairs of bin o sit at keys[bin0[o] - base]
             const uint32_t *ck = fits ? sh.a_key : md.pair_key + bstart;
             const float *cv = fits ? sh.a_val : md.pair_tsdf + bstart;
@@ -1473,6 +1507,51 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_fuse_batch(MapBatch mb)
 }
 
 
+// One wave per voxel descriptor of the frame (open set, wide class counts,
+// most-recent open set): the combine of the wave-per-voxel leaf kernels, run
+// over all voxels of the frame at once so that the heavy voxels spread over the
+// whole GPU.  Consecutive descriptors (neighbouring voxels, which share
+// observations) go to workgroups on the same XCD.
+template <int KMAX>
+__device__ __forceinline__ void voxel_combine_range(const FrameParams &fp, const MapDev &md, uint32_t blk,
+                                                    uint32_t nblk)
+{
+    const uint32_t nv = md.fs->n_vox.v;
+    const uint32_t nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+    // blocks are dealt to the 8 XCDs round robin: give each XCD a contiguous share
+    const uint32_t per_xcd = (nblk + 7) / 8;
+    const uint32_t vb = (blk % 8) * per_xcd + blk / 8;
+    if (vb >= nblk) return;
+    for (uint32_t v = vb * nw + w; v < nv; v += nblk * nw) {
+        const uint4 d = md.vox_list[v];
+        const uint32_t n = d.y & 0x7FFFFFFFu;
+        const bool existed = (d.y >> 31) != 0u;
+        const uint32_t *keys = md.pair_key + d.z;
+        const float *vals = md.pair_tsdf + d.z;
+        if (KMAX < 0)
+            combine_last_wave(fp, md, keys, vals, n, (long long)d.x, existed);
+        else if (KMAX > 0)
+            combine_wave_vec<(KMAX > 0 ? KMAX : 1)>(fp, md, keys, vals, n, (long long)d.x, existed);
+        else
+            combine_wave(fp, md, keys, vals, n, (long long)d.x, existed);
+    }
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_voxel_combine(FrameParams fp, MapDev md)
+{
+    voxel_combine_range<KMAX>(fp, md, blockIdx.x, gridDim.x);
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_voxel_combine_batch(MapBatch mb)
+{
+    for (int q = 0; q < mb.nsubset; ++q) {
+        const int i = mb.subset[q];
+        voxel_combine_range<KMAX>(mb.fps[i], mb.mds[i], blockIdx.x, gridDim.x);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // 5. commit (one workgroup)
 // ---------------------------------------------------------------------------
@@ -1531,6 +1610,7 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
         md.fs->new_pages.v = 0;
         md.fs->pair_cursor.v = 0;
         md.fs->work_big.v = 0;
+        md.fs->n_vox.v = 0;
         md.fs->frame_err.v = 0;
     }
 }
@@ -1572,6 +1652,52 @@ int leaf_kernel_kind(const FrameParams &fp)
     const bool rows = fp.sem_kind == SLIM_IN_PROB_F32 || fp.sem_kind == SLIM_IN_LOGIT_F32;
     if (rows) return fp.K > 16 ? 7 : (fp.K > 8 ? 6 : 5);
     return fp.K > 24 ? 4 : (fp.K > 16 ? 3 : (fp.K > 8 ? 2 : 1));
+}
+
+// Leaf-kernel variants whose voxels are combined by k_voxel_combine (one wave
+// per voxel), with that kernel's template argument; -2: combined in the leaf kernel.
+static int voxel_combine_arg(int kind)
+{
+    switch (kind) {
+    case 8: return 0;
+    case 10: return -1;
+    case 11: return 1;
+    case 12: return 2;
+    case 13: return 4;
+    case 14: return 8;
+    case 15: return 16;
+    default: return -2;
+    }
+}
+
+static void launch_voxel_combine(int kind, const FrameParams &fp, const MapDev &md, int blocks, hipStream_t s)
+{
+    const dim3 gl(blocks), bl(256);
+    switch (voxel_combine_arg(kind)) {
+    case 0: hipLaunchKernelGGL((k_voxel_combine<0>), gl, bl, 0, s, fp, md); break;
+    case -1: hipLaunchKernelGGL((k_voxel_combine<-1>), gl, bl, 0, s, fp, md); break;
+    case 1: hipLaunchKernelGGL((k_voxel_combine<1>), gl, bl, 0, s, fp, md); break;
+    case 2: hipLaunchKernelGGL((k_voxel_combine<2>), gl, bl, 0, s, fp, md); break;
+    case 4: hipLaunchKernelGGL((k_voxel_combine<4>), gl, bl, 0, s, fp, md); break;
+    case 8: hipLaunchKernelGGL((k_voxel_combine<8>), gl, bl, 0, s, fp, md); break;
+    case 16: hipLaunchKernelGGL((k_voxel_combine<16>), gl, bl, 0, s, fp, md); break;
+    default: break;
+    }
+}
+
+static void launch_voxel_combine_batch(int kind, const MapBatch &mb, int blocks, hipStream_t s)
+{
+    const dim3 gl(blocks), bl(256);
+    switch (voxel_combine_arg(kind)) {
+    case 0: hipLaunchKernelGGL((k_voxel_combine_batch<0>), gl, bl, 0, s, mb); break;
+    case -1: hipLaunchKernelGGL((k_voxel_combine_batch<-1>), gl, bl, 0, s, mb); break;
+    case 1: hipLaunchKernelGGL((k_voxel_combine_batch<1>), gl, bl, 0, s, mb); break;
+    case 2: hipLaunchKernelGGL((k_voxel_combine_batch<2>), gl, bl, 0, s, mb); break;
+    case 4: hipLaunchKernelGGL((k_voxel_combine_batch<4>), gl, bl, 0, s, mb); break;
+    case 8: hipLaunchKernelGGL((k_voxel_combine_batch<8>), gl, bl, 0, s, mb); break;
+    case 16: hipLaunchKernelGGL((k_voxel_combine_batch<16>), gl, bl, 0, s, mb); break;
+    default: break;
+    }
 }
 
 static void launch_leaf(int kind, const FrameParams &fp, const MapDev &md, int blocks, hipStream_t s)
@@ -1641,7 +1767,9 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const La
     hipLaunchKernelGGL(k_pair_bucket, dim3(bb), dim3(256), 0, s, fp, md);
     rec(5);
     rec(6);
-    launch_leaf(leaf_kernel_kind(fp), fp, md, shape.leaf_blocks, s);
+    const int kind = leaf_kernel_kind(fp);
+    launch_leaf(kind, fp, md, shape.leaf_blocks, s);
+    launch_voxel_combine(kind, fp, md, shape.leaf_blocks, s);
     rec(7);
     rec(8);
     hipLaunchKernelGGL(k_frame_commit, dim3(1), dim3(256), 0, s, fp, md);
@@ -1664,7 +1792,9 @@ hipError_t launch_after_walk(const FrameParams &fp, const MapDev &md_in, const L
     const long long want = ((long long)fp.n * fp.maxsteps + 255) / 256;
     const int bb = (int)std::max<long long>(1, std::min<long long>(want, shape.bucket_blocks));
     hipLaunchKernelGGL(k_pair_bucket, dim3(bb), dim3(256), 0, s, fp, md);
-    launch_leaf(leaf_kernel_kind(fp), fp, md, shape.leaf_blocks, s);
+    const int kind = leaf_kernel_kind(fp);
+    launch_leaf(kind, fp, md, shape.leaf_blocks, s);
+    launch_voxel_combine(kind, fp, md, shape.leaf_blocks, s);
     hipLaunchKernelGGL(k_frame_commit, dim3(1), dim3(256), 0, s, fp, md);
     return hipGetLastError();
 }
@@ -1680,6 +1810,7 @@ hipError_t launch_integrate_batched(const MapBatch &mb, const BatchPlan &plan, c
         sub.subset = mb.subset + plan.group_begin[g];
         sub.nsubset = plan.group_size[g];
         launch_leaf_batch(plan.group_kind[g], sub, shape.leaf_blocks, s);
+        launch_voxel_combine_batch(plan.group_kind[g], sub, shape.leaf_blocks, s);
     }
     hipLaunchKernelGGL(k_frame_commit_batch, dim3(plan.nmaps), dim3(256), 0, s, mb);
     return hipGetLastError();
