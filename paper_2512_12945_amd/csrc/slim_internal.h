@@ -48,6 +48,8 @@ struct FrameState {
     Line new_pages;   // record pages to create
     Line pair_cursor; // bucket allocation cursor
     Line work_big;    // slab work items of large leaves
+    Line n_med;       // leaves done by one workgroup
+    Line n_small;     // leaves done by one wave
     Line n_vox;       // voxel descriptors for the wave combine
     Line frame_err;   // nonzero: do not apply this frame
 };
@@ -131,6 +133,8 @@ struct MapDev {
     int4 *pos_plan;      // (slot or -1, new-leaf index, bucket start, 0)
     int4 *pos_pages;     // 2 per position: record page of each of the 8 slabs (-1: none)
     LeafItem *items;     // per touched index: the leaf kernel's view of the leaf
+    uint32_t *med_list;  // touched indices of leaves done by one workgroup
+    uint32_t *small_list;  // touched indices of leaves done by one wave
     // leaves
     unsigned long long *leaf_key; // packed key per slot
     int32_t *leaf_page;           // 8 record pages per slot (-1: none)

@@ -278,7 +278,7 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, config->device) == hipSuccess && prop.multiProcessorCount > 0)
         m->cus = prop.multiProcessorCount;
-    m->shape = {m->cus, m->cus * 16, m->cus * 16};
+    m->shape = {m->cus, m->cus * 16, m->cus * 8};
 
     MapDev &md = m->md;
     md.hmask = (uint32_t)(cap - 1);
@@ -291,6 +291,7 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
         (r = dalloc(m, &md.touched, cap)) || (r = dalloc(m, &md.pos_count, cap)) ||
         (r = dalloc(m, &md.pos_slab, cap)) || (r = dalloc(m, &md.pos_plan, cap)) ||
         (r = dalloc(m, &md.pos_pages, 2 * cap)) || (r = dalloc(m, &md.items, cap)) ||
+        (r = dalloc(m, &md.med_list, cap)) || (r = dalloc(m, &md.small_list, cap)) ||
         (r = dalloc(m, &md.leaf_key, L)) ||
         (r = dalloc(m, &md.leaf_page, L * kLeafPages)) || (r = dalloc(m, &md.leaf_occ, L * kMaskWords)) ||
         (r = dalloc(m, &md.vox, NP * kPageVoxels * (size_t)md.rec_stride)) ||
@@ -437,6 +438,7 @@ slim_status ensure_buffer1(slim_map *m, hipStream_t s)
     md.touched = md.pos_count = md.pos_slab = nullptr;
     md.pos_plan = md.pos_pages = nullptr;
     md.items = nullptr;
+    md.med_list = md.small_list = nullptr;
     md.fs = nullptr;
     md.pair_pos = md.pair_rank = md.pair_key = md.srt_key = md.tmp_key = nullptr;
     md.pair_tsdf = md.srt_tsdf = md.tmp_tsdf = nullptr;
@@ -449,7 +451,8 @@ slim_status ensure_buffer1(slim_map *m, hipStream_t s)
     slim_status r;
     if ((r = dalloc(m, &md.skeys, cap)) || (r = dalloc(m, &md.touched, cap)) || (r = dalloc(m, &md.pos_count, cap)) ||
         (r = dalloc(m, &md.pos_slab, cap)) || (r = dalloc(m, &md.pos_plan, cap)) ||
-        (r = dalloc(m, &md.pos_pages, 2 * cap)) || (r = dalloc(m, &md.items, cap)) || (r = dalloc(m, &md.fs, 1)))
+        (r = dalloc(m, &md.pos_pages, 2 * cap)) || (r = dalloc(m, &md.items, cap)) ||
+        (r = dalloc(m, &md.med_list, cap)) || (r = dalloc(m, &md.small_list, cap)) || (r = dalloc(m, &md.fs, 1)))
         return r;
     HIP_OK(hipStreamCreateWithFlags(&m->wstream, hipStreamNonBlocking));
     for (hipEvent_t *e : {&m->ev_in, &m->ev_free[0], &m->ev_free[1], &m->ev_walk[0], &m->ev_walk[1]})
@@ -804,7 +807,7 @@ slim_status slim_set_launch_shape(slim_map *m, const slim_launch_shape *shape)
     g_err[0] = 0;
     if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
     if (!shape) {
-        m->shape = {m->cus, m->cus * 16, m->cus * 16};
+        m->shape = {m->cus, m->cus * 16, m->cus * 8};
         return SLIM_OK;
     }
     if (shape->plan_blocks < 1 || shape->bucket_blocks < 1 || shape->leaf_blocks_per_cu < 1 ||

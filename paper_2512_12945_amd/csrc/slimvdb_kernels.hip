@@ -297,6 +297,7 @@ __device__ void block_scan512(const uint32_t *in, uint32_t *out, uint32_t *wsum)
 // 1. ray walk and pair emission
 // ---------------------------------------------------------------------------
 
+constexpr int kWaveItemPairs = 256;  // leaves with at most this many pairs are one wave's work
 constexpr int kMaxRuns = 8;  // leaf runs per ray; sdf_trunc <= 6 voxel_size keeps a ray within this
 static_assert(kWalkTable >= kWalkThreads * kMaxRuns, "the walk table must hold every run of a block");
 
@@ -545,6 +546,13 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
         wave_reserve4(&md.fs->new_leaves.v, &md.fs->new_pages.v, &md.fs->pair_cursor.v, &md.fs->work_big.v, want,
                       got);
         const uint32_t newleaf = got[0], pbase = got[1], bstart = got[2], ibase = got[3];
+        // the other leaves: one workgroup each, or one wave each if small
+        const bool small = act && npairs <= (uint32_t)kWaveItemPairs;
+        const bool med = act && !big && !small;
+        const uint32_t mi = wave_reserve(&md.fs->n_med.v, med ? 1u : 0u);
+        const uint32_t si = wave_reserve(&md.fs->n_small.v, small ? 1u : 0u);
+        if (med) md.med_list[mi] = j;
+        if (small) md.small_list[si] = j;
         if (big) {
             uint32_t r = 0;
             for (int q = 0; q < kLeafPages; ++q)
@@ -629,7 +637,6 @@ struct LeafShared {
     uint32_t touch[kMaskWords], occ0[kMaskWords], wsum[4];
     int pages[kLeafPages];
     uint32_t chunk_end, uold, unew;
-    uint32_t gn[4];           // pairs of the block's current group of leaves (one per wave)
     uint32_t item[32];        // the current block item
 };
 
@@ -1321,7 +1328,6 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
 // key (offset, point index), which groups them by voxel in point order; lanes
 // then take one voxel each.  Waves run such leaves independently (no block
 // barrier), four per block.
-constexpr int kWaveItemPairs = 256;
 constexpr int kWaveLds = kLeafLdsPairs / 4;  // LDS pairs per wave
 static_assert(kWaveItemPairs <= kWaveLds, "a wave item must fit its LDS quarter");
 
@@ -1462,26 +1468,26 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
         sh.unew = 0;
     }
     __syncthreads();
-    for (uint32_t w = blk; w < nbig; w += nblk) {
-        const int2 it = md.work[w];
-        fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, (uint32_t)it.x, it.y, lused, ok);
-    }
-    // the other touched leaves: this block owns j = blk + nblk * i.  Four at a
-    // time: small ones go to one wave each, the rest are done block-wide after
-    // them.  A leaf's staging entry is read and cleared by its owner only.
-    const uint32_t w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (uint32_t base = blk; base < nt; base += nw * nblk) {
-        const uint32_t j = base + w * nblk;
-        const uint32_t n = j < nt ? md.items[j].n : 0u;
-        if (lane_id() == 0) sh.gn[w] = n;
-        if (!WAVE && n > 0 && n <= (uint32_t)kWaveItemPairs) fuse_wave_item<KMAX, WAVE, ROWS>(fp, md, sh, j, lused, ok);
-        __syncthreads();
-        for (uint32_t q = 0; q < nw; ++q) {
-            const uint32_t nq = sh.gn[q];
-            if (nq == 0 || nq > (uint32_t)kLeafLdsPairs || (!WAVE && nq <= (uint32_t)kWaveItemPairs)) continue;
-            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, base + q * nblk, -1, lused, ok);
+    // units of work, one per block at a time: the slab items of large leaves,
+    // then the leaves done by a workgroup, then groups of four small leaves
+    // (one per wave; the wave kernels take the small leaves one per workgroup)
+    const uint32_t nmed = md.fs->n_med.v, nsmall = md.fs->n_small.v;
+    const uint32_t nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+    const uint32_t ngroups = WAVE ? nsmall : (nsmall + nw - 1) / nw;
+    const uint32_t nunits = nbig + nmed + ngroups;
+    for (uint32_t u = blk; u < nunits; u += nblk) {
+        if (u < nbig) {
+            const int2 it = md.work[u];
+            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, (uint32_t)it.x, it.y, lused, ok);
+        } else if (u < nbig + nmed) {
+            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, md.med_list[u - nbig], -1, lused, ok);
+        } else if (WAVE) {
+            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, md.small_list[u - nbig - nmed], -1, lused, ok);
+        } else {
+            const uint32_t k = (u - nbig - nmed) * nw + w;
+            if (k < nsmall) fuse_wave_item<KMAX, WAVE, ROWS>(fp, md, sh, md.small_list[k], lused, ok);
+            __syncthreads();
         }
-        __syncthreads();
     }
     __syncthreads();
     if (threadIdx.x == 0) md.blk_stats[blk] = make_uint2(sh.uold, sh.unew);
@@ -1610,6 +1616,8 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
         md.fs->new_pages.v = 0;
         md.fs->pair_cursor.v = 0;
         md.fs->work_big.v = 0;
+        md.fs->n_med.v = 0;
+        md.fs->n_small.v = 0;
         md.fs->n_vox.v = 0;
         md.fs->frame_err.v = 0;
     }
