@@ -48,8 +48,8 @@ struct FrameState {
     Line new_pages;   // record pages to create
     Line pair_cursor; // bucket allocation cursor
     Line work_big;    // slab work items of large leaves
-    Line n_med;       // leaves done by one workgroup
-    Line n_small;     // leaves done by one wave
+    alignas(128) unsigned long long n_lists;  // leaves done by one workgroup (low half), by one wave (high half)
+    unsigned int pad_lists[30];
     Line n_vox;       // voxel descriptors for the wave combine
     Line frame_err;   // nonzero: do not apply this frame
 };

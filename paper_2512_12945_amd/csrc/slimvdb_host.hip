@@ -272,6 +272,10 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
               : config->sem_mode == SLIM_SEM_OPEN_LAST   ? config->embed_dim
                                                          : 0;
     m->maxsteps = max_steps(config->voxel_size, config->sdf_trunc);
+    if (m->maxsteps > 64) {  // the walk kernel records a ray's cells in 64-bit masks
+        delete m;
+        return fail(SLIM_ERR_UNSUPPORTED, "sdf_trunc / voxel_size too large");
+    }
     size_t cap = 1024;
     while (cap < 2 * (size_t)config->max_leaves) cap <<= 1;
     m->hcap = cap;

@@ -354,16 +354,35 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
         rlen[q] = 0;
         rslab[q] = 0;
     }
+    // the walk is recorded for pass 2: the first cell, the axis of every step
+    // (2 bits each) and which cells passed the gate
+    int c0[3] = {0, 0, 0}, pc[3] = {0, 0, 0};
+    int nvis = 0;
+    unsigned long long steps[2] = {0ull, 0ull}, kept = 0ull;
     if (valid) {
         bool inrange = true;
         unsigned long long cur = kEmptyKey;
         band_walk(fp, ry, [&](int cx, int cy, int cz) {
+            if (nvis == 0) {
+                c0[0] = cx;
+                c0[1] = cy;
+                c0[2] = cz;
+            } else {
+                const unsigned long long ax = cx != pc[0] ? 0ull : (cy != pc[1] ? 1ull : 2ull);
+                const int si = nvis - 1;
+                steps[si >> 5] |= ax << (2 * (si & 31));
+            }
+            pc[0] = cx;
+            pc[1] = cy;
+            pc[2] = cz;
+            const int vi = nvis++;
             const int kx = fp.a[0] + cx, ky = fp.a[1] + cy, kz = fp.a[2] + cz;
             if (!(key_ok(kx) && key_ok(ky) && key_ok(kz))) {
                 inrange = false;
                 return;
             }
             if (!(cell_sdf(fp, ry, cx, cy, cz) > -fp.tau)) return;
+            kept |= 1ull << vi;
             const unsigned long long lk = pack_leaf(kx >> 3, ky >> 3, kz >> 3);
             if (lk != cur) {
                 cur = lk;
@@ -450,15 +469,25 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
     for (uint32_t e = tid; e < s_nfresh; e += blockDim.x) md.touched[s_fresh_base + e] = t_fresh[e];
     if (cnt == 0) return;
 
-    // pass 2: write the pairs
+    // pass 2: write the pairs, replaying the recorded walk
     const uint32_t o = s_pair_base + off;
     uint32_t j = 0;
     int run = -1;
     unsigned long long cur = kEmptyKey;
     uint32_t pos = kNoPos, rank = 0;
-    band_walk(fp, ry, [&](int cx, int cy, int cz) {
+    const int stp[3] = {ry.u[0] > 0.0f ? 1 : -1, ry.u[1] > 0.0f ? 1 : -1, ry.u[2] > 0.0f ? 1 : -1};
+    int cc[3] = {c0[0], c0[1], c0[2]};
+    for (int vi = 0; vi < nvis; ++vi) {
+        if (vi > 0) {
+            const int si = vi - 1;
+            const int ax = (int)((steps[si >> 5] >> (2 * (si & 31))) & 3ull);
+            if (ax == 0) cc[0] += stp[0];
+            else if (ax == 1) cc[1] += stp[1];
+            else cc[2] += stp[2];
+        }
+        if (!((kept >> vi) & 1ull)) continue;
+        const int cx = cc[0], cy = cc[1], cz = cc[2];
         const float s = cell_sdf(fp, ry, cx, cy, cz);
-        if (!(s > -fp.tau)) return;
         const int kx = fp.a[0] + cx, ky = fp.a[1] + cy, kz = fp.a[2] + cz;
         const unsigned long long lk = pack_leaf(kx >> 3, ky >> 3, kz >> 3);
         if (lk != cur) {
@@ -479,7 +508,7 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
             md.pair_tsdf[o + j] = fminf(s, fp.tau);
         }
         j++;
-    });
+    }
 }
 
 __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, MapDev md)
@@ -540,17 +569,36 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
         // work item per touched x-slab
         const uint32_t tslabs = act ? md.pos_slab[pos] & 0xFFu : 0u;
         const bool big = act && npairs > (uint32_t)kLeafLdsPairs;
-        const uint32_t want[4] = {(act && slot < 0) ? 1u : 0u, (uint32_t)__popc(need), npairs,
-                                  big ? (uint32_t)__popc(tslabs) : 0u};
-        uint32_t got[4];
-        wave_reserve4(&md.fs->new_leaves.v, &md.fs->new_pages.v, &md.fs->pair_cursor.v, &md.fs->work_big.v, want,
-                      got);
-        const uint32_t newleaf = got[0], pbase = got[1], bstart = got[2], ibase = got[3];
         // the other leaves: one workgroup each, or one wave each if small
         const bool small = act && npairs <= (uint32_t)kWaveItemPairs;
         const bool med = act && !big && !small;
-        const uint32_t mi = wave_reserve(&md.fs->n_med.v, med ? 1u : 0u);
-        const uint32_t si = wave_reserve(&md.fs->n_small.v, small ? 1u : 0u);
+        // six reservations with five atomics in flight together (the two list
+        // counters share one 64-bit word)
+        const uint32_t want[4] = {(act && slot < 0) ? 1u : 0u, (uint32_t)__popc(need), npairs,
+                                  big ? (uint32_t)__popc(tslabs) : 0u};
+        uint32_t incl[4], total[4], base[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            incl[q] = wave_incl_scan(want[q]);
+            total[q] = __shfl(incl[q], 63, 64);
+        }
+        const uint32_t mincl = wave_incl_scan(med ? 1u : 0u), sincl = wave_incl_scan(small ? 1u : 0u);
+        const unsigned long long lt = ((unsigned long long)__shfl(sincl, 63, 64) << 32) | __shfl(mincl, 63, 64);
+        unsigned long long lbase = 0;
+        if (lane_id() == 63) {
+            if (total[0]) base[0] = atomicAdd(&md.fs->new_leaves.v, total[0]);
+            if (total[1]) base[1] = atomicAdd(&md.fs->new_pages.v, total[1]);
+            if (total[2]) base[2] = atomicAdd(&md.fs->pair_cursor.v, total[2]);
+            if (total[3]) base[3] = atomicAdd(&md.fs->work_big.v, total[3]);
+            if (lt) lbase = atomicAdd((unsigned long long *)&md.fs->n_lists, lt);
+        }
+        uint32_t got[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) got[q] = __shfl(base[q], 63, 64) + incl[q] - want[q];
+        const unsigned long long lb = __shfl(lbase, 63, 64);
+        const uint32_t newleaf = got[0], pbase = got[1], bstart = got[2], ibase = got[3];
+        const uint32_t mi = (uint32_t)lb + mincl - (med ? 1u : 0u);
+        const uint32_t si = (uint32_t)(lb >> 32) + sincl - (small ? 1u : 0u);
         if (med) md.med_list[mi] = j;
         if (small) md.small_list[si] = j;
         if (big) {
@@ -1471,7 +1519,7 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
     // units of work, one per block at a time: the slab items of large leaves,
     // then the leaves done by a workgroup, then groups of four small leaves
     // (one per wave; the wave kernels take the small leaves one per workgroup)
-    const uint32_t nmed = md.fs->n_med.v, nsmall = md.fs->n_small.v;
+    const uint32_t nmed = (uint32_t)md.fs->n_lists, nsmall = (uint32_t)(md.fs->n_lists >> 32);
     const uint32_t nw = blockDim.x >> 6, w = threadIdx.x >> 6;
     const uint32_t ngroups = WAVE ? nsmall : (nsmall + nw - 1) / nw;
     const uint32_t nunits = nbig + nmed + ngroups;
@@ -1616,8 +1664,7 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
         md.fs->new_pages.v = 0;
         md.fs->pair_cursor.v = 0;
         md.fs->work_big.v = 0;
-        md.fs->n_med.v = 0;
-        md.fs->n_small.v = 0;
+        md.fs->n_lists = 0;
         md.fs->n_vox.v = 0;
         md.fs->frame_err.v = 0;
     }
