@@ -208,39 +208,74 @@ __device__ __forceinline__ void load_point(const FrameParams &fp, int i, float &
 // (fp.t).  Calls visit(cx, cy, cz) per cell (anchor-relative).  Ties between
 // axes step the lowest axis first, one axis per step; the walk stops when the
 // next boundary lies beyond t1, or after maxsteps cells.
-template <class Visit>
-__device__ __forceinline__ void band_walk(const FrameParams &fp, const Ray &ry, Visit &&visit)
-{
-    const float vs = fp.vs, t0 = ry.t0;
+// Start of the walk: first cell c, step direction, first boundary crossing
+// tm and crossing interval td per axis (tm = td = inf on an axis the ray does
+// not move along).
+struct WalkState {
     int c[3], stp[3];
     float tm[3], td[3];
+};
+
+__device__ __forceinline__ void walk_start(const FrameParams &fp, const Ray &ry, WalkState &w)
+{
+    const float vs = fp.vs, t0 = ry.t0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float s = fmaf(t0, ry.u[a], fp.t[a]);
-        c[a] = (int)floorf(s / vs);
+        w.c[a] = (int)floorf(s / vs);
         if (ry.u[a] > 0.0f) {
-            stp[a] = 1;
-            tm[a] = t0 + fmaf((float)(c[a] + 1), vs, -s) / ry.u[a];
-            td[a] = vs / ry.u[a];
+            w.stp[a] = 1;
+            w.tm[a] = t0 + fmaf((float)(w.c[a] + 1), vs, -s) / ry.u[a];
+            w.td[a] = vs / ry.u[a];
         } else if (ry.u[a] < 0.0f) {
-            stp[a] = -1;
-            tm[a] = t0 + fmaf((float)c[a], vs, -s) / ry.u[a];
-            td[a] = -vs / ry.u[a];
+            w.stp[a] = -1;
+            w.tm[a] = t0 + fmaf((float)w.c[a], vs, -s) / ry.u[a];
+            w.td[a] = -vs / ry.u[a];
         } else {
-            stp[a] = 0;
-            tm[a] = INFINITY;
-            td[a] = INFINITY;
+            w.stp[a] = 0;
+            w.tm[a] = INFINITY;
+            w.td[a] = INFINITY;
         }
     }
+}
+
+// Axis of the next step (ties step the lowest axis) and the ray parameter of
+// the boundary it crosses.
+__device__ __forceinline__ int walk_axis(const WalkState &w, float &tnext)
+{
+    const bool xy = w.tm[0] <= w.tm[1];
+    const int ax = xy ? (w.tm[0] <= w.tm[2] ? 0 : 2) : (w.tm[1] <= w.tm[2] ? 1 : 2);
+    tnext = ax == 0 ? w.tm[0] : (ax == 1 ? w.tm[1] : w.tm[2]);
+    return ax;
+}
+
+// One step along axis ax, written as selects (no branch per axis).
+__device__ __forceinline__ void walk_step(WalkState &w, int ax)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool on = ax == a;
+        w.c[a] += on ? w.stp[a] : 0;
+        const float nt = w.tm[a] + w.td[a];
+        w.tm[a] = on ? nt : w.tm[a];
+    }
+}
+
+// Amanatides-Woo walk over the band of the ray from the sensor origin
+// (fp.t).  Calls visit(cx, cy, cz) per cell (anchor-relative).  Ties between
+// axes step the lowest axis first, one axis per step; the walk stops when the
+// next boundary lies beyond t1, or after maxsteps cells.
+template <class Visit>
+__device__ __forceinline__ void band_walk(const FrameParams &fp, const Ray &ry, Visit &&visit)
+{
+    WalkState w;
+    walk_start(fp, ry, w);
     for (int it = 0; it < fp.maxsteps; ++it) {
-        visit(c[0], c[1], c[2]);
-        const bool xy = tm[0] <= tm[1];
-        const int ax = xy ? (tm[0] <= tm[2] ? 0 : 2) : (tm[1] <= tm[2] ? 1 : 2);
-        const float tnext = ax == 0 ? tm[0] : (ax == 1 ? tm[1] : tm[2]);
+        visit(w.c[0], w.c[1], w.c[2]);
+        float tnext;
+        const int ax = walk_axis(w, tnext);
         if (tnext > ry.t1) break;
-        if (ax == 0) { c[0] += stp[0]; tm[0] += td[0]; }
-        else if (ax == 1) { c[1] += stp[1]; tm[1] += td[1]; }
-        else { c[2] += stp[2]; tm[2] += td[2]; }
+        walk_step(w, ax);
     }
 }
 
@@ -306,6 +341,25 @@ __device__ __forceinline__ uint32_t lds_hash(unsigned long long k)
     return (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 40) & (kWalkTable - 1);
 }
 
+// Staging-table position of a leaf for the walk: one compare-and-swap per
+// probe (an empty slot is claimed, a slot holding the key is found), so the
+// common case is one round trip.  *fresh is true for the claiming caller.
+__device__ __forceinline__ uint32_t stage_leaf_cas(const MapDev &md, unsigned long long key, bool *fresh)
+{
+    *fresh = false;
+    uint32_t h = leaf_hash(key, md.hmask);
+    for (uint32_t probe = 0; probe <= md.hmask; ++probe) {
+        const unsigned long long prev = atomicCAS(&md.skeys[h], kEmptyKey, key);
+        if (prev == kEmptyKey) {
+            *fresh = true;
+            return h;
+        }
+        if (prev == key) return h;
+        h = (h + 1) & md.hmask;
+    }
+    return kNoPos;
+}
+
 // One block of the walk: rays blk * blockDim.x + [0, blockDim.x) of a frame.
 __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const MapDev &md, int blk)
 {
@@ -316,21 +370,11 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
     __shared__ uint32_t t_slab[kWalkTable];  // x-slabs of the leaf this block touches
     __shared__ uint32_t t_list[kWalkTable];  // occupied entries
     __shared__ uint32_t t_fresh[kWalkTable]; // staging positions this block inserted
-    __shared__ uint32_t s_n, s_nfresh, s_fresh_base, s_pair_base, wsum[4];
+    __shared__ uint32_t s_n, s_nfresh, s_pair_base, wsum[4];
 
     const int tid = threadIdx.x;
-    for (int e = tid; e < kWalkTable; e += blockDim.x) {
-        t_key[e] = kEmptyKey;
-        t_cnt[e] = 0;
-        t_slab[e] = 0;
-    }
-    if (tid == 0) {
-        s_n = 0;
-        s_nfresh = 0;
-    }
-    __syncthreads();
-
     const int i = blk * blockDim.x + tid;
+    // the point is loaded first: its latency overlaps the table clear
     Ray ry;
     bool valid = false;
     if (i < fp.n) {
@@ -342,8 +386,22 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
             valid = lab >= 0 && lab < fp.K;
         }
     }
+    for (int e = tid; e < kWalkTable; e += blockDim.x) {
+        t_key[e] = kEmptyKey;
+        t_cnt[e] = 0;
+        t_slab[e] = 0;
+    }
+    if (tid == 0) {
+        s_n = 0;
+        s_nfresh = 0;
+    }
+    __syncthreads();
 
-    // pass 1: count kept cells, check the key range, record the leaf runs
+    // pass 1: count kept cells, check the key range, record the leaf runs.
+    // The current run is accumulated in clen/cslab; the run arrays are
+    // written only when a run ends.  The walk is recorded for pass 2: the
+    // first cell, the axis of every step (2 bits each) and which cells passed
+    // the gate.
     uint32_t cnt = 0;
     int nruns = 0;
     unsigned long long rkey[kMaxRuns];
@@ -354,51 +412,58 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
         rlen[q] = 0;
         rslab[q] = 0;
     }
-    // the walk is recorded for pass 2: the first cell, the axis of every step
-    // (2 bits each) and which cells passed the gate
-    int c0[3] = {0, 0, 0}, pc[3] = {0, 0, 0};
+    int c0[3] = {0, 0, 0};
     int nvis = 0;
     unsigned long long steps[2] = {0ull, 0ull}, kept = 0ull;
     if (valid) {
         bool inrange = true;
         unsigned long long cur = kEmptyKey;
-        band_walk(fp, ry, [&](int cx, int cy, int cz) {
-            if (nvis == 0) {
-                c0[0] = cx;
-                c0[1] = cy;
-                c0[2] = cz;
-            } else {
-                const unsigned long long ax = cx != pc[0] ? 0ull : (cy != pc[1] ? 1ull : 2ull);
-                const int si = nvis - 1;
-                steps[si >> 5] |= ax << (2 * (si & 31));
-            }
-            pc[0] = cx;
-            pc[1] = cy;
-            pc[2] = cz;
-            const int vi = nvis++;
-            const int kx = fp.a[0] + cx, ky = fp.a[1] + cy, kz = fp.a[2] + cz;
+        uint32_t clen = 0, cslab = 0;
+        WalkState w;
+        walk_start(fp, ry, w);
+        c0[0] = w.c[0];
+        c0[1] = w.c[1];
+        c0[2] = w.c[2];
+        for (int it = 0; it < fp.maxsteps; ++it) {
+            const int kx = fp.a[0] + w.c[0], ky = fp.a[1] + w.c[1], kz = fp.a[2] + w.c[2];
             if (!(key_ok(kx) && key_ok(ky) && key_ok(kz))) {
                 inrange = false;
-                return;
+                break;
             }
-            if (!(cell_sdf(fp, ry, cx, cy, cz) > -fp.tau)) return;
-            kept |= 1ull << vi;
-            const unsigned long long lk = pack_leaf(kx >> 3, ky >> 3, kz >> 3);
-            if (lk != cur) {
-                cur = lk;
-                nruns++;
+            nvis = it + 1;
+            if (cell_sdf(fp, ry, w.c[0], w.c[1], w.c[2]) > -fp.tau) {
+                kept |= 1ull << it;
+                const unsigned long long lk = pack_leaf(kx >> 3, ky >> 3, kz >> 3);
+                if (lk != cur) {
 #pragma unroll
-                for (int q = 0; q < kMaxRuns; ++q)
-                    if (q == nruns - 1) rkey[q] = lk;
-            }
-#pragma unroll
-            for (int q = 0; q < kMaxRuns; ++q)
-                if (q == nruns - 1) {
-                    rlen[q]++;
-                    rslab[q] |= 1u << (kx & 7);
+                    for (int q = 0; q < kMaxRuns; ++q) {
+                        if (q == nruns - 1) {
+                            rlen[q] = clen;
+                            rslab[q] = cslab;
+                        }
+                        if (q == nruns) rkey[q] = lk;
+                    }
+                    cur = lk;
+                    nruns++;
+                    clen = 0;
+                    cslab = 0;
                 }
-            cnt++;
-        });
+                clen++;
+                cslab |= 1u << (kx & 7);
+                cnt++;
+            }
+            float tnext;
+            const int ax = walk_axis(w, tnext);
+            if (tnext > ry.t1) break;
+            steps[it >> 5] |= (unsigned long long)ax << (2 * (it & 31));
+            walk_step(w, ax);
+        }
+#pragma unroll
+        for (int q = 0; q < kMaxRuns; ++q)
+            if (q == nruns - 1) {
+                rlen[q] = clen;
+                rslab[q] = cslab;
+            }
         if (!inrange || nruns > kMaxRuns) valid = false;
     }
     if (!valid) {
@@ -439,14 +504,22 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
             }
         }
     }
-    __syncthreads();
+    const uint32_t rejected_block = __syncthreads_count((i < fp.n) && !valid);
 
+    // the block's pair range is reserved while the leaves are staged
+    uint32_t total;
+    const uint32_t off = block_excl_scan(cnt, wsum, &total);
+    uint32_t pair_base = 0;
+    if (tid == 0) {
+        if (total) pair_base = atomicAdd(&md.fs->pairs.v, total);
+        if (rejected_block) atomicAdd(&md.fs->rejected.v, rejected_block);
+    }
     // one staging lookup, one bucket reservation and one slab update per leaf of the block
     const uint32_t nloc = s_n;
     for (uint32_t e = tid; e < nloc; e += blockDim.x) {
         const uint32_t h = t_list[e];
         bool fresh;
-        const uint32_t pos = stage_leaf(md, t_key[h], &fresh);
+        const uint32_t pos = stage_leaf_cas(md, t_key[h], &fresh);
         t_pos[h] = pos;
         if (pos != kNoPos) {
             t_cnt[h] = atomicAdd(&md.pos_count[pos], t_cnt[h]);
@@ -456,34 +529,30 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
             atomicOr(&md.fs->frame_err.v, 1u);
         }
     }
+    if (tid == 0) s_pair_base = pair_base;
     __syncthreads();
-    const uint32_t rejected_block = __syncthreads_count((i < fp.n) && !valid);
-    uint32_t total;
-    const uint32_t off = block_excl_scan(cnt, wsum, &total);
-    if (tid == 0) {
-        if (s_nfresh) s_fresh_base = atomicAdd(&md.fs->n_touched.v, s_nfresh);
-        if (total) s_pair_base = atomicAdd(&md.fs->pairs.v, total);
-        if (rejected_block) atomicAdd(&md.fs->rejected.v, rejected_block);
-    }
-    __syncthreads();
-    for (uint32_t e = tid; e < s_nfresh; e += blockDim.x) md.touched[s_fresh_base + e] = t_fresh[e];
-    if (cnt == 0) return;
+    // wave 0 reserves the block's touched-list range now and writes it after
+    // its own pairs, so the reservation's latency overlaps pass 2
+    const uint32_t nfresh = s_nfresh;
+    uint32_t fresh_base = 0;
+    if (tid == 0 && nfresh) fresh_base = atomicAdd(&md.fs->n_touched.v, nfresh);
 
     // pass 2: write the pairs, replaying the recorded walk
     const uint32_t o = s_pair_base + off;
+    const bool fits = o + cnt <= md.pair_cap;
     uint32_t j = 0;
     int run = -1;
     unsigned long long cur = kEmptyKey;
     uint32_t pos = kNoPos, rank = 0;
     const int stp[3] = {ry.u[0] > 0.0f ? 1 : -1, ry.u[1] > 0.0f ? 1 : -1, ry.u[2] > 0.0f ? 1 : -1};
     int cc[3] = {c0[0], c0[1], c0[2]};
+    if (cnt == 0) nvis = 0;
     for (int vi = 0; vi < nvis; ++vi) {
         if (vi > 0) {
             const int si = vi - 1;
             const int ax = (int)((steps[si >> 5] >> (2 * (si & 31))) & 3ull);
-            if (ax == 0) cc[0] += stp[0];
-            else if (ax == 1) cc[1] += stp[1];
-            else cc[2] += stp[2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) cc[a] += ax == a ? stp[a] : 0;
         }
         if (!((kept >> vi) & 1ull)) continue;
         const int cx = cc[0], cy = cc[1], cz = cc[2];
@@ -501,13 +570,17 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
                 }
         }
         const uint32_t voff = (uint32_t)(((kx & 7) << 6) | ((ky & 7) << 3) | (kz & 7));
-        if (o + j < md.pair_cap) {
+        if (fits || o + j < md.pair_cap) {
             md.pair_pos[o + j] = pos;
             md.pair_rank[o + j] = rank++;
             md.pair_key[o + j] = (voff << kPidBits) | (uint32_t)i;
             md.pair_tsdf[o + j] = fminf(s, fp.tau);
         }
         j++;
+    }
+    if (tid < 64 && nfresh) {
+        const uint32_t base = __shfl(fresh_base, 0, 64);
+        for (uint32_t e = tid; e < nfresh; e += 64) md.touched[base + e] = t_fresh[e];
     }
 }
 
