@@ -819,20 +819,39 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
     float acc[KA];
 #pragma unroll
     for (int k = 0; k < KA; ++k) acc[k] = 0.0f;
-    for (uint32_t c0 = 0; c0 < n; c0 += 8) {
+    if (KMAX > 0 && !ROWS) {
+        // class counts as 8-bit fields, four classes to a word, added into acc
+        // every 255 observations (exact integers either way, so acc holds the
+        // same values as a sum of ones)
+        constexpr int KW = (KA + 3) / 4;
+        for (uint32_t c0 = 0; c0 < n; c0 += 255u) {
+            const uint32_t c1 = min(n, c0 + 255u);
+            uint32_t cw[KW];
+#pragma unroll
+            for (int w = 0; w < KW; ++w) cw[w] = 0u;
+            for (uint32_t q0 = c0; q0 < c1; q0 += 8) {
+                int lab[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const uint32_t t = q0 + q;
+                    lab[q] = t < c1 ? (labs ? labs[t] : ((const int32_t *)fp.sem)[keys[t] & kPidMask]) : -1;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int wi = lab[q] >> 2;  // -1 for no observation
+                    const uint32_t inc = 1u << ((lab[q] & 3) << 3);
+#pragma unroll
+                    for (int w = 0; w < KW; ++w) cw[w] += (w == wi) ? inc : 0u;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < KA; ++k) acc[k] += (float)((cw[k >> 2] >> ((k & 3) << 3)) & 0xFFu);
+        }
+    }
+    for (uint32_t c0 = 0; (KMAX > 0 && ROWS) && c0 < n; c0 += 8) {
         uint32_t kk[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) kk[q] = c0 + q < n ? keys[c0 + q] : 0u;
-        if (KMAX > 0 && !ROWS) {
-            int lab[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                lab[q] = c0 + q < n ? (labs ? labs[c0 + q] : ((const int32_t *)fp.sem)[kk[q] & kPidMask]) : -1;
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-#pragma unroll
-                for (int k = 0; k < KA; ++k) acc[k] += (lab[q] == k) ? 1.0f : 0.0f;
-        }
         for (int q = 0; q < 8; ++q) {
             if (c0 + q >= n) break;
             if (KMAX > 0 && ROWS) {
