@@ -267,21 +267,33 @@ typedef struct slim_frame {
 slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const slim_frame *frames, int32_t use_graph,
                                    void *stream);
 
-/* Integrates `count` frames into one map, in order: the result is the same as
- * count calls of slim_integrate / slim_integrate_rays (bit for bit), but the
- * ray walk of frame t + 1 runs on an internal stream beside the rest of frame t
- * (a second staging buffer makes them independent; the walk reads no map
- * state).  Every frame's inputs must be ready in `stream` order when the call
- * is made.  frames[i] as for slim_integrate_batched.  Queued on `stream`;
- * kernel timing (slim_profile_enable) covers single-frame calls only. */
+/* Integrates `count` frames into one map, in order: the map and the per-frame
+ * statistics afterwards are the same as after count calls of slim_integrate /
+ * slim_integrate_rays (bit for bit).  Geometry-only and label maps (int32
+ * labels, at most 32 classes, Bayesian mode) take consecutive frames in
+ * multi-frame passes (up to slim_launch_shape.pass_frames, default 2; the last
+ * frame alone): one ray walk over all their rays, one plan, bucketing, leaf
+ * kernel and commit, each voxel applying its frames' observations frame by
+ * frame, Eq. (1)-(2) and Eq. (6) as for a frame alone.  This form returns after
+ * the GPU has finished the call's work: a pass that exceeds the map's
+ * capacity or staging table is not applied, and its frames and the later ones
+ * are then integrated again one at a time, as per-frame calls would.  Other
+ * maps return at once, with the ray walk of frame t + 1 on an internal stream
+ * beside the rest of frame t (a second staging buffer makes them independent;
+ * the walk reads no map state).  Every frame's inputs must be ready in
+ * `stream` order when the call is made; at most 2^23 points in a frame.
+ * frames[i] as for slim_integrate_batched.  Queued on `stream`; kernel timing
+ * (slim_profile_enable) covers single-frame calls only. */
 slim_status slim_integrate_sequence(slim_map *map, const slim_frame *frames_host, int32_t count, void *stream);
 
 /* Grid sizes of the grid-stride kernels of integration: leaf planning and pair
- * bucketing blocks, and leaf-kernel blocks per compute unit (1 .. 32).  Results
- * do not depend on them (each voxel is reduced in point order); they only move
+ * bucketing blocks, and leaf-kernel blocks per compute unit (1 .. 32); and
+ * pass_frames, the most frames slim_integrate_sequence takes in one pass
+ * (0: the default 2, 1: one at a time, at most 8).  Results do not depend on
+ * any of them (each voxel is reduced in frame and point order); they only move
  * time.  NULL restores the defaults.  Batched calls use the shape of maps[0]. */
 typedef struct slim_launch_shape {
-    int32_t plan_blocks, bucket_blocks, leaf_blocks_per_cu, reserved;
+    int32_t plan_blocks, bucket_blocks, leaf_blocks_per_cu, pass_frames;
 } slim_launch_shape;
 slim_status slim_set_launch_shape(slim_map *map, const slim_launch_shape *shape);
 

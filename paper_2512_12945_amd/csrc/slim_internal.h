@@ -26,6 +26,7 @@ constexpr int kLeafThreads = 256;
 constexpr int kLeafBatch = 8;                // loads in flight per thread in the leaf kernel
 constexpr int kLeafLdsPairs = kLeafBatch * kLeafThreads;  // pairs a leaf holds in LDS at once
 constexpr int kNumProfiled = 5;
+constexpr int kPassFrames = 8;               // most frames integrated in one pass
 constexpr int kMaxLeafBlocksPerCu = 32;
 
 // floats of one voxel record: D, W, then the semantic state, padded to 16 bytes
@@ -60,7 +61,7 @@ struct DevState {
     unsigned long long pages_used;
     unsigned long long voxels_used;  // voxels with W > 0
     int status;       // first asynchronous error not yet reported
-    int pad0;
+    int pass_failed;  // 0, or 1 + the first frame of a multi-frame pass that could not be applied
     // last frame (written by the commit)
     long long last_points, last_rejected, last_pairs, last_touched, last_new_leaves, last_u_old, last_u_new;
     int last_status;
@@ -84,7 +85,22 @@ struct FrameParams {
     int width;
     float fx, fy, cx, cy;        // pinhole intrinsics of the depth image
     const void *sem;   // per-point semantics
+    // several consecutive frames integrated in one pass: every frame's point
+    // indices are offset so that they are distinct across the pass
+    uint32_t pid_base;                  // offset of this frame's point indices
+    int nsub;                           // frames of the pass (0 or 1: a frame on its own)
+    int pass_first;                     // the pass's first frame in its sequence call
+    uint32_t sub_start[kPassFrames + 1];  // offset of each frame of the pass, then the pass's total
+    const void *sub_sem[kPassFrames];     // per-point semantics of each frame of the pass
 };
+
+// The walk of a multi-frame pass: each frame's rays, one block range per frame.
+struct PassWalk {
+    FrameParams fp[kPassFrames];
+    int blk_start[kPassFrames + 1];
+    int nframes;
+};
+static_assert(sizeof(PassWalk) + 512 <= 4096, "the pass walk's kernel arguments fit the 4 KiB argument buffer");
 
 // Inputs and outputs of the map loss and its backward.
 struct LossParams {
@@ -208,6 +224,7 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md, const Launc
 hipError_t launch_reset(const MapDev &md, hipStream_t s);
 hipError_t launch_reset_staging(const MapDev &md, hipStream_t s);
 hipError_t launch_walk(const FrameParams &fp, const MapDev &md, hipStream_t s);
+hipError_t launch_walk_pass(const PassWalk &pw, const MapDev &md, hipStream_t s);
 hipError_t launch_after_walk(const FrameParams &fp, const MapDev &md, const LaunchShape &shape, hipStream_t s);
 hipError_t launch_loss(const FrameParams &fp, const MapDev &md, const LossParams &lp, hipStream_t s);
 hipError_t launch_backward(const FrameParams &fp, const MapDev &md, const LossParams &lp, const float *grad_scale,

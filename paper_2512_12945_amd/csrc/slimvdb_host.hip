@@ -68,12 +68,15 @@ struct BatchCtx {
     std::vector<long long> sig;   // what the captured graph was built for
 };
 
+constexpr int kDefaultPassFrames = 2;
+
 struct slim_map {
     slim_map_config cfg;
     int nsem = 0;
     int maxsteps = 0;
     int cus = 256;
     LaunchShape shape = {256, 4096, 2048};
+    int pass_frames = kDefaultPassFrames;  // frames slim_integrate_sequence integrates in one pass
     BatchCtx *batch = nullptr;
     MapDev md = {};
     size_t hcap = 0;
@@ -402,6 +405,11 @@ slim_status make_frame(slim_map *m, const float *points, const float *ranges, co
     fp->width = 0;
     fp->fx = fp->fy = fp->cx = fp->cy = 0.0f;
     fp->sem = sem;
+    fp->pid_base = 0;
+    fp->nsub = 0;
+    fp->pass_first = 0;
+    for (int f = 0; f <= kPassFrames; ++f) fp->sub_start[f] = 0;
+    for (int f = 0; f < kPassFrames; ++f) fp->sub_sem[f] = nullptr;
     return SLIM_OK;
 }
 
@@ -469,37 +477,21 @@ slim_status ensure_buffer1(slim_map *m, hipStream_t s)
     return SLIM_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-slim_status slim_integrate_sequence(slim_map *m, const slim_frame *frames, int32_t count, void *stream)
+// Frames [t0, t1) of a sequence, one at a time, with the walk of frame t + 1
+// on the walk stream beside the rest of frame t (two staging buffers).
+slim_status integrate_overlapped(slim_map *m, const std::vector<FrameParams> &fps, int t0, int t1, hipStream_t s)
 {
-    g_err[0] = 0;
-    if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
-    if (count < 0 || (count > 0 && !frames)) return fail(SLIM_ERR_INVALID, "need count >= 0 and frames");
-    if (count == 0) return SLIM_OK;
-    DeviceGuard g(m->cfg.device);
-    hipStream_t s = (hipStream_t)stream;
-    std::vector<FrameParams> fps(count);
-    int64_t nmax = 1;
-    for (int i = 0; i < count; ++i) {
-        const slim_frame &f = frames[i];
-        if (f.points && (f.ranges || f.dirs)) return fail(SLIM_ERR_INVALID, "frame %d has points and rays", i);
-        if (f.n > 0 && !f.points && !(f.ranges && f.dirs)) return fail(SLIM_ERR_INVALID, "frame %d has no points", i);
-        slim_status r = make_frame(m, f.points, f.ranges, f.dirs, f.n, f.pose, f.sem, f.sem_kind, &fps[i]);
-        if (r) return r;
-        nmax = std::max<int64_t>(nmax, f.n);
-    }
-    if (count == 1) return integrate_frame(m, fps[0], stream);
+    if (t1 - t0 == 1) return integrate_frame(m, fps[t0], s);
     slim_status r = ensure_buffer1(m, s);
     if (r) return r;
+    int64_t nmax = 1;
+    for (int t = t0; t < t1; ++t) nmax = std::max<int64_t>(nmax, fps[t].n);
     const size_t need = (size_t)nmax * (size_t)m->maxsteps;
     if ((r = ensure_pairs(m, need, s, 0)) || (r = ensure_pairs(m, need, s, 1))) return r;
     // every frame's inputs, and all earlier work on the stream, come first
     HIP_OK(hipEventRecord(m->ev_in, s));
     HIP_OK(hipStreamWaitEvent(m->wstream, m->ev_in, 0));
-    for (int t = 0; t < count; ++t) {
+    for (int t = t0; t < t1; ++t) {
         const int b = t & 1;
         const MapDev &md = b ? m->md1 : m->md;
         // the walk of frame t (on the walk stream) needs only its buffer back
@@ -513,6 +505,118 @@ slim_status slim_integrate_sequence(slim_map *m, const slim_frame *frames, int32
         m->used[b] = true;
     }
     return SLIM_OK;
+}
+
+// Frames a multi-frame pass can take: geometry, or int32 labels with at most
+// 32 classes, Bayesian mode.
+bool pass_kind(const FrameParams &fp)
+{
+    if (fp.last || fp.L > 0) return false;
+    if (fp.K == 0) return true;
+    return fp.sem_kind == SLIM_IN_LABEL_I32 && fp.K <= 32;
+}
+
+// Frames [t0, t1) in one pass on staging buffer 0: one walk over all their
+// rays (point indices offset per frame, so every observation key stays
+// distinct and frame-ordered), then one plan, bucketing, leaf kernel and
+// commit for the union of the leaves they touch.
+slim_status integrate_pass(slim_map *m, const std::vector<FrameParams> &fps, int t0, int t1, hipStream_t s)
+{
+    PassWalk pw;
+    memset(&pw, 0, sizeof(pw));
+    FrameParams base = fps[t0];
+    uint32_t off = 0;
+    int nb = 0;
+    for (int f = 0; f < t1 - t0; ++f) {
+        FrameParams fp = fps[t0 + f];
+        fp.pid_base = off;
+        pw.fp[f] = fp;
+        pw.blk_start[f] = nb;
+        nb += (fp.n + kWalkThreads - 1) / kWalkThreads;
+        base.sub_start[f] = off;
+        base.sub_sem[f] = fp.sem;
+        off += (uint32_t)fp.n;
+    }
+    pw.blk_start[t1 - t0] = nb;
+    pw.nframes = t1 - t0;
+    base.sub_start[t1 - t0] = off;
+    base.nsub = t1 - t0;
+    base.pass_first = t0;
+    base.n = (int)off;
+    slim_status r = ensure_pairs(m, (size_t)std::max<uint32_t>(off, 1u) * (size_t)m->maxsteps, s, 0);
+    if (r) return r;
+    HIP_OK(launch_walk_pass(pw, m->md, s));
+    HIP_OK(launch_after_walk(base, m->md, m->shape, s));
+    return SLIM_OK;
+}
+
+// A sequence in passes of up to m->pass_frames consecutive frames (the last
+// frame alone, so that the per-frame statistics are its own).  A pass the map
+// cannot take (capacity, staging) is not applied, nor is anything after it;
+// after the queue drains, those frames are integrated again one at a time,
+// which reproduces exactly what per-frame calls do.
+slim_status integrate_passes(slim_map *m, const std::vector<FrameParams> &fps, hipStream_t s)
+{
+    const int count = (int)fps.size();
+    auto one = [&](int t) -> slim_status {
+        slim_status r = ensure_pairs(m, (size_t)std::max<int>(fps[t].n, 1) * (size_t)m->maxsteps, s, 0);
+        if (r) return r;
+        HIP_OK(launch_walk(fps[t], m->md, s));
+        HIP_OK(launch_after_walk(fps[t], m->md, m->shape, s));
+        return SLIM_OK;
+    };
+    slim_status r = SLIM_OK;
+    int t = 0;
+    while (!r && t < count - 1) {
+        int t1 = t + 1;
+        int64_t tot = fps[t].n;
+        while (t1 < count - 1 && t1 - t < m->pass_frames && fps[t1].sem_kind == fps[t].sem_kind &&
+               tot + fps[t1].n < kMaxPoints) {
+            tot += fps[t1].n;
+            ++t1;
+        }
+        r = t1 - t == 1 ? one(t) : integrate_pass(m, fps, t, t1, s);
+        t = t1;
+    }
+    if (!r) r = one(count - 1);
+    // whatever was queued has run once the stream drains; a pass that was not
+    // applied leaves its first frame in pass_failed
+    int failed = 0;
+    HIP_OK(hipMemcpyAsync(&failed, &m->md.st->pass_failed, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (failed == 0) return r;
+    HIP_OK(hipMemsetAsync(&m->md.st->pass_failed, 0, sizeof(int), s));
+    if (r) return r;
+    return integrate_overlapped(m, fps, failed - 1, count, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+slim_status slim_integrate_sequence(slim_map *m, const slim_frame *frames, int32_t count, void *stream)
+{
+    g_err[0] = 0;
+    if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
+    if (count < 0 || (count > 0 && !frames)) return fail(SLIM_ERR_INVALID, "need count >= 0 and frames");
+    if (count == 0) return SLIM_OK;
+    DeviceGuard g(m->cfg.device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<FrameParams> fps(count);
+    for (int i = 0; i < count; ++i) {
+        const slim_frame &f = frames[i];
+        if (f.points && (f.ranges || f.dirs)) return fail(SLIM_ERR_INVALID, "frame %d has points and rays", i);
+        if (f.n > 0 && !f.points && !(f.ranges && f.dirs)) return fail(SLIM_ERR_INVALID, "frame %d has no points", i);
+        slim_status r = make_frame(m, f.points, f.ranges, f.dirs, f.n, f.pose, f.sem, f.sem_kind, &fps[i]);
+        if (r) return r;
+    }
+    if (count == 1) return integrate_frame(m, fps[0], stream);
+    if (m->pass_frames > 1 && count > 2) {
+        bool all = true;
+        for (int i = 0; i < count && all; ++i) all = pass_kind(fps[i]);
+        if (all) return integrate_passes(m, fps, s);
+    }
+    return integrate_overlapped(m, fps, 0, count, s);
 }
 
 slim_status slim_integrate(slim_map *m, const float *points, int64_t n, const double *pose, const void *sem,
@@ -812,13 +916,16 @@ slim_status slim_set_launch_shape(slim_map *m, const slim_launch_shape *shape)
     if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
     if (!shape) {
         m->shape = {m->cus, m->cus * 16, m->cus * 8};
+        m->pass_frames = kDefaultPassFrames;
         return SLIM_OK;
     }
     if (shape->plan_blocks < 1 || shape->bucket_blocks < 1 || shape->leaf_blocks_per_cu < 1 ||
         shape->plan_blocks > 65536 || shape->bucket_blocks > 65536 ||
-        shape->leaf_blocks_per_cu > kMaxLeafBlocksPerCu)
+        shape->leaf_blocks_per_cu > kMaxLeafBlocksPerCu || shape->pass_frames < 0 ||
+        shape->pass_frames > kPassFrames)
         return fail(SLIM_ERR_INVALID, "launch shape out of range");
     m->shape = {shape->plan_blocks, shape->bucket_blocks, shape->leaf_blocks_per_cu * m->cus};
+    m->pass_frames = shape->pass_frames > 0 ? shape->pass_frames : kDefaultPassFrames;
     return SLIM_OK;
 }
 

@@ -573,7 +573,7 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
         if (fits || o + j < md.pair_cap) {
             md.pair_pos[o + j] = pos;
             md.pair_rank[o + j] = rank++;
-            md.pair_key[o + j] = (voff << kPidBits) | (uint32_t)i;
+            md.pair_key[o + j] = (voff << kPidBits) | (fp.pid_base + (uint32_t)i);
             md.pair_tsdf[o + j] = fminf(s, fp.tau);
         }
         j++;
@@ -589,7 +589,8 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, 
     walk_emit_block(fp, md, blockIdx.x);
 }
 
-// Map of a block of a batched launch: the last i with start[i] <= blk.
+// Map of a block of a batched launch (frame of a multi-frame pass): the last i
+// with start[i] <= blk.
 __device__ __forceinline__ int batch_map(const int *start, int nmaps, int blk)
 {
     int lo = 0, hi = nmaps;
@@ -605,6 +606,30 @@ __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit_batch(MapBatch m
 {
     const int i = batch_map(mb.walk_start, mb.nmaps, blockIdx.x);
     walk_emit_block(mb.fps[i], mb.mds[i], blockIdx.x - mb.walk_start[i]);
+}
+
+// The rays of every frame of a multi-frame pass into one staging buffer.
+__global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit_pass(PassWalk pw, MapDev md)
+{
+    const int f = batch_map(pw.blk_start, pw.nframes, blockIdx.x);
+    walk_emit_block(pw.fp[f], md, blockIdx.x - pw.blk_start[f]);
+}
+
+// Frame (within a multi-frame pass) of sort-key point index p.
+__device__ __forceinline__ int pass_frame(const FrameParams &fp, uint32_t p)
+{
+    int f = 0;
+#pragma unroll
+    for (int q = 1; q < kPassFrames; ++q) f += (q < fp.nsub && p >= fp.sub_start[q]) ? 1 : 0;
+    return f;
+}
+
+// Class label of the observation with sort-key point index p.
+__device__ __forceinline__ int32_t point_label(const FrameParams &fp, uint32_t p)
+{
+    if (fp.nsub <= 1) return ((const int32_t *)fp.sem)[p];
+    const int f = pass_frame(fp, p);
+    return ((const int32_t *)fp.sub_sem[f])[p - fp.sub_start[f]];
 }
 
 // ---------------------------------------------------------------------------
@@ -733,7 +758,7 @@ __device__ __forceinline__ void pair_bucket_range(const FrameParams &fp, const M
         md.srt_key[dst] = key;
         md.srt_tsdf[dst] = md.pair_tsdf[i];
         // the leaf kernel's small items find the label beside the pair
-        if (labels) md.srt_lab[dst] = ((const int32_t *)fp.sem)[key & kPidMask];
+        if (labels) md.srt_lab[dst] = point_label(fp, key & kPidMask);
     }
 }
 
@@ -804,6 +829,73 @@ __device__ __forceinline__ float tsdf_mean(float D0, float W0, float W1, double 
     return (float)(((double)W0 * (double)D0 + sum_t) / (double)W1);
 }
 
+// One voxel of a multi-frame pass (geometry, or int32 labels): its
+// observations are ordered by frame, then by point, and each frame's run
+// updates the record exactly as that frame integrated alone would -- Eq.
+// (1)-(2) with the frame's binary64 sum and one rounding, Eq. (6) with the
+// frame's exact class counts -- so the pass equals the frames one by one.
+template <int KMAX>
+__device__ __forceinline__ void combine_lane_pass(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
+                                                  const float *vals, const int32_t *labs, uint32_t n, long long rec,
+                                                  bool existed)
+{
+    constexpr int KA = KMAX > 0 ? KMAX : 1;
+    constexpr int NV = (2 + KMAX + 3) / 4;
+    constexpr int KW = (KA + 3) / 4;
+    const int nv = md.rec_stride / 4, K = fp.K;
+    float4 *R = (float4 *)(md.vox + (size_t)rec * md.rec_stride);
+    float r[4 * NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const float4 x = (existed && v < nv) ? R[v] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        r[4 * v + 0] = x.x;
+        r[4 * v + 1] = x.y;
+        r[4 * v + 2] = x.z;
+        r[4 * v + 3] = x.w;
+    }
+    uint32_t q = 0;
+    while (q < n) {
+        // the run of one frame: point indices below the next frame's offset
+        const uint32_t end = fp.sub_start[pass_frame(fp, keys[q] & kPidMask) + 1];
+        uint32_t qe = q + 1;
+        while (qe < n && (keys[qe] & kPidMask) < end) ++qe;
+        const uint32_t m = qe - q;
+        const float W0 = r[1], W1 = W0 + (float)m;
+        r[0] = tsdf_mean(r[0], W0, W1, tsdf_sum(vals + q, m));
+        r[1] = W1;
+        if (KMAX > 0) {
+            if (m <= 255u) {
+                uint32_t cw[KW];
+#pragma unroll
+                for (int w = 0; w < KW; ++w) cw[w] = 0u;
+                for (uint32_t t = q; t < qe; ++t) {
+                    const int lab = labs ? labs[t] : point_label(fp, keys[t] & kPidMask);
+                    const int wi = lab >> 2;
+                    const uint32_t inc = 1u << ((lab & 3) << 3);
+#pragma unroll
+                    for (int w = 0; w < KW; ++w) cw[w] += (w == wi) ? inc : 0u;
+                }
+#pragma unroll
+                for (int k = 0; k < KA; ++k)
+                    if (k < K) r[2 + k] += (float)((cw[k >> 2] >> ((k & 3) << 3)) & 0xFFu);
+            } else {
+#pragma unroll
+                for (int k = 0; k < KA; ++k) {
+                    if (k >= K) break;
+                    uint32_t c = 0;
+                    for (uint32_t t = q; t < qe; ++t)
+                        c += (labs ? labs[t] : point_label(fp, keys[t] & kPidMask)) == k ? 1u : 0u;
+                    r[2 + k] += (float)c;
+                }
+            }
+        }
+        q = qe;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        if (v < nv) R[v] = make_float4(r[4 * v + 0], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
+}
+
 // One voxel, one lane: its n observations sit at keys[0..n) / vals[0..n) in
 // point order.  Closed set with K <= KMAX classes in registers (KMAX = 0:
 // geometry only); ROWS: probability or logit rows, else int32 labels.  The
@@ -813,6 +905,10 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
                                              const float *vals, const int32_t *labs, uint32_t n, long long rec,
                                              bool existed)
 {
+    if (!ROWS && fp.nsub > 1) {
+        combine_lane_pass<KMAX>(fp, md, keys, vals, labs, n, rec, existed);
+        return;
+    }
     constexpr int KA = KMAX > 0 ? KMAX : 1;
     constexpr int NV = (2 + KMAX + 3) / 4;
     const int nv = md.rec_stride / 4, K = fp.K;
@@ -834,7 +930,7 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const uint32_t t = q0 + q;
-                    lab[q] = t < c1 ? (labs ? labs[t] : ((const int32_t *)fp.sem)[keys[t] & kPidMask]) : -1;
+                    lab[q] = t < c1 ? (labs ? labs[t] : point_label(fp, keys[t] & kPidMask)) : -1;
                 }
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
@@ -1170,14 +1266,53 @@ __device__ __forceinline__ void combine_last_wave(const FrameParams &fp, const M
 
 // Combines every touched voxel with offset in [o0, o1); the sorted pairs of
 // bin o sit at keys[bin0[o] - base] / vals[bin0[o] - base] (LDS or global).
+// Bits of touched-mask word w that fall in offsets [o0, o1).
+__device__ __forceinline__ uint32_t range_bits(uint32_t bits, uint32_t w, uint32_t o0, uint32_t o1)
+{
+    if ((w << 5) < o0) bits &= ~0u << (o0 & 31);
+    if (((w + 1) << 5) > o1) bits &= (o1 & 31) ? ((1u << (o1 & 31)) - 1u) : ~0u;
+    return bits;
+}
+
+// Position of the k-th set bit (from 0) of x, which has more than k set bits.
+__device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t k)
+{
+    uint32_t pos = 0;
+#pragma unroll
+    for (int s = 16; s > 0; s >>= 1) {
+        const uint32_t low = x & ((1u << s) - 1u), c = (uint32_t)__popc(low);
+        if (k >= c) {
+            k -= c;
+            x >>= s;
+            pos += (uint32_t)s;
+        } else {
+            x = low;
+        }
+    }
+    return pos;
+}
+
 template <int KMAX, bool WAVE, bool ROWS>
 __device__ void combine_range(const FrameParams &fp, const MapDev &md, LeafShared &sh, const uint32_t *keys,
                               const float *vals, const int32_t *labs, uint32_t o0, uint32_t o1, uint32_t base)
 {
     if (!WAVE) {
-        for (uint32_t o = o0 + threadIdx.x; o < o1; o += blockDim.x) {
+        // thread t takes the touched offsets of rank t, t + blockDim.x, ... in
+        // [o0, o1), so a leaf with at most blockDim.x touched voxels loads its
+        // records in one round
+        const uint32_t w0 = o0 >> 5, w1 = (o1 - 1) >> 5;
+        uint32_t cnt = 0;
+        for (uint32_t w = w0; w <= w1; ++w) cnt += __popc(range_bits(sh.touch[w], w, o0, o1));
+        for (uint32_t r = threadIdx.x; r < cnt; r += blockDim.x) {
+            uint32_t w = w0, before = 0, bits = 0;
+            for (; w <= w1; ++w) {
+                bits = range_bits(sh.touch[w], w, o0, o1);
+                const uint32_t c = __popc(bits);
+                if (r < before + c) break;
+                before += c;
+            }
+            const uint32_t o = (w << 5) + select_bit(bits, r - before);
             const uint32_t n = sh.hist[o];
-            if (!n) continue;
             const long long rec = (long long)sh.pages[o >> 6] * kPageVoxels + (o & (kPageVoxels - 1));
             const bool existed = (sh.occ0[o >> 5] >> (o & 31)) & 1u;
             if (KMAX < 0)
@@ -1380,7 +1515,7 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
         if (KMAX > 0 && !ROWS && !WAVE && fits && ok) {
             // the labels of the sorted pairs, gathered once into the free binning array
             for (uint32_t t = tid; t < hi - lo; t += blockDim.x)
-                sh.b_key[t] = (uint32_t)((const int32_t *)fp.sem)[sh.a_key[t] & kPidMask];
+                sh.b_key[t] = (uint32_t)point_label(fp, sh.a_key[t] & kPidMask);
             __syncthreads();
             labs = (const int32_t *)sh.b_key;
         }
@@ -1601,7 +1736,8 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
     const uint32_t nt = md.fs->n_touched.v;
     const uint32_t nbig = min(md.fs->work_big.v, md.work_cap);
     const unsigned long long lused = st->leaves_used;
-    const bool ok = md.fs->frame_err.v == 0 && lused + md.fs->new_leaves.v <= (unsigned long long)md.max_leaves &&
+    const bool ok = md.fs->frame_err.v == 0 && st->pass_failed == 0 &&
+                    lused + md.fs->new_leaves.v <= (unsigned long long)md.max_leaves &&
                     st->pages_used + md.fs->new_pages.v <= (unsigned long long)md.max_pages;
     if (threadIdx.x == 0) {
         sh.uold = 0;
@@ -1732,23 +1868,32 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
     }
     if (threadIdx.x == 0) {
         const unsigned long long nl = md.fs->new_leaves.v, np = md.fs->new_pages.v;
-        const bool ok = md.fs->frame_err.v == 0 && st->leaves_used + nl <= (unsigned long long)md.max_leaves &&
+        // after a multi-frame pass that could not be applied, the frames that
+        // follow it in the same sequence call are skipped too: the host
+        // integrates them again one by one
+        const bool skipped = st->pass_failed != 0;
+        const bool ok = !skipped && md.fs->frame_err.v == 0 &&
+                        st->leaves_used + nl <= (unsigned long long)md.max_leaves &&
                         st->pages_used + np <= (unsigned long long)md.max_pages;
         if (ok) {
             st->leaves_used += nl;
             st->pages_used += np;
             st->voxels_used += s_new[0];
-        } else if (st->status == SLIM_OK) {
+        } else if (!skipped && fp.nsub > 1) {
+            st->pass_failed = 1 + fp.pass_first;
+        } else if (!skipped && st->status == SLIM_OK) {
             st->status = SLIM_ERR_CAPACITY;
         }
-        st->last_points = fp.n;
-        st->last_rejected = md.fs->rejected.v;
-        st->last_pairs = md.fs->pairs.v;
-        st->last_touched = md.fs->n_touched.v;
-        st->last_new_leaves = nl;
-        st->last_u_old = (long long)s_old[0];
-        st->last_u_new = (long long)s_new[0];
-        st->last_status = ok ? SLIM_OK : SLIM_ERR_CAPACITY;
+        if (!skipped && (ok || fp.nsub <= 1)) {
+            st->last_points = fp.n;
+            st->last_rejected = md.fs->rejected.v;
+            st->last_pairs = md.fs->pairs.v;
+            st->last_touched = md.fs->n_touched.v;
+            st->last_new_leaves = nl;
+            st->last_u_old = (long long)s_old[0];
+            st->last_u_new = (long long)s_new[0];
+            st->last_status = ok ? SLIM_OK : SLIM_ERR_CAPACITY;
+        }
         md.fs->n_touched.v = 0;
         md.fs->pairs.v = 0;
         md.fs->rejected.v = 0;
@@ -1921,6 +2066,13 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const La
     rec(8);
     hipLaunchKernelGGL(k_frame_commit, dim3(1), dim3(256), 0, s, fp, md);
     rec(9);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_pass(const PassWalk &pw, const MapDev &md, hipStream_t s)
+{
+    const int nb = pw.blk_start[pw.nframes];
+    hipLaunchKernelGGL(k_ray_walk_emit_pass, dim3(nb > 0 ? nb : 1), dim3(kWalkThreads), 0, s, pw, md);
     return hipGetLastError();
 }
 

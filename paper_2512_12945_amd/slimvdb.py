@@ -60,7 +60,7 @@ class Frame(ctypes.Structure):
 
 class LaunchShape(ctypes.Structure):
     _fields_ = [("plan_blocks", ctypes.c_int32), ("bucket_blocks", ctypes.c_int32),
-                ("leaf_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("leaf_blocks_per_cu", ctypes.c_int32), ("pass_frames", ctypes.c_int32)]
 
 
 class SlimError(RuntimeError):
@@ -241,12 +241,17 @@ class Map:
                                   _stream(self.device)))
         return dict(D=d[:m], W=w[:m], sem=sem[:m, : self.nsem])
 
-    def set_launch_shape(self, plan_blocks=None, bucket_blocks=None, leaf_blocks_per_cu=None):
-        """Grid sizes of the grid-stride kernels; all None restores the defaults."""
-        if plan_blocks is None and bucket_blocks is None and leaf_blocks_per_cu is None:
+    def set_launch_shape(self, plan_blocks=None, bucket_blocks=None, leaf_blocks_per_cu=None, pass_frames=0):
+        """Grid sizes of the grid-stride kernels and the frames integrate_sequence
+        takes in one pass (0: the default, 1: one at a time); all None / 0
+        restores the defaults, grid sizes left None take their defaults."""
+        if plan_blocks is None and bucket_blocks is None and leaf_blocks_per_cu is None and not pass_frames:
             _check(self._L.slim_set_launch_shape(self.h, None))
         else:
-            sh = LaunchShape(plan_blocks, bucket_blocks, leaf_blocks_per_cu, 0)
+            cus = torch.cuda.get_device_properties(self.device).multi_processor_count
+            sh = LaunchShape(cus if plan_blocks is None else plan_blocks,
+                             16 * cus if bucket_blocks is None else bucket_blocks,
+                             8 if leaf_blocks_per_cu is None else leaf_blocks_per_cu, int(pass_frames))
             _check(self._L.slim_set_launch_shape(self.h, ctypes.byref(sh)))
 
     def profile(self, enable=True):

@@ -1,6 +1,8 @@
-"""slim_integrate_sequence (the walk of each next frame overlapping the rest
-of the current one on a second staging buffer) gives bitwise the map of one
-slim_integrate call per frame, interleaved with single frames and resets."""
+"""slim_integrate_sequence gives bitwise the map (and last-frame statistics)
+of one slim_integrate call per frame, interleaved with single frames and
+resets: label and geometry maps through multi-frame passes of every size, with
+empty frames and a pass that exceeds the leaf capacity; open-set maps with the
+walk of each next frame overlapping the rest of the current one."""
 import numpy as np
 import pytest
 import torch
@@ -86,4 +88,79 @@ def test_sequence_open_set():
     for f in frames:
         ref.integrate(f["points"], f["pose"], f["sem"], f["kind"])
     sv.integrate_sequence(seq, frames)
+    _same(extract_np(ref), extract_np(seq))
+
+
+def _stats_status(m):
+    """Statistics and the asynchronous error they report (0 if none)."""
+    try:
+        return m.stats(), 0
+    except sv.SlimError as e:
+        return m.stats(), e.code
+
+
+@pytest.mark.parametrize("pass_frames", [1, 2, 3, 8])
+def test_sequence_pass_sizes(sweeps, pass_frames):
+    # geometry and label maps take consecutive frames in multi-frame passes:
+    # every pass size gives the per-frame map and the last frame's statistics
+    ref, seq = _map(), _map()
+    seq.set_launch_shape(pass_frames=pass_frames)
+    for f in sweeps:
+        ref.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+    sv.integrate_sequence(seq, sweeps)
+    assert ref.stats() == seq.stats()
+    _same(extract_np(ref), extract_np(seq))
+
+
+def test_sequence_geometry_only(sweeps):
+    ref = sv.Map(0.1, 0.3, 0.0, 50.0, sv.SEM_NONE, 0, 0, 0, 1 << 16, 1 << 22)
+    seq = sv.Map(0.1, 0.3, 0.0, 50.0, sv.SEM_NONE, 0, 0, 0, 1 << 16, 1 << 22)
+    frames = [dict(points=f["points"], pose=f["pose"]) for f in sweeps]
+    for f in frames:
+        ref.integrate(f["points"], f["pose"])
+    sv.integrate_sequence(seq, frames)
+    assert ref.stats() == seq.stats()
+    _same(extract_np(ref), extract_np(seq))
+
+
+def test_sequence_empty_frames_inside_passes(sweeps):
+    empty = dict(points=torch.zeros((0, 3), dtype=torch.float32, device="cuda"), pose=sweeps[0]["pose"],
+                 sem=torch.zeros(0, dtype=torch.int32, device="cuda"), kind=sv.IN_LABEL_I32)
+    frames = [sweeps[0], empty, sweeps[1], sweeps[2], empty, empty, sweeps[3], sweeps[4]]
+    ref, seq = _map(), _map()
+    for f in frames:
+        ref.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+    sv.integrate_sequence(seq, frames)
+    assert ref.stats() == seq.stats()
+    _same(extract_np(ref), extract_np(seq))
+
+
+def test_sequence_capacity_fallback(sweeps):
+    # a leaf capacity that frame 4 exceeds: the pass holding it is not applied,
+    # and its frames and the later ones are integrated again one at a time,
+    # ending exactly where per-frame calls end (rejected frames, error status)
+    big = _map()
+    leaves = []
+    for f in sweeps:
+        big.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+        leaves.append(big.stats()["leaves"])
+    assert leaves[4] > leaves[3] + 1
+    cap = (leaves[3] + leaves[4]) // 2
+    ref = sv.Map(0.1, 0.3, 0.0, 50.0, sv.SEM_CLOSED, 20, 0, 0, cap, 1 << 22)
+    seq = sv.Map(0.1, 0.3, 0.0, 50.0, sv.SEM_CLOSED, 20, 0, 0, cap, 1 << 22)
+    for f in sweeps:
+        ref.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+    sv.integrate_sequence(seq, sweeps)
+    st_ref, err_ref = _stats_status(ref)
+    st_seq, err_seq = _stats_status(seq)
+    assert err_ref == sv.ERR_CAPACITY and err_seq == err_ref
+    assert st_ref == st_seq and st_ref["leaves"] <= cap
+    _same(extract_np(ref), extract_np(seq))
+    # the map keeps taking passes afterwards
+    ref.reset()
+    seq.reset()
+    for f in sweeps[:3]:
+        ref.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+    sv.integrate_sequence(seq, sweeps[:3])
+    assert ref.stats() == seq.stats()
     _same(extract_np(ref), extract_np(seq))
