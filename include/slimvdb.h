@@ -283,7 +283,8 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
  * the walk reads no map state).  Every frame's inputs must be ready in
  * `stream` order when the call is made; at most 2^23 points in a frame.
  * frames[i] as for slim_integrate_batched.  Queued on `stream`; kernel timing
- * (slim_profile_enable) covers single-frame calls only. */
+ * (slim_profile_enable) covers the pass form (one launch set per pass) and
+ * single-frame calls, not the overlapped form. */
 slim_status slim_integrate_sequence(slim_map *map, const slim_frame *frames_host, int32_t count, void *stream);
 
 /* Grid sizes of the grid-stride kernels of integration: leaf planning and pair
@@ -297,7 +298,8 @@ typedef struct slim_launch_shape {
 } slim_launch_shape;
 slim_status slim_set_launch_shape(slim_map *map, const slim_launch_shape *shape);
 
-/* Kernel timing.  While enabled, slim_integrate brackets each of its kernels
+/* Kernel timing.  While enabled, slim_integrate (and each pass of
+ * slim_integrate_sequence) brackets each of its kernels
  * with HIP events on the stream it launches on; slim_profile_read returns the
  * accumulated per-kernel time in milliseconds and launch counts (index 0 ray
  * walk and pair emission, 1 leaf planning, 2 pair bucketing, 3 per-leaf sort,

@@ -220,11 +220,11 @@ __host__ __device__ inline unsigned long long pack_leaf(int lx, int ly, int lz)
 
 // kernel launchers (slimvdb_kernels.hip)
 hipError_t launch_integrate(const FrameParams &fp, const MapDev &md, const LaunchShape &shape, hipStream_t s,
-                            hipEvent_t *ev /* 2 * kNumProfiled events or nullptr */);
+                            hipEvent_t *ev /* 2 * kNumProfiled events or nullptr */,
+                            const PassWalk *pw = nullptr /* the walk of a multi-frame pass */);
 hipError_t launch_reset(const MapDev &md, hipStream_t s);
 hipError_t launch_reset_staging(const MapDev &md, hipStream_t s);
 hipError_t launch_walk(const FrameParams &fp, const MapDev &md, hipStream_t s);
-hipError_t launch_walk_pass(const PassWalk &pw, const MapDev &md, hipStream_t s);
 hipError_t launch_after_walk(const FrameParams &fp, const MapDev &md, const LaunchShape &shape, hipStream_t s);
 hipError_t launch_loss(const FrameParams &fp, const MapDev &md, const LossParams &lp, hipStream_t s);
 hipError_t launch_backward(const FrameParams &fp, const MapDev &md, const LossParams &lp, const float *grad_scale,

@@ -413,7 +413,9 @@ slim_status make_frame(slim_map *m, const float *points, const float *ranges, co
     return SLIM_OK;
 }
 
-slim_status integrate_frame(slim_map *m, const FrameParams &fp, void *stream)
+// One frame, or with pw the frames of a multi-frame pass (fp then describes the
+// pass: n is its total of points), with kernel timing events while enabled.
+slim_status integrate_frame(slim_map *m, const FrameParams &fp, void *stream, const PassWalk *pw = nullptr)
 {
     DeviceGuard g(m->cfg.device);
     hipStream_t s = (hipStream_t)stream;
@@ -436,7 +438,7 @@ slim_status integrate_frame(slim_map *m, const FrameParams &fp, void *stream)
         m->prof_head = (m->prof_head + 1) % kProfRing;
         m->prof_count++;
     }
-    HIP_OK(launch_integrate(fp, m->md, m->shape, s, ev));
+    HIP_OK(launch_integrate(fp, m->md, m->shape, s, ev, pw));
     return SLIM_OK;
 }
 
@@ -543,11 +545,7 @@ slim_status integrate_pass(slim_map *m, const std::vector<FrameParams> &fps, int
     base.nsub = t1 - t0;
     base.pass_first = t0;
     base.n = (int)off;
-    slim_status r = ensure_pairs(m, (size_t)std::max<uint32_t>(off, 1u) * (size_t)m->maxsteps, s, 0);
-    if (r) return r;
-    HIP_OK(launch_walk_pass(pw, m->md, s));
-    HIP_OK(launch_after_walk(base, m->md, m->shape, s));
-    return SLIM_OK;
+    return integrate_frame(m, base, s, &pw);
 }
 
 // A sequence in passes of up to m->pass_frames consecutive frames (the last
@@ -558,13 +556,7 @@ slim_status integrate_pass(slim_map *m, const std::vector<FrameParams> &fps, int
 slim_status integrate_passes(slim_map *m, const std::vector<FrameParams> &fps, hipStream_t s)
 {
     const int count = (int)fps.size();
-    auto one = [&](int t) -> slim_status {
-        slim_status r = ensure_pairs(m, (size_t)std::max<int>(fps[t].n, 1) * (size_t)m->maxsteps, s, 0);
-        if (r) return r;
-        HIP_OK(launch_walk(fps[t], m->md, s));
-        HIP_OK(launch_after_walk(fps[t], m->md, m->shape, s));
-        return SLIM_OK;
-    };
+    auto one = [&](int t) -> slim_status { return integrate_frame(m, fps[t], s); };
     slim_status r = SLIM_OK;
     int t = 0;
     while (!r && t < count - 1) {

@@ -2039,7 +2039,7 @@ static void launch_leaf_batch(int kind, const MapBatch &mb, int blocks, hipStrea
 }
 
 hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const LaunchShape &shape, hipStream_t s,
-                            hipEvent_t *ev)
+                            hipEvent_t *ev, const PassWalk *pw)
 {
     MapDev md = md_in;
     md.leaf_blocks = shape.leaf_blocks;
@@ -2048,7 +2048,12 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const La
         if (ev) (void)hipEventRecord(ev[e], s);
     };
     rec(0);
-    hipLaunchKernelGGL(k_ray_walk_emit, dim3(bw > 0 ? bw : 1), dim3(kWalkThreads), 0, s, fp, md);
+    if (pw) {
+        const int nb = pw->blk_start[pw->nframes];
+        hipLaunchKernelGGL(k_ray_walk_emit_pass, dim3(nb > 0 ? nb : 1), dim3(kWalkThreads), 0, s, *pw, md);
+    } else {
+        hipLaunchKernelGGL(k_ray_walk_emit, dim3(bw > 0 ? bw : 1), dim3(kWalkThreads), 0, s, fp, md);
+    }
     rec(1);
     rec(2);
     hipLaunchKernelGGL(k_leaf_plan, dim3(shape.plan_blocks), dim3(256), 0, s, md);
@@ -2066,13 +2071,6 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const La
     rec(8);
     hipLaunchKernelGGL(k_frame_commit, dim3(1), dim3(256), 0, s, fp, md);
     rec(9);
-    return hipGetLastError();
-}
-
-hipError_t launch_walk_pass(const PassWalk &pw, const MapDev &md, hipStream_t s)
-{
-    const int nb = pw.blk_start[pw.nframes];
-    hipLaunchKernelGGL(k_ray_walk_emit_pass, dim3(nb > 0 ? nb : 1), dim3(kWalkThreads), 0, s, pw, md);
     return hipGetLastError();
 }
 
