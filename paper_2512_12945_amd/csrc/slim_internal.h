@@ -134,16 +134,24 @@ struct alignas(16) LeafItem {
 };
 static_assert(sizeof(LeafItem) == 128, "a leaf item is 128 bytes");
 
+// One slot of the leaf table: packed leaf key (kEmptyKey: free) and leaf
+// slot, read together with one 16-byte load.
+struct alignas(16) HashSlot {
+    unsigned long long key;
+    int32_t val;
+    int32_t pad;
+};
+
 // Device pointers of one map.
 struct MapDev {
     // leaf table: packed leaf key -> leaf slot, open addressing, cap = hmask + 1
-    unsigned long long *hkeys;
-    int32_t *hvals;
+    HashSlot *htab;
     uint32_t hmask;
     // staging table of the leaves one frame touches (same capacity), and
     // per-position frame data
     unsigned long long *skeys;
     uint32_t *touched;   // staging positions in insertion order
+    unsigned long long *touched_key;  // their packed leaf keys
     uint32_t *pos_count; // pairs per position
     uint32_t *pos_slab;  // x-slabs of the leaf the frame touches (8 bits)
     int4 *pos_plan;      // (slot or -1, new-leaf index, bucket start, 0)
@@ -160,8 +168,7 @@ struct MapDev {
     float *vox;
     int rec_stride;
     // per-frame pair buffers
-    uint32_t *pair_pos;   // staging position of the pair's leaf
-    uint32_t *pair_rank;  // rank of the pair inside its leaf's bucket
+    uint2 *pair_pr;       // (staging position of the pair's leaf, rank of the pair inside its leaf's bucket)
     uint32_t *pair_key;   // (offset << 23) | point index
     float *pair_tsdf;     // truncated signed distance (FP32)
     uint32_t *srt_key;    // pairs grouped by leaf

@@ -197,14 +197,15 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s, int buf = 0)
     size_t cap = std::max<size_t>(need, pcap + pcap / 2);
     cap = std::min<size_t>(cap, 0xFFFFFFF0ull);
     MapDev &md = buf ? m->md1 : m->md;
-    void *ptrs[11] = {md.pair_pos, md.pair_rank, md.pair_key, md.pair_tsdf, md.srt_key, md.srt_tsdf,
-                      md.srt_lab,  md.tmp_key,   md.tmp_tsdf, md.work,      md.vox_list};
+    void *ptrs[10] = {md.pair_pr, md.pair_key, md.pair_tsdf, md.srt_key, md.srt_tsdf,
+                      md.srt_lab, md.tmp_key,  md.tmp_tsdf, md.work,     md.vox_list};
     for (void *p : ptrs) {
         if (!p) continue;
         (void)hipFree(p);
         m->allocs.erase(std::remove(m->allocs.begin(), m->allocs.end(), p), m->allocs.end());
     }
-    md.pair_pos = md.pair_rank = md.pair_key = md.srt_key = md.tmp_key = nullptr;
+    md.pair_pr = nullptr;
+    md.pair_key = md.srt_key = md.tmp_key = nullptr;
     md.pair_tsdf = md.srt_tsdf = md.tmp_tsdf = nullptr;
     md.srt_lab = nullptr;
     md.work = nullptr;
@@ -212,7 +213,7 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s, int buf = 0)
     // a large leaf has more than kLeafLdsPairs pairs and at most 8 slab items
     const size_t wcap = cap / (kLeafLdsPairs / kLeafPages) + kLeafPages;
     slim_status r;
-    if ((r = dalloc(m, &md.pair_pos, cap)) || (r = dalloc(m, &md.pair_rank, cap)) ||
+    if ((r = dalloc(m, &md.pair_pr, cap)) ||
         (r = dalloc(m, &md.pair_key, cap)) || (r = dalloc(m, &md.pair_tsdf, cap)) ||
         (r = dalloc(m, &md.srt_key, cap)) || (r = dalloc(m, &md.srt_tsdf, cap)) ||
         (r = dalloc(m, &md.srt_lab, cap)) || (r = dalloc(m, &md.tmp_key, cap)) ||
@@ -294,8 +295,9 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
     md.rec_stride = record_stride(m->nsem);
     md.leaf_blocks = m->cus * 8;
     const size_t L = (size_t)config->max_leaves, NP = (size_t)md.max_pages;
-    if ((r = dalloc(m, &md.hkeys, cap)) || (r = dalloc(m, &md.hvals, cap)) || (r = dalloc(m, &md.skeys, cap)) ||
-        (r = dalloc(m, &md.touched, cap)) || (r = dalloc(m, &md.pos_count, cap)) ||
+    if ((r = dalloc(m, &md.htab, cap)) || (r = dalloc(m, &md.skeys, cap)) ||
+        (r = dalloc(m, &md.touched, cap)) || (r = dalloc(m, &md.touched_key, cap)) ||
+        (r = dalloc(m, &md.pos_count, cap)) ||
         (r = dalloc(m, &md.pos_slab, cap)) || (r = dalloc(m, &md.pos_plan, cap)) ||
         (r = dalloc(m, &md.pos_pages, 2 * cap)) || (r = dalloc(m, &md.items, cap)) ||
         (r = dalloc(m, &md.med_list, cap)) || (r = dalloc(m, &md.small_list, cap)) ||
@@ -450,11 +452,13 @@ slim_status ensure_buffer1(slim_map *m, hipStream_t s)
     MapDev md = m->md;
     md.skeys = nullptr;
     md.touched = md.pos_count = md.pos_slab = nullptr;
+    md.touched_key = nullptr;
     md.pos_plan = md.pos_pages = nullptr;
     md.items = nullptr;
     md.med_list = md.small_list = nullptr;
     md.fs = nullptr;
-    md.pair_pos = md.pair_rank = md.pair_key = md.srt_key = md.tmp_key = nullptr;
+    md.pair_pr = nullptr;
+    md.pair_key = md.srt_key = md.tmp_key = nullptr;
     md.pair_tsdf = md.srt_tsdf = md.tmp_tsdf = nullptr;
     md.srt_lab = nullptr;
     md.work = nullptr;
@@ -463,7 +467,8 @@ slim_status ensure_buffer1(slim_map *m, hipStream_t s)
     md.work_cap = 0;
     const size_t cap = m->hcap;
     slim_status r;
-    if ((r = dalloc(m, &md.skeys, cap)) || (r = dalloc(m, &md.touched, cap)) || (r = dalloc(m, &md.pos_count, cap)) ||
+    if ((r = dalloc(m, &md.skeys, cap)) || (r = dalloc(m, &md.touched, cap)) ||
+        (r = dalloc(m, &md.touched_key, cap)) || (r = dalloc(m, &md.pos_count, cap)) ||
         (r = dalloc(m, &md.pos_slab, cap)) || (r = dalloc(m, &md.pos_plan, cap)) ||
         (r = dalloc(m, &md.pos_pages, 2 * cap)) || (r = dalloc(m, &md.items, cap)) ||
         (r = dalloc(m, &md.med_list, cap)) || (r = dalloc(m, &md.small_list, cap)) || (r = dalloc(m, &md.fs, 1)))

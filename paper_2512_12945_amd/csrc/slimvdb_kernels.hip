@@ -59,8 +59,9 @@ __device__ int32_t map_find(const MapDev &md, unsigned long long key)
 {
     uint32_t h = leaf_hash(key, md.hmask);
     for (uint32_t probe = 0; probe <= md.hmask; ++probe) {
-        unsigned long long k = md.hkeys[h];
-        if (k == key) return md.hvals[h];
+        const uint4 e = *(const uint4 *)&md.htab[h];
+        const unsigned long long k = ((unsigned long long)e.y << 32) | e.x;
+        if (k == key) return (int32_t)e.z;
         if (k == kEmptyKey) return -1;
         h = (h + 1) & md.hmask;
     }
@@ -72,9 +73,9 @@ __device__ void map_insert(const MapDev &md, unsigned long long key, int32_t slo
 {
     uint32_t h = leaf_hash(key, md.hmask);
     for (uint32_t probe = 0; probe <= md.hmask; ++probe) {
-        unsigned long long prev = atomicCAS(&md.hkeys[h], kEmptyKey, key);
+        unsigned long long prev = atomicCAS(&md.htab[h].key, kEmptyKey, key);
         if (prev == kEmptyKey) {
-            md.hvals[h] = slot;
+            md.htab[h].val = slot;
             return;
         }
         h = (h + 1) & md.hmask;
@@ -369,7 +370,7 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
     __shared__ uint32_t t_pos[kWalkTable];   // staging position
     __shared__ uint32_t t_slab[kWalkTable];  // x-slabs of the leaf this block touches
     __shared__ uint32_t t_list[kWalkTable];  // occupied entries
-    __shared__ uint32_t t_fresh[kWalkTable]; // staging positions this block inserted
+    __shared__ uint32_t t_fresh[kWalkTable]; // entries whose staging insert this block made
     __shared__ uint32_t s_n, s_nfresh, s_pair_base, wsum[4];
 
     const int tid = threadIdx.x;
@@ -524,7 +525,7 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
         if (pos != kNoPos) {
             t_cnt[h] = atomicAdd(&md.pos_count[pos], t_cnt[h]);
             atomicOr(&md.pos_slab[pos], t_slab[h]);
-            if (fresh) t_fresh[atomicAdd(&s_nfresh, 1u)] = pos;
+            if (fresh) t_fresh[atomicAdd(&s_nfresh, 1u)] = h;
         } else {
             atomicOr(&md.fs->frame_err.v, 1u);
         }
@@ -571,8 +572,7 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
         }
         const uint32_t voff = (uint32_t)(((kx & 7) << 6) | ((ky & 7) << 3) | (kz & 7));
         if (fits || o + j < md.pair_cap) {
-            md.pair_pos[o + j] = pos;
-            md.pair_rank[o + j] = rank++;
+            md.pair_pr[o + j] = make_uint2(pos, rank++);
             md.pair_key[o + j] = (voff << kPidBits) | (fp.pid_base + (uint32_t)i);
             md.pair_tsdf[o + j] = fminf(s, fp.tau);
         }
@@ -580,7 +580,11 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
     }
     if (tid < 64 && nfresh) {
         const uint32_t base = __shfl(fresh_base, 0, 64);
-        for (uint32_t e = tid; e < nfresh; e += 64) md.touched[base + e] = t_fresh[e];
+        for (uint32_t e = tid; e < nfresh; e += 64) {
+            const uint32_t h = t_fresh[e];
+            md.touched[base + e] = t_pos[h];
+            md.touched_key[base + e] = t_key[h];
+        }
     }
 }
 
@@ -646,18 +650,24 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
         const bool act = j < nt;
         int32_t slot = -1;
         uint32_t npairs = 0, pos = 0, need = 0;
+        unsigned long long key = kEmptyKey;
+        uint4 occ[4] = {make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u),
+                        make_uint4(0u, 0u, 0u, 0u)};
         int pg[kLeafPages];
 #pragma unroll
         for (int q = 0; q < kLeafPages; ++q) pg[q] = -1;
         if (act) {
             pos = md.touched[j];
-            slot = map_find(md, md.skeys[pos]);
+            key = md.touched_key[j];
+            slot = map_find(md, key);
             npairs = md.pos_count[pos];
             uint32_t have = 0;
             if (slot >= 0) {
                 const int4 p0 = ((const int4 *)md.leaf_page)[2 * slot], p1 = ((const int4 *)md.leaf_page)[2 * slot + 1];
                 pg[0] = p0.x; pg[1] = p0.y; pg[2] = p0.z; pg[3] = p0.w;
                 pg[4] = p1.x; pg[5] = p1.y; pg[6] = p1.z; pg[7] = p1.w;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) occ[q] = ((const uint4 *)md.leaf_occ)[(size_t)slot * 4 + q];
 #pragma unroll
                 for (int q = 0; q < kLeafPages; ++q) have |= (pg[q] >= 0 ? 1u : 0u) << q;
             }
@@ -718,14 +728,12 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
             md.pos_plan[pos] = make_int4(slot, slot < 0 ? (int)newleaf : -1, (int)bstart, 0);
             // the leaf kernel's item: header, pages, occupancy before this frame
             uint4 *it = (uint4 *)&md.items[j];
-            const unsigned long long key = md.skeys[pos];
             it[0] = make_uint4(pos, npairs, bstart, (uint32_t)(slot >= 0 ? slot : -1 - (int)newleaf));
             it[1] = make_uint4(tslabs, 0u, (uint32_t)key, (uint32_t)(key >> 32));
             it[2] = make_uint4((uint32_t)pg[0], (uint32_t)pg[1], (uint32_t)pg[2], (uint32_t)pg[3]);
             it[3] = make_uint4((uint32_t)pg[4], (uint32_t)pg[5], (uint32_t)pg[6], (uint32_t)pg[7]);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                it[4 + q] = slot >= 0 ? ((const uint4 *)md.leaf_occ)[(size_t)slot * 4 + q] : make_uint4(0u, 0u, 0u, 0u);
+            for (int q = 0; q < 4; ++q) it[4 + q] = occ[q];
         }
     }
 }
@@ -751,9 +759,10 @@ __device__ __forceinline__ void pair_bucket_range(const FrameParams &fp, const M
     const uint32_t stride = nblk * blockDim.x;
     const bool labels = fp.K > 0 && fp.sem_kind == SLIM_IN_LABEL_I32;
     for (uint32_t i = blk * blockDim.x + threadIdx.x; i < P; i += stride) {
-        const uint32_t pos = md.pair_pos[i];
+        const uint2 pr = md.pair_pr[i];
+        const uint32_t pos = pr.x;
         if (pos == kNoPos) continue;
-        const uint32_t dst = (uint32_t)md.pos_plan[pos].z + md.pair_rank[i];
+        const uint32_t dst = (uint32_t)md.pos_plan[pos].z + pr.y;
         const uint32_t key = md.pair_key[i];
         md.srt_key[dst] = key;
         md.srt_tsdf[dst] = md.pair_tsdf[i];
@@ -1389,16 +1398,29 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
     // in flight per thread, and a whole leaf that fits LDS stays in registers
     uint32_t rk[kLeafBatch];
     float rv[kLeafBatch];
-    for (uint32_t t0 = 0; t0 < n; t0 += kLeafLdsPairs) {
+    if (whole_small) {
 #pragma unroll
         for (int u = 0; u < kLeafBatch; ++u) {
-            const uint32_t t = t0 + u * kLeafThreads + tid;
+            const uint32_t t = u * kLeafThreads + tid;
             rk[u] = t < n ? gk[t] : 0u;
             rv[u] = t < n ? gv[t] : 0.0f;
         }
 #pragma unroll
         for (int u = 0; u < kLeafBatch; ++u)
-            if (t0 + u * kLeafThreads + tid < n) atomicAdd(&sh.hist[rk[u] >> kPidBits], 1u);
+            if ((uint32_t)(u * kLeafThreads + tid) < n) atomicAdd(&sh.hist[rk[u] >> kPidBits], 1u);
+    } else {
+        // keys only, twice as many loads in flight
+        for (uint32_t t0 = 0; t0 < n; t0 += 2 * kLeafLdsPairs) {
+            uint32_t kq[2 * kLeafBatch];
+#pragma unroll
+            for (int u = 0; u < 2 * kLeafBatch; ++u) {
+                const uint32_t t = t0 + u * kLeafThreads + tid;
+                kq[u] = t < n ? gk[t] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 2 * kLeafBatch; ++u)
+                if (t0 + u * kLeafThreads + tid < n) atomicAdd(&sh.hist[kq[u] >> kPidBits], 1u);
+        }
     }
     __syncthreads();
     block_scan512(sh.hist, sh.bin0, sh.wsum);
@@ -2359,7 +2381,8 @@ __global__ void k_reset_state(DevState *st, FrameState *fs)
 hipError_t launch_reset(const MapDev &md, hipStream_t s)
 {
     const size_t cap = (size_t)md.hmask + 1;
-    hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, s, md.hkeys, cap, kEmptyKey);
+    // free slots: key kEmptyKey (slot and padding all ones, never read)
+    hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, s, (unsigned long long *)md.htab, 2 * cap, kEmptyKey);
     hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, s, md.skeys, cap, kEmptyKey);
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, md.pos_count, cap, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, md.pos_slab, cap, 0u);
