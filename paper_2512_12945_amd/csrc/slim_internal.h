@@ -49,8 +49,13 @@ struct FrameState {
     Line new_pages;   // record pages to create
     Line pair_cursor; // bucket allocation cursor
     Line work_big;    // slab work items of large leaves
-    alignas(128) unsigned long long n_lists;  // leaves done by one workgroup (low half), by one wave (high half)
+    // leaves done by one workgroup (low half) and by one wave (high half): the
+    // larger ones of each list from the front of its array, the smaller ones
+    // from the back, so that the leaf kernel starts the longer work first
+    alignas(128) unsigned long long n_lists;
     unsigned int pad_lists[30];
+    alignas(128) unsigned long long n_lists_tail;
+    unsigned int pad_tail[30];
     Line n_vox;       // voxel descriptors for the wave combine
     Line frame_err;   // nonzero: do not apply this frame
 };

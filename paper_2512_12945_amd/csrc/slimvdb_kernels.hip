@@ -680,8 +680,12 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
         // the other leaves: one workgroup each, or one wave each if small
         const bool small = act && npairs <= (uint32_t)kWaveItemPairs;
         const bool med = act && !big && !small;
-        // six reservations with five atomics in flight together (the two list
-        // counters share one 64-bit word)
+        // the larger workgroup and wave leaves are listed from the front of
+        // their arrays, the smaller ones from the back
+        const bool medf = med && npairs > (uint32_t)kLeafLdsPairs / 2, medb = med && !medf;
+        const bool smallf = small && npairs > (uint32_t)kWaveItemPairs / 4, smallb = small && !smallf;
+        // eight reservations with six atomics in flight together (two list
+        // counters share each 64-bit word)
         const uint32_t want[4] = {(act && slot < 0) ? 1u : 0u, (uint32_t)__popc(need), npairs,
                                   big ? (uint32_t)__popc(tslabs) : 0u};
         uint32_t incl[4], total[4], base[4] = {0u, 0u, 0u, 0u};
@@ -690,25 +694,29 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
             incl[q] = wave_incl_scan(want[q]);
             total[q] = __shfl(incl[q], 63, 64);
         }
-        const uint32_t mincl = wave_incl_scan(med ? 1u : 0u), sincl = wave_incl_scan(small ? 1u : 0u);
+        const uint32_t mincl = wave_incl_scan(medf ? 1u : 0u), sincl = wave_incl_scan(smallf ? 1u : 0u);
+        const uint32_t mincb = wave_incl_scan(medb ? 1u : 0u), sincb = wave_incl_scan(smallb ? 1u : 0u);
         const unsigned long long lt = ((unsigned long long)__shfl(sincl, 63, 64) << 32) | __shfl(mincl, 63, 64);
-        unsigned long long lbase = 0;
+        const unsigned long long ltb = ((unsigned long long)__shfl(sincb, 63, 64) << 32) | __shfl(mincb, 63, 64);
+        unsigned long long lbase = 0, lbaseb = 0;
         if (lane_id() == 63) {
             if (total[0]) base[0] = atomicAdd(&md.fs->new_leaves.v, total[0]);
             if (total[1]) base[1] = atomicAdd(&md.fs->new_pages.v, total[1]);
             if (total[2]) base[2] = atomicAdd(&md.fs->pair_cursor.v, total[2]);
             if (total[3]) base[3] = atomicAdd(&md.fs->work_big.v, total[3]);
             if (lt) lbase = atomicAdd((unsigned long long *)&md.fs->n_lists, lt);
+            if (ltb) lbaseb = atomicAdd((unsigned long long *)&md.fs->n_lists_tail, ltb);
         }
         uint32_t got[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) got[q] = __shfl(base[q], 63, 64) + incl[q] - want[q];
-        const unsigned long long lb = __shfl(lbase, 63, 64);
+        const unsigned long long lb = __shfl(lbase, 63, 64), lbb = __shfl(lbaseb, 63, 64);
         const uint32_t newleaf = got[0], pbase = got[1], bstart = got[2], ibase = got[3];
-        const uint32_t mi = (uint32_t)lb + mincl - (med ? 1u : 0u);
-        const uint32_t si = (uint32_t)(lb >> 32) + sincl - (small ? 1u : 0u);
-        if (med) md.med_list[mi] = j;
-        if (small) md.small_list[si] = j;
+        const uint32_t last = md.hmask;  // the lists hold hmask + 1 entries
+        if (medf) md.med_list[(uint32_t)lb + mincl - 1u] = j;
+        if (smallf) md.small_list[(uint32_t)(lb >> 32) + sincl - 1u] = j;
+        if (medb) md.med_list[last - ((uint32_t)lbb + mincb - 1u)] = j;
+        if (smallb) md.small_list[last - ((uint32_t)(lbb >> 32) + sincb - 1u)] = j;
         if (big) {
             uint32_t r = 0;
             for (int q = 0; q < kLeafPages; ++q)
@@ -1769,7 +1777,14 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
     // units of work, one per block at a time: the slab items of large leaves,
     // then the leaves done by a workgroup, then groups of four small leaves
     // (one per wave; the wave kernels take the small leaves one per workgroup)
-    const uint32_t nmed = (uint32_t)md.fs->n_lists, nsmall = (uint32_t)(md.fs->n_lists >> 32);
+    // each list: its larger leaves from the front of the array, then its
+    // smaller ones from the back
+    const uint32_t medf = (uint32_t)md.fs->n_lists, smallf = (uint32_t)(md.fs->n_lists >> 32);
+    const uint32_t nmed = medf + (uint32_t)md.fs->n_lists_tail;
+    const uint32_t nsmall = smallf + (uint32_t)(md.fs->n_lists_tail >> 32);
+    const uint32_t last = md.hmask;
+    auto med_at = [&](uint32_t m) { return md.med_list[m < medf ? m : last - (m - medf)]; };
+    auto small_at = [&](uint32_t k) { return md.small_list[k < smallf ? k : last - (k - smallf)]; };
     const uint32_t nw = blockDim.x >> 6, w = threadIdx.x >> 6;
     const uint32_t ngroups = WAVE ? nsmall : (nsmall + nw - 1) / nw;
     const uint32_t nunits = nbig + nmed + ngroups;
@@ -1778,12 +1793,12 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
             const int2 it = md.work[u];
             fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, (uint32_t)it.x, it.y, lused, ok);
         } else if (u < nbig + nmed) {
-            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, md.med_list[u - nbig], -1, lused, ok);
+            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, med_at(u - nbig), -1, lused, ok);
         } else if (WAVE) {
-            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, md.small_list[u - nbig - nmed], -1, lused, ok);
+            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, small_at(u - nbig - nmed), -1, lused, ok);
         } else {
             const uint32_t k = (u - nbig - nmed) * nw + w;
-            if (k < nsmall) fuse_wave_item<KMAX, WAVE, ROWS>(fp, md, sh, md.small_list[k], lused, ok);
+            if (k < nsmall) fuse_wave_item<KMAX, WAVE, ROWS>(fp, md, sh, small_at(k), lused, ok);
             __syncthreads();
         }
     }
@@ -1924,6 +1939,7 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
         md.fs->pair_cursor.v = 0;
         md.fs->work_big.v = 0;
         md.fs->n_lists = 0;
+        md.fs->n_lists_tail = 0;
         md.fs->n_vox.v = 0;
         md.fs->frame_err.v = 0;
     }
