@@ -236,7 +236,7 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md, const Launc
                             const PassWalk *pw = nullptr /* the walk of a multi-frame pass */);
 hipError_t launch_reset(const MapDev &md, hipStream_t s);
 hipError_t launch_reset_staging(const MapDev &md, hipStream_t s);
-hipError_t launch_walk(const FrameParams &fp, const MapDev &md, hipStream_t s);
+hipError_t launch_walk(const FrameParams &fp, const MapDev &md, hipStream_t s, const PassWalk *pw = nullptr);
 hipError_t launch_after_walk(const FrameParams &fp, const MapDev &md, const LaunchShape &shape, hipStream_t s);
 hipError_t launch_loss(const FrameParams &fp, const MapDev &md, const LossParams &lp, hipStream_t s);
 hipError_t launch_backward(const FrameParams &fp, const MapDev &md, const LossParams &lp, const float *grad_scale,

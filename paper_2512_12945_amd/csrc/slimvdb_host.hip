@@ -523,59 +523,92 @@ bool pass_kind(const FrameParams &fp)
     return fp.sem_kind == SLIM_IN_LABEL_I32 && fp.K <= 32;
 }
 
-// Frames [t0, t1) in one pass on staging buffer 0: one walk over all their
-// rays (point indices offset per frame, so every observation key stays
-// distinct and frame-ordered), then one plan, bucketing, leaf kernel and
-// commit for the union of the leaves they touch.
-slim_status integrate_pass(slim_map *m, const std::vector<FrameParams> &fps, int t0, int t1, hipStream_t s)
+// The pass of frames [t0, t1): its walk (each frame's rays, point indices
+// offset per frame so that every observation key stays distinct and
+// frame-ordered) and the frame parameters of the rest of its kernels, which
+// run once for the union of the leaves the frames touch.
+void make_pass(const std::vector<FrameParams> &fps, int t0, int t1, FrameParams *base, PassWalk *pw)
 {
-    PassWalk pw;
-    memset(&pw, 0, sizeof(pw));
-    FrameParams base = fps[t0];
+    memset(pw, 0, sizeof(*pw));
+    *base = fps[t0];
     uint32_t off = 0;
     int nb = 0;
     for (int f = 0; f < t1 - t0; ++f) {
         FrameParams fp = fps[t0 + f];
         fp.pid_base = off;
-        pw.fp[f] = fp;
-        pw.blk_start[f] = nb;
+        pw->fp[f] = fp;
+        pw->blk_start[f] = nb;
         nb += (fp.n + kWalkThreads - 1) / kWalkThreads;
-        base.sub_start[f] = off;
-        base.sub_sem[f] = fp.sem;
+        base->sub_start[f] = off;
+        base->sub_sem[f] = fp.sem;
         off += (uint32_t)fp.n;
     }
-    pw.blk_start[t1 - t0] = nb;
-    pw.nframes = t1 - t0;
-    base.sub_start[t1 - t0] = off;
-    base.nsub = t1 - t0;
-    base.pass_first = t0;
-    base.n = (int)off;
-    return integrate_frame(m, base, s, &pw);
+    pw->blk_start[t1 - t0] = nb;
+    pw->nframes = t1 - t0;
+    base->sub_start[t1 - t0] = off;
+    base->nsub = t1 - t0;
+    base->pass_first = t0;
+    base->n = (int)off;
 }
 
 // A sequence in passes of up to m->pass_frames consecutive frames (the last
-// frame alone, so that the per-frame statistics are its own).  A pass the map
-// cannot take (capacity, staging) is not applied, nor is anything after it;
-// after the queue drains, those frames are integrated again one at a time,
-// which reproduces exactly what per-frame calls do.
+// frame alone, so that the per-frame statistics are its own).  Without kernel
+// timing, passes alternate between the two staging buffers and the walk of
+// pass p + 1 runs on the walk stream beside the rest of pass p.  A pass the
+// map cannot take (capacity, staging) is not applied, nor is anything after
+// it; after the queue drains, those frames are integrated again one at a
+// time, which reproduces exactly what per-frame calls do.
 slim_status integrate_passes(slim_map *m, const std::vector<FrameParams> &fps, hipStream_t s)
 {
     const int count = (int)fps.size();
-    auto one = [&](int t) -> slim_status { return integrate_frame(m, fps[t], s); };
-    slim_status r = SLIM_OK;
-    int t = 0;
-    while (!r && t < count - 1) {
+    std::vector<std::pair<int, int>> units;
+    int64_t most = 1;
+    for (int t = 0; t < count;) {
         int t1 = t + 1;
         int64_t tot = fps[t].n;
-        while (t1 < count - 1 && t1 - t < m->pass_frames && fps[t1].sem_kind == fps[t].sem_kind &&
+        while (t < count - 1 && t1 < count - 1 && t1 - t < m->pass_frames && fps[t1].sem_kind == fps[t].sem_kind &&
                tot + fps[t1].n < kMaxPoints) {
             tot += fps[t1].n;
             ++t1;
         }
-        r = t1 - t == 1 ? one(t) : integrate_pass(m, fps, t, t1, s);
+        units.emplace_back(t, t1);
+        most = std::max<int64_t>(most, tot);
         t = t1;
     }
-    if (!r) r = one(count - 1);
+    slim_status r = SLIM_OK;
+    FrameParams base;
+    PassWalk pw;
+    if (m->prof) {
+        for (const auto &u : units) {
+            if (u.second - u.first == 1) {
+                r = integrate_frame(m, fps[u.first], s);
+            } else {
+                make_pass(fps, u.first, u.second, &base, &pw);
+                r = integrate_frame(m, base, s, &pw);
+            }
+            if (r) break;
+        }
+    } else {
+        const size_t need = (size_t)most * (size_t)m->maxsteps;
+        if (!(r = ensure_buffer1(m, s)) && !(r = ensure_pairs(m, need, s, 0)) && !(r = ensure_pairs(m, need, s, 1))) {
+            HIP_OK(hipEventRecord(m->ev_in, s));
+            HIP_OK(hipStreamWaitEvent(m->wstream, m->ev_in, 0));
+            for (size_t i = 0; i < units.size(); ++i) {
+                const int b = (int)(i & 1);
+                const MapDev &md = b ? m->md1 : m->md;
+                const bool pass = units[i].second - units[i].first > 1;
+                if (pass) make_pass(fps, units[i].first, units[i].second, &base, &pw);
+                const FrameParams &fp = pass ? base : fps[units[i].first];
+                if (m->used[b]) HIP_OK(hipStreamWaitEvent(m->wstream, m->ev_free[b], 0));
+                HIP_OK(launch_walk(fp, md, m->wstream, pass ? &pw : nullptr));
+                HIP_OK(hipEventRecord(m->ev_walk[b], m->wstream));
+                HIP_OK(hipStreamWaitEvent(s, m->ev_walk[b], 0));
+                HIP_OK(launch_after_walk(fp, md, m->shape, s));
+                HIP_OK(hipEventRecord(m->ev_free[b], s));
+                m->used[b] = true;
+            }
+        }
+    }
     // whatever was queued has run once the stream drains; a pass that was not
     // applied leaves its first frame in pass_failed
     int failed = 0;

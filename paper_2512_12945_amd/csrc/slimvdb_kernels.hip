@@ -2112,8 +2112,13 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const La
     return hipGetLastError();
 }
 
-hipError_t launch_walk(const FrameParams &fp, const MapDev &md, hipStream_t s)
+hipError_t launch_walk(const FrameParams &fp, const MapDev &md, hipStream_t s, const PassWalk *pw)
 {
+    if (pw) {
+        const int nb = pw->blk_start[pw->nframes];
+        hipLaunchKernelGGL(k_ray_walk_emit_pass, dim3(nb > 0 ? nb : 1), dim3(kWalkThreads), 0, s, *pw, md);
+        return hipGetLastError();
+    }
     const int bw = (fp.n + kWalkThreads - 1) / kWalkThreads;
     hipLaunchKernelGGL(k_ray_walk_emit, dim3(bw > 0 ? bw : 1), dim3(kWalkThreads), 0, s, fp, md);
     return hipGetLastError();
