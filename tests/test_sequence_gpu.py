@@ -164,3 +164,21 @@ def test_sequence_capacity_fallback(sweeps):
     sv.integrate_sequence(seq, sweeps[:3])
     assert ref.stats() == seq.stats()
     _same(extract_np(ref), extract_np(seq))
+
+
+def test_sequence_passes_with_kernel_timing(sweeps):
+    # with kernel timing on, passes run on one staging buffer with events around
+    # each kernel: one launch set per pass or single frame, same map
+    ref, seq = _map(), _map()
+    for f in sweeps:
+        ref.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+    seq.profile(True)
+    seq.profile_read()
+    sv.integrate_sequence(seq, sweeps)
+    kern = seq.profile_read()
+    seq.profile(False)
+    assert ref.stats() == seq.stats()
+    _same(extract_np(ref), extract_np(seq))
+    # 9 frames in passes of 2 with the last alone: 4 passes + 1 single frame
+    assert all(n == 5 for _, n in kern.values()), kern
+    assert all(ms > 0 for ms, _ in kern.values()), kern
