@@ -1808,7 +1808,7 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
 }
 
 template <int KMAX, bool WAVE, bool ROWS>
-__global__ __launch_bounds__(kLeafThreads, WAVE ? 1 : 4) void k_leaf_fuse(FrameParams fp, MapDev md)
+__global__ __launch_bounds__(kLeafThreads, WAVE ? 1 : 3) void k_leaf_fuse(FrameParams fp, MapDev md)
 {
     __shared__ LeafShared sh;
     leaf_fuse_range<KMAX, WAVE, ROWS>(fp, md, sh, blockIdx.x, gridDim.x);
