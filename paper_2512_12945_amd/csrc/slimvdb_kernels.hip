@@ -49,11 +49,6 @@ __device__ __forceinline__ uint32_t leaf_hash(unsigned long long k, uint32_t mas
     return (uint32_t)k & mask;
 }
 
-__device__ __forceinline__ unsigned long long load_key(const unsigned long long *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Slot of a leaf in the map's table, or -1.
 __device__ int32_t map_find(const MapDev &md, unsigned long long key)
 {
@@ -82,29 +77,6 @@ __device__ void map_insert(const MapDev &md, unsigned long long key, int32_t slo
     }
 }
 
-// Staging-table position of a leaf touched by this frame, inserting it on
-// first sight (*fresh = true for the inserting caller).  kNoPos if the table
-// is full.
-__device__ uint32_t stage_leaf(const MapDev &md, unsigned long long key, bool *fresh)
-{
-    *fresh = false;
-    uint32_t h = leaf_hash(key, md.hmask);
-    for (uint32_t probe = 0; probe <= md.hmask; ++probe) {
-        unsigned long long cur = load_key(&md.skeys[h]);
-        if (cur == key) return h;
-        if (cur == kEmptyKey) {
-            unsigned long long prev = atomicCAS(&md.skeys[h], kEmptyKey, key);
-            if (prev == kEmptyKey) {
-                *fresh = true;
-                return h;
-            }
-            if (prev == key) return h;
-        }
-        h = (h + 1) & md.hmask;
-    }
-    return kNoPos;
-}
-
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
@@ -116,38 +88,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
         if (lane >= d) v += t;
     }
     return v;
-}
-
-// Wave-aggregated atomicAdd (one atomic per wave): every lane of the wave must
-// call it.  Returns the lane's exclusive offset into the reserved range.
-__device__ __forceinline__ uint32_t wave_reserve(unsigned int *counter, uint32_t v)
-{
-    uint32_t incl = wave_incl_scan(v);
-    uint32_t total = __shfl(incl, 63, 64);
-    uint32_t base = 0;
-    if (lane_id() == 63 && total) base = atomicAdd(counter, total);
-    base = __shfl(base, 63, 64);
-    return base + incl - v;
-}
-
-// Four independent reservations at once (their atomics are in flight together).
-__device__ __forceinline__ void wave_reserve4(unsigned int *c0, unsigned int *c1, unsigned int *c2, unsigned int *c3,
-                                              const uint32_t (&v)[4], uint32_t (&out)[4])
-{
-    uint32_t incl[4], total[4], base[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        incl[q] = wave_incl_scan(v[q]);
-        total[q] = __shfl(incl[q], 63, 64);
-    }
-    if (lane_id() == 63) {
-        if (total[0]) base[0] = atomicAdd(c0, total[0]);
-        if (total[1]) base[1] = atomicAdd(c1, total[1]);
-        if (total[2]) base[2] = atomicAdd(c2, total[2]);
-        if (total[3]) base[3] = atomicAdd(c3, total[3]);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) out[q] = __shfl(base[q], 63, 64) + incl[q] - v[q];
 }
 
 // ---------------------------------------------------------------------------
