@@ -182,3 +182,25 @@ def test_sequence_passes_with_kernel_timing(sweeps):
     # 9 frames in passes of 2 with the last alone: 4 passes + 1 single frame
     assert all(n == 5 for _, n in kern.values()), kern
     assert all(ms > 0 for ms, _ in kern.values()), kern
+
+
+def test_sequence_probability_rows_and_mixed_kinds(sweeps):
+    # probability rows are not taken in passes (overlapped form); a call that
+    # mixes rows and labels is overlapped as a whole; both equal per-frame calls
+    rng = np.random.default_rng(5)
+    frames = []
+    for t, f in enumerate(sweeps[:6]):
+        n = f["points"].shape[0]
+        if t % 2:
+            p = rng.random((n, 20)).astype(np.float32)
+            p /= p.sum(axis=1, keepdims=True)
+            frames.append(dict(points=f["points"], pose=f["pose"], sem=cuda(p), kind=sv.IN_PROB_F32))
+        else:
+            frames.append(f)
+    for subset in (frames[1::2], frames):
+        ref, seq = _map(), _map()
+        for f in subset:
+            ref.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+        sv.integrate_sequence(seq, subset)
+        assert ref.stats() == seq.stats()
+        _same(extract_np(ref), extract_np(seq))
