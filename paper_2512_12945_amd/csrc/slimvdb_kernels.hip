@@ -1819,6 +1819,24 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
 {
     __shared__ unsigned long long s_old[256], s_new[256];
     DevState *st = md.st;
+    // the frame's counters and the map's state are read together with the
+    // per-block statistics (one round trip for all of them)
+    unsigned long long nl = 0, np = 0, lu = 0, pu = 0, vu = 0;
+    uint32_t ferr = 0, nrej = 0, npairs = 0, ntouch = 0;
+    int failed = 0, status = 0;
+    if (threadIdx.x == 0) {
+        nl = md.fs->new_leaves.v;
+        np = md.fs->new_pages.v;
+        ferr = md.fs->frame_err.v;
+        nrej = md.fs->rejected.v;
+        npairs = md.fs->pairs.v;
+        ntouch = md.fs->n_touched.v;
+        failed = st->pass_failed;
+        status = st->status;
+        lu = st->leaves_used;
+        pu = st->pages_used;
+        vu = st->voxels_used;
+    }
     unsigned long long uo = 0, un = 0;
     for (int b0 = threadIdx.x; b0 < md.leaf_blocks; b0 += 8 * blockDim.x) {
         uint2 v[8];
@@ -1844,28 +1862,26 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const unsigned long long nl = md.fs->new_leaves.v, np = md.fs->new_pages.v;
         // after a multi-frame pass that could not be applied, the frames that
         // follow it in the same sequence call are skipped too: the host
         // integrates them again one by one
-        const bool skipped = st->pass_failed != 0;
-        const bool ok = !skipped && md.fs->frame_err.v == 0 &&
-                        st->leaves_used + nl <= (unsigned long long)md.max_leaves &&
-                        st->pages_used + np <= (unsigned long long)md.max_pages;
+        const bool skipped = failed != 0;
+        const bool ok = !skipped && ferr == 0 && lu + nl <= (unsigned long long)md.max_leaves &&
+                        pu + np <= (unsigned long long)md.max_pages;
         if (ok) {
-            st->leaves_used += nl;
-            st->pages_used += np;
-            st->voxels_used += s_new[0];
+            st->leaves_used = lu + nl;
+            st->pages_used = pu + np;
+            st->voxels_used = vu + s_new[0];
         } else if (!skipped && fp.nsub > 1) {
             st->pass_failed = 1 + fp.pass_first;
-        } else if (!skipped && st->status == SLIM_OK) {
+        } else if (!skipped && status == SLIM_OK) {
             st->status = SLIM_ERR_CAPACITY;
         }
         if (!skipped && (ok || fp.nsub <= 1)) {
             st->last_points = fp.n;
-            st->last_rejected = md.fs->rejected.v;
-            st->last_pairs = md.fs->pairs.v;
-            st->last_touched = md.fs->n_touched.v;
+            st->last_rejected = nrej;
+            st->last_pairs = npairs;
+            st->last_touched = ntouch;
             st->last_new_leaves = nl;
             st->last_u_old = (long long)s_old[0];
             st->last_u_new = (long long)s_new[0];
