@@ -174,8 +174,9 @@ struct MapDev {
     int rec_stride;
     // per-frame pair buffers
     uint2 *pair_pr;       // (staging position of the pair's leaf, rank of the pair inside its leaf's bucket)
-    uint32_t *pair_key;   // (offset << 23) | point index
-    float *pair_tsdf;     // truncated signed distance (FP32)
+    uint2 *pair_kt;       // the walk's pairs: ((offset << 23) | point index, truncated distance bits)
+    uint32_t *pair_key;   // leaf-kernel scratch: sorted keys of bins beyond LDS, wave-combine input
+    float *pair_tsdf;     // and their truncated distances
     uint32_t *srt_key;    // pairs grouped by leaf
     float *srt_tsdf;
     int32_t *srt_lab;     // int32 label of each bucketed pair (closed set with labels)

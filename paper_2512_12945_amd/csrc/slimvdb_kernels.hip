@@ -513,8 +513,8 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
         const uint32_t voff = (uint32_t)(((kx & 7) << 6) | ((ky & 7) << 3) | (kz & 7));
         if (fits || o + j < md.pair_cap) {
             md.pair_pr[o + j] = make_uint2(pos, rank++);
-            md.pair_key[o + j] = (voff << kPidBits) | (fp.pid_base + (uint32_t)i);
-            md.pair_tsdf[o + j] = fminf(s, fp.tau);
+            md.pair_kt[o + j] =
+                make_uint2((voff << kPidBits) | (fp.pid_base + (uint32_t)i), __float_as_uint(fminf(s, fp.tau)));
         }
         j++;
     }
@@ -711,9 +711,10 @@ __device__ __forceinline__ void pair_bucket_range(const FrameParams &fp, const M
         const uint32_t pos = pr.x;
         if (pos == kNoPos) continue;
         const uint32_t dst = (uint32_t)md.pos_plan[pos].z + pr.y;
-        const uint32_t key = md.pair_key[i];
+        const uint2 kt = md.pair_kt[i];
+        const uint32_t key = kt.x;
         md.srt_key[dst] = key;
-        md.srt_tsdf[dst] = md.pair_tsdf[i];
+        md.srt_tsdf[dst] = __uint_as_float(kt.y);
         // the leaf kernel's small items find the label beside the pair
         if (labels) md.srt_lab[dst] = point_label(fp, key & kPidMask);
     }
