@@ -173,8 +173,8 @@ struct MapDev {
     float *vox;
     int rec_stride;
     // per-frame pair buffers
-    uint2 *pair_pr;       // (staging position of the pair's leaf, rank of the pair inside its leaf's bucket)
-    uint2 *pair_kt;       // the walk's pairs: ((offset << 23) | point index, truncated distance bits)
+    uint4 *pairs;         // the walk's pairs: (staging position of the pair's leaf, rank of the pair
+                          // inside its leaf's bucket, (offset << 23) | point index, truncated distance bits)
     uint32_t *pair_key;   // leaf-kernel scratch: sorted keys of bins beyond LDS, wave-combine input
     float *pair_tsdf;     // and their truncated distances
     uint32_t *srt_key;    // pairs grouped by leaf

@@ -512,9 +512,8 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
         }
         const uint32_t voff = (uint32_t)(((kx & 7) << 6) | ((ky & 7) << 3) | (kz & 7));
         if (fits || o + j < md.pair_cap) {
-            md.pair_pr[o + j] = make_uint2(pos, rank++);
-            md.pair_kt[o + j] =
-                make_uint2((voff << kPidBits) | (fp.pid_base + (uint32_t)i), __float_as_uint(fminf(s, fp.tau)));
+            md.pairs[o + j] = make_uint4(pos, rank++, (voff << kPidBits) | (fp.pid_base + (uint32_t)i),
+                                         __float_as_uint(fminf(s, fp.tau)));
         }
         j++;
     }
@@ -707,16 +706,13 @@ __device__ __forceinline__ void pair_bucket_range(const FrameParams &fp, const M
     const uint32_t stride = nblk * blockDim.x;
     const bool labels = fp.K > 0 && fp.sem_kind == SLIM_IN_LABEL_I32;
     for (uint32_t i = blk * blockDim.x + threadIdx.x; i < P; i += stride) {
-        const uint2 pr = md.pair_pr[i];
-        const uint32_t pos = pr.x;
-        if (pos == kNoPos) continue;
-        const uint32_t dst = (uint32_t)md.pos_plan[pos].z + pr.y;
-        const uint2 kt = md.pair_kt[i];
-        const uint32_t key = kt.x;
-        md.srt_key[dst] = key;
-        md.srt_tsdf[dst] = __uint_as_float(kt.y);
+        const uint4 pq = md.pairs[i];  // (staging position, rank, key, distance bits)
+        if (pq.x == kNoPos) continue;
+        const uint32_t dst = (uint32_t)md.pos_plan[pq.x].z + pq.y;
+        md.srt_key[dst] = pq.z;
+        md.srt_tsdf[dst] = __uint_as_float(pq.w);
         // the leaf kernel's small items find the label beside the pair
-        if (labels) md.srt_lab[dst] = point_label(fp, key & kPidMask);
+        if (labels) md.srt_lab[dst] = point_label(fp, pq.z & kPidMask);
     }
 }
 
