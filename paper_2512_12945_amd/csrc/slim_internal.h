@@ -177,8 +177,7 @@ struct MapDev {
                           // inside its leaf's bucket, (offset << 23) | point index, truncated distance bits)
     uint32_t *pair_key;   // leaf-kernel scratch: sorted keys of bins beyond LDS, wave-combine input
     float *pair_tsdf;     // and their truncated distances
-    uint32_t *srt_key;    // pairs grouped by leaf
-    float *srt_tsdf;
+    uint2 *srt_kv;        // pairs grouped by leaf: (key, truncated distance bits)
     int32_t *srt_lab;     // int32 label of each bucketed pair (closed set with labels)
     uint32_t *tmp_key;    // scratch of large leaves: pairs binned by voxel offset
     float *tmp_tsdf;

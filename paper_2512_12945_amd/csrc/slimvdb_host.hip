@@ -197,16 +197,17 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s, int buf = 0)
     size_t cap = std::max<size_t>(need, pcap + pcap / 2);
     cap = std::min<size_t>(cap, 0xFFFFFFF0ull);
     MapDev &md = buf ? m->md1 : m->md;
-    void *ptrs[10] = {md.pairs, md.pair_key, md.pair_tsdf, md.srt_key, md.srt_tsdf,
-                      md.srt_lab, md.tmp_key,  md.tmp_tsdf, md.work,     md.vox_list};
+    void *ptrs[9] = {md.pairs,   md.pair_key, md.pair_tsdf, md.srt_kv,  md.srt_lab,
+                     md.tmp_key, md.tmp_tsdf, md.work,      md.vox_list};
     for (void *p : ptrs) {
         if (!p) continue;
         (void)hipFree(p);
         m->allocs.erase(std::remove(m->allocs.begin(), m->allocs.end(), p), m->allocs.end());
     }
     md.pairs = nullptr;
-    md.pair_key = md.srt_key = md.tmp_key = nullptr;
-    md.pair_tsdf = md.srt_tsdf = md.tmp_tsdf = nullptr;
+    md.pair_key = md.tmp_key = nullptr;
+    md.pair_tsdf = md.tmp_tsdf = nullptr;
+    md.srt_kv = nullptr;
     md.srt_lab = nullptr;
     md.work = nullptr;
     md.vox_list = nullptr;
@@ -215,7 +216,7 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s, int buf = 0)
     slim_status r;
     if ((r = dalloc(m, &md.pairs, cap)) ||
         (r = dalloc(m, &md.pair_key, cap)) || (r = dalloc(m, &md.pair_tsdf, cap)) ||
-        (r = dalloc(m, &md.srt_key, cap)) || (r = dalloc(m, &md.srt_tsdf, cap)) ||
+        (r = dalloc(m, &md.srt_kv, cap)) ||
         (r = dalloc(m, &md.srt_lab, cap)) || (r = dalloc(m, &md.tmp_key, cap)) ||
         (r = dalloc(m, &md.tmp_tsdf, cap)) ||
         (r = dalloc(m, &md.work, wcap)) || (r = dalloc(m, &md.vox_list, cap))) {
@@ -458,8 +459,9 @@ slim_status ensure_buffer1(slim_map *m, hipStream_t s)
     md.med_list = md.small_list = nullptr;
     md.fs = nullptr;
     md.pairs = nullptr;
-    md.pair_key = md.srt_key = md.tmp_key = nullptr;
-    md.pair_tsdf = md.srt_tsdf = md.tmp_tsdf = nullptr;
+    md.pair_key = md.tmp_key = nullptr;
+    md.pair_tsdf = md.tmp_tsdf = nullptr;
+    md.srt_kv = nullptr;
     md.srt_lab = nullptr;
     md.work = nullptr;
     md.vox_list = nullptr;

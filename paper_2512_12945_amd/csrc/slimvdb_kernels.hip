@@ -709,8 +709,7 @@ __device__ __forceinline__ void pair_bucket_range(const FrameParams &fp, const M
         const uint4 pq = md.pairs[i];  // (staging position, rank, key, distance bits)
         if (pq.x == kNoPos) continue;
         const uint32_t dst = (uint32_t)md.pos_plan[pq.x].z + pq.y;
-        md.srt_key[dst] = pq.z;
-        md.srt_tsdf[dst] = __uint_as_float(pq.w);
+        md.srt_kv[dst] = make_uint2(pq.z, pq.w);
         // the leaf kernel's small items find the label beside the pair
         if (labels) md.srt_lab[dst] = point_label(fp, pq.z & kPidMask);
     }
@@ -1333,8 +1332,7 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
     if (tid < kMaskWords) sh.occ0[tid] = sh.item[16 + tid];
     if (tid < kLeafPages) sh.pages[tid] = (int)sh.item[8 + tid];
 
-    const uint32_t *gk = md.srt_key + bstart;
-    const float *gv = md.srt_tsdf + bstart;
+    const uint2 *gkv = md.srt_kv + bstart;
     uint32_t *tk = md.tmp_key + bstart;
     float *tv = md.tmp_tsdf + bstart;
     const bool whole_small = slab < 0 && n <= (uint32_t)kLeafLdsPairs;
@@ -1347,8 +1345,9 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
 #pragma unroll
         for (int u = 0; u < kLeafBatch; ++u) {
             const uint32_t t = u * kLeafThreads + tid;
-            rk[u] = t < n ? gk[t] : 0u;
-            rv[u] = t < n ? gv[t] : 0.0f;
+            const uint2 e = t < n ? gkv[t] : make_uint2(0u, 0u);
+            rk[u] = e.x;
+            rv[u] = __uint_as_float(e.y);
         }
 #pragma unroll
         for (int u = 0; u < kLeafBatch; ++u)
@@ -1360,7 +1359,7 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
 #pragma unroll
             for (int u = 0; u < 2 * kLeafBatch; ++u) {
                 const uint32_t t = t0 + u * kLeafThreads + tid;
-                kq[u] = t < n ? gk[t] : 0u;
+                kq[u] = t < n ? gkv[t].x : 0u;
             }
 #pragma unroll
             for (int u = 0; u < 2 * kLeafBatch; ++u)
@@ -1410,8 +1409,9 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
 #pragma unroll
             for (int u = 0; u < kLeafBatch; ++u) {
                 const uint32_t t = t0 + u * kLeafThreads + tid;
-                rk[u] = t < n ? gk[t] : 0u;
-                rv[u] = t < n ? gv[t] : 0.0f;
+                const uint2 e = t < n ? gkv[t] : make_uint2(0u, 0u);
+                rk[u] = e.x;
+                rv[u] = __uint_as_float(e.y);
             }
 #pragma unroll
             for (int u = 0; u < kLeafBatch; ++u) {
@@ -1604,8 +1604,9 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
     for (int q = 0; q < 4; ++q) {
         const uint32_t i = lane + 64 * q;
         const bool has = i < n;
-        kq[q] = has ? md.srt_key[bstart + i] : 0xFFFFFFFFu;
-        vq[q] = has ? md.srt_tsdf[bstart + i] : 0.0f;
+        const uint2 e = has ? md.srt_kv[bstart + i] : make_uint2(0xFFFFFFFFu, 0u);
+        kq[q] = e.x;
+        vq[q] = __uint_as_float(e.y);
         lq[q] = (has && labels) ? md.srt_lab[bstart + i] : 0;
         if (i < ((n + 3u) & ~3u)) uk[i] = kq[q];
     }
