@@ -204,3 +204,22 @@ def test_sequence_probability_rows_and_mixed_kinds(sweeps):
         sv.integrate_sequence(seq, subset)
         assert ref.stats() == seq.stats()
         _same(extract_np(ref), extract_np(seq))
+
+
+def test_sequence_passes_of_ray_frames(sweeps):
+    # frames given as ranges and unit directions go through passes too
+    frames = []
+    for f in sweeps[:5]:
+        p = f["np_points"].astype(np.float64)
+        r = np.linalg.norm(p, axis=1)
+        keep = r > 0
+        d = np.zeros_like(p)
+        d[keep] = p[keep] / r[keep, None]
+        frames.append(dict(ranges=cuda(r.astype(np.float32)), dirs=cuda(d.astype(np.float32)), pose=f["pose"],
+                           sem=f["sem"], kind=sv.IN_LABEL_I32))
+    ref, seq = _map(), _map()
+    for f in frames:
+        ref.integrate_rays(f["ranges"], f["dirs"], f["pose"], f["sem"], f["kind"])
+    sv.integrate_sequence(seq, frames)
+    assert ref.stats() == seq.stats()
+    _same(extract_np(ref), extract_np(seq))
