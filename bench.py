@@ -360,7 +360,8 @@ def main():
                                "20 classes as int32 labels, 10% flicker; map grows over the sweeps",
                    "points_per_step": n_pts, "voxel_size": vs, "sdf_trunc": tau, "num_classes": ncls,
                    "first_timed_sweep": W,
-                   "api": "slim_integrate_sequence, all timed sweeps in one call" if use_seq
+                   "api": "slim_integrate_sequence, all timed sweeps in one call (two-sweep passes, the default)"
+                   if use_seq
                    else "slim_integrate, one call per sweep"},
         "ms_per_step_single_calls": run["elapsed"] / K * 1e3,
         "ms_per_step_sequence": run["elapsed_sequence"] / K * 1e3,
