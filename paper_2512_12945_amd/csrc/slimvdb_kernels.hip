@@ -736,6 +736,7 @@ struct LeafShared {
     uint32_t touch[kMaskWords], occ0[kMaskWords], wsum[4];
     int pages[kLeafPages];
     uint32_t chunk_end, uold, unew;
+    uint32_t stash_n;         // pairs of an x-slab item's own offsets (kept in a_key/a_val while they fit)
     uint32_t item[32];        // the current block item
 };
 
@@ -1315,8 +1316,10 @@ __device__ __forceinline__ void rank_bins(LeafShared &sh, KP bk, VP bv, uint32_t
 // of it (slab < 0) or, for a leaf with more pairs than LDS holds, the voxels
 // of one x-slab (offsets 64 slab .. 64 slab + 63), so that the slabs of a
 // large leaf run in different workgroups.  Reads every pair of the leaf for
-// the offset histogram, keeps those of its offsets, orders them by point index
-// inside each voxel and combines the voxels.
+// the offset histogram (which fixes the bucket position of every voxel),
+// keeps those of its offsets, orders them by point index inside each voxel and
+// combines the voxels.  An x-slab item reads the leaf once when its own pairs
+// fit LDS and a second time otherwise.
 template <int KMAX, bool WAVE, bool ROWS>
 __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &md, LeafShared &sh, uint32_t j,
                                           int slab, unsigned long long lused, bool ok)
@@ -1324,6 +1327,7 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
     const int tid = threadIdx.x;
     if (tid < 32) sh.item[tid] = ((const uint32_t *)&md.items[j])[tid];
     for (int o = tid; o < kLeafVoxels; o += blockDim.x) sh.hist[o] = 0;
+    if (tid == 0) sh.stash_n = 0;
     __syncthreads();
     const uint32_t pos = sh.item[0], n = sh.item[1], bstart = sh.item[2];
     const int islot = (int)sh.item[3];
@@ -1353,17 +1357,41 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
         for (int u = 0; u < kLeafBatch; ++u)
             if ((uint32_t)(u * kLeafThreads + tid) < n) atomicAdd(&sh.hist[rk[u] >> kPidBits], 1u);
     } else {
-        // keys only, twice as many loads in flight
-        for (uint32_t t0 = 0; t0 < n; t0 += 2 * kLeafLdsPairs) {
-            uint32_t kq[2 * kLeafBatch];
+        // every pair into the histogram; the pairs of the item's own offsets
+        // into a_key/a_val in arrival order, as long as they fit (one slot
+        // reservation per wave and batch)
+        for (uint32_t t0 = 0; t0 < n; t0 += kLeafLdsPairs) {
 #pragma unroll
-            for (int u = 0; u < 2 * kLeafBatch; ++u) {
+            for (int u = 0; u < kLeafBatch; ++u) {
                 const uint32_t t = t0 + u * kLeafThreads + tid;
-                kq[u] = t < n ? gkv[t].x : 0u;
+                const uint2 e = t < n ? gkv[t] : make_uint2(0u, 0u);
+                rk[u] = e.x;
+                rv[u] = __uint_as_float(e.y);
             }
+            uint32_t mine = 0;
 #pragma unroll
-            for (int u = 0; u < 2 * kLeafBatch; ++u)
-                if (t0 + u * kLeafThreads + tid < n) atomicAdd(&sh.hist[kq[u] >> kPidBits], 1u);
+            for (int u = 0; u < kLeafBatch; ++u) {
+                const uint32_t o = rk[u] >> kPidBits;
+                if (t0 + u * kLeafThreads + tid < n) {
+                    atomicAdd(&sh.hist[o], 1u);
+                    mine += (o >= ob && o < oe) ? 1u : 0u;
+                }
+            }
+            const uint32_t incl = wave_incl_scan(mine);
+            uint32_t wbase = 0;
+            if (lane_id() == 63 && incl) wbase = atomicAdd(&sh.stash_n, incl);
+            uint32_t q = __shfl(wbase, 63, 64) + incl - mine;
+#pragma unroll
+            for (int u = 0; u < kLeafBatch; ++u) {
+                const uint32_t o = rk[u] >> kPidBits;
+                if (t0 + u * kLeafThreads + tid < n && o >= ob && o < oe) {
+                    if (q < (uint32_t)kLeafLdsPairs) {
+                        sh.a_key[q] = rk[u];
+                        sh.a_val[q] = rv[u];
+                    }
+                    q++;
+                }
+            }
         }
     }
     __syncthreads();
@@ -1395,7 +1423,9 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
     }
 
     // bin by offset (order inside a bin arbitrary): in LDS if the item fits,
-    // else in the scratch buffer
+    // else in the scratch buffer.  An x-slab item that fits bins from the
+    // pairs it kept (exactly those of its offsets: their count is the width
+    // of its range of the histogram)
     if (whole_small) {
 #pragma unroll
         for (int u = 0; u < kLeafBatch; ++u)
@@ -1404,6 +1434,14 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
                 sh.b_key[p] = rk[u];
                 sh.b_val[p] = rv[u];
             }
+    } else if (small) {
+        const uint32_t m = hi_all - lo_all;
+        for (uint32_t t = tid; t < m; t += blockDim.x) {
+            const uint32_t k = sh.a_key[t];
+            const uint32_t p = atomicAdd(&sh.cur[k >> kPidBits], 1u);
+            sh.b_key[p - lo_all] = k;
+            sh.b_val[p - lo_all] = sh.a_val[t];
+        }
     } else {
         for (uint32_t t0 = 0; t0 < n; t0 += kLeafLdsPairs) {
 #pragma unroll
@@ -1418,13 +1456,8 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
                 const uint32_t o = rk[u] >> kPidBits;
                 if (t0 + u * kLeafThreads + tid < n && o >= ob && o < oe) {
                     const uint32_t p = atomicAdd(&sh.cur[o], 1u);
-                    if (small) {
-                        sh.b_key[p - lo_all] = rk[u];
-                        sh.b_val[p - lo_all] = rv[u];
-                    } else {
-                        tk[p] = rk[u];
-                        tv[p] = rv[u];
-                    }
+                    tk[p] = rk[u];
+                    tv[p] = rv[u];
                 }
             }
         }
