@@ -161,9 +161,14 @@ struct MapDev {
     uint32_t *pos_slab;  // x-slabs of the leaf the frame touches (8 bits)
     int4 *pos_plan;      // (slot or -1, new-leaf index, bucket start, 0)
     int4 *pos_pages;     // 2 per position: record page of each of the 8 slabs (-1: none)
-    LeafItem *items;     // per touched index: the leaf kernel's view of the leaf
-    uint32_t *med_list;  // touched indices of leaves done by one workgroup
-    uint32_t *small_list;  // touched indices of leaves done by one wave
+    // the leaf kernel's view of each touched leaf, written by the plan kernel
+    // where the leaf kernel's unit finds it without another lookup: leaves done
+    // by one workgroup and by one wave in the order of their work lists (the
+    // larger ones from the front of the array, the smaller ones from the back),
+    // large leaves at the index of their first slab work item
+    LeafItem *items;       // leaves done by one workgroup (cap entries)
+    LeafItem *items_small; // leaves done by one wave (cap entries)
+    LeafItem *items_big;   // large leaves (work_cap entries)
     // leaves
     unsigned long long *leaf_key; // packed key per slot
     int32_t *leaf_page;           // 8 record pages per slot (-1: none)
@@ -182,7 +187,7 @@ struct MapDev {
     uint32_t *tmp_key;    // scratch of large leaves: pairs binned by voxel offset
     float *tmp_tsdf;
     uint32_t pair_cap;
-    int2 *work;           // slab work items (touched index, slab) of large leaves
+    int2 *work;           // slab work items (index in items_big, slab) of large leaves
     uint32_t work_cap;
     uint4 *vox_list;      // wave-combine voxels: (record, pairs | existed << 31, first sorted pair, 0)
     uint2 *blk_stats;     // per leaf-kernel block: (voxels updated that existed, voxels created)

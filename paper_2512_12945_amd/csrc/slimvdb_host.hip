@@ -197,8 +197,8 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s, int buf = 0)
     size_t cap = std::max<size_t>(need, pcap + pcap / 2);
     cap = std::min<size_t>(cap, 0xFFFFFFF0ull);
     MapDev &md = buf ? m->md1 : m->md;
-    void *ptrs[9] = {md.pairs,   md.pair_key, md.pair_tsdf, md.srt_kv,  md.srt_lab,
-                     md.tmp_key, md.tmp_tsdf, md.work,      md.vox_list};
+    void *ptrs[10] = {md.pairs,   md.pair_key, md.pair_tsdf, md.srt_kv,  md.srt_lab,
+                      md.tmp_key, md.tmp_tsdf, md.work,      md.vox_list, md.items_big};
     for (void *p : ptrs) {
         if (!p) continue;
         (void)hipFree(p);
@@ -211,6 +211,7 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s, int buf = 0)
     md.srt_lab = nullptr;
     md.work = nullptr;
     md.vox_list = nullptr;
+    md.items_big = nullptr;
     // a large leaf has more than kLeafLdsPairs pairs and at most 8 slab items
     const size_t wcap = cap / (kLeafLdsPairs / kLeafPages) + kLeafPages;
     slim_status r;
@@ -219,7 +220,8 @@ slim_status ensure_pairs(slim_map *m, size_t need, hipStream_t s, int buf = 0)
         (r = dalloc(m, &md.srt_kv, cap)) ||
         (r = dalloc(m, &md.srt_lab, cap)) || (r = dalloc(m, &md.tmp_key, cap)) ||
         (r = dalloc(m, &md.tmp_tsdf, cap)) ||
-        (r = dalloc(m, &md.work, wcap)) || (r = dalloc(m, &md.vox_list, cap))) {
+        (r = dalloc(m, &md.work, wcap)) || (r = dalloc(m, &md.vox_list, cap)) ||
+        (r = dalloc(m, &md.items_big, wcap))) {
         pcap = 0;
         md.pair_cap = 0;
         md.work_cap = 0;
@@ -301,8 +303,7 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
         (r = dalloc(m, &md.pos_count, cap)) ||
         (r = dalloc(m, &md.pos_slab, cap)) || (r = dalloc(m, &md.pos_plan, cap)) ||
         (r = dalloc(m, &md.pos_pages, 2 * cap)) || (r = dalloc(m, &md.items, cap)) ||
-        (r = dalloc(m, &md.med_list, cap)) || (r = dalloc(m, &md.small_list, cap)) ||
-        (r = dalloc(m, &md.leaf_key, L)) ||
+        (r = dalloc(m, &md.items_small, cap)) || (r = dalloc(m, &md.leaf_key, L)) ||
         (r = dalloc(m, &md.leaf_page, L * kLeafPages)) || (r = dalloc(m, &md.leaf_occ, L * kMaskWords)) ||
         (r = dalloc(m, &md.vox, NP * kPageVoxels * (size_t)md.rec_stride)) ||
         (r = dalloc(m, &md.blk_stats, (size_t)m->cus * kMaxLeafBlocksPerCu)) || (r = dalloc(m, &md.st, 1)) ||
@@ -455,8 +456,7 @@ slim_status ensure_buffer1(slim_map *m, hipStream_t s)
     md.touched = md.pos_count = md.pos_slab = nullptr;
     md.touched_key = nullptr;
     md.pos_plan = md.pos_pages = nullptr;
-    md.items = nullptr;
-    md.med_list = md.small_list = nullptr;
+    md.items = md.items_small = nullptr;
     md.fs = nullptr;
     md.pairs = nullptr;
     md.pair_key = md.tmp_key = nullptr;
@@ -465,6 +465,7 @@ slim_status ensure_buffer1(slim_map *m, hipStream_t s)
     md.srt_lab = nullptr;
     md.work = nullptr;
     md.vox_list = nullptr;
+    md.items_big = nullptr;
     md.pair_cap = 0;
     md.work_cap = 0;
     const size_t cap = m->hcap;
@@ -473,7 +474,7 @@ slim_status ensure_buffer1(slim_map *m, hipStream_t s)
         (r = dalloc(m, &md.touched_key, cap)) || (r = dalloc(m, &md.pos_count, cap)) ||
         (r = dalloc(m, &md.pos_slab, cap)) || (r = dalloc(m, &md.pos_plan, cap)) ||
         (r = dalloc(m, &md.pos_pages, 2 * cap)) || (r = dalloc(m, &md.items, cap)) ||
-        (r = dalloc(m, &md.med_list, cap)) || (r = dalloc(m, &md.small_list, cap)) || (r = dalloc(m, &md.fs, 1)))
+        (r = dalloc(m, &md.items_small, cap)) || (r = dalloc(m, &md.fs, 1)))
         return r;
     HIP_OK(hipStreamCreateWithFlags(&m->wstream, hipStreamNonBlocking));
     for (hipEvent_t *e : {&m->ev_in, &m->ev_free[0], &m->ev_free[1], &m->ev_walk[0], &m->ev_walk[1]})

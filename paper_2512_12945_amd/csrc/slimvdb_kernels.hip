@@ -651,16 +651,22 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
         for (int q = 0; q < 4; ++q) got[q] = __shfl(base[q], 63, 64) + incl[q] - want[q];
         const unsigned long long lb = __shfl(lbase, 63, 64), lbb = __shfl(lbaseb, 63, 64);
         const uint32_t newleaf = got[0], pbase = got[1], bstart = got[2], ibase = got[3];
-        const uint32_t last = md.hmask;  // the lists hold hmask + 1 entries
-        if (medf) md.med_list[(uint32_t)lb + mincl - 1u] = j;
-        if (smallf) md.small_list[(uint32_t)(lb >> 32) + sincl - 1u] = j;
-        if (medb) md.med_list[last - ((uint32_t)lbb + mincb - 1u)] = j;
-        if (smallb) md.small_list[last - ((uint32_t)(lbb >> 32) + sincb - 1u)] = j;
+        const uint32_t last = md.hmask;  // the item arrays of the lists hold hmask + 1 entries
+        LeafItem *dst = nullptr;
+        if (medf) dst = &md.items[(uint32_t)lb + mincl - 1u];
+        if (smallf) dst = &md.items_small[(uint32_t)(lb >> 32) + sincl - 1u];
+        if (medb) dst = &md.items[last - ((uint32_t)lbb + mincb - 1u)];
+        if (smallb) dst = &md.items_small[last - ((uint32_t)(lbb >> 32) + sincb - 1u)];
         if (big) {
+            // the leaf's slab items sit at ibase .. ibase + slabs - 1, its item at
+            // ibase; every work entry below work_cap is written, so the leaf
+            // kernel never reads an unwritten one (a frame that overflows the
+            // work list is not applied)
+            if (ibase < md.work_cap) dst = &md.items_big[ibase];
             uint32_t r = 0;
             for (int q = 0; q < kLeafPages; ++q)
                 if ((tslabs >> q) & 1u) {
-                    if (ibase + r < md.work_cap) md.work[ibase + r] = make_int2((int)j, q);
+                    if (ibase + r < md.work_cap) md.work[ibase + r] = make_int2((int)ibase, q);
                     else atomicOr(&md.fs->frame_err.v, 1u);
                     r++;
                 }
@@ -673,8 +679,10 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
             md.pos_pages[2 * pos] = make_int4(pg[0], pg[1], pg[2], pg[3]);
             md.pos_pages[2 * pos + 1] = make_int4(pg[4], pg[5], pg[6], pg[7]);
             md.pos_plan[pos] = make_int4(slot, slot < 0 ? (int)newleaf : -1, (int)bstart, 0);
+        }
+        if (dst) {
             // the leaf kernel's item: header, pages, occupancy before this frame
-            uint4 *it = (uint4 *)&md.items[j];
+            uint4 *it = (uint4 *)dst;
             it[0] = make_uint4(pos, npairs, bstart, (uint32_t)(slot >= 0 ? slot : -1 - (int)newleaf));
             it[1] = make_uint4(tslabs, 0u, (uint32_t)key, (uint32_t)(key >> 32));
             it[2] = make_uint4((uint32_t)pg[0], (uint32_t)pg[1], (uint32_t)pg[2], (uint32_t)pg[3]);
@@ -1321,11 +1329,11 @@ __device__ __forceinline__ void rank_bins(LeafShared &sh, KP bk, VP bv, uint32_t
 // combines the voxels.  An x-slab item reads the leaf once when its own pairs
 // fit LDS and a second time otherwise.
 template <int KMAX, bool WAVE, bool ROWS>
-__device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &md, LeafShared &sh, uint32_t j,
+__device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &md, LeafShared &sh, LeafItem *itp,
                                           int slab, unsigned long long lused, bool ok)
 {
     const int tid = threadIdx.x;
-    if (tid < 32) sh.item[tid] = ((const uint32_t *)&md.items[j])[tid];
+    if (tid < 32) sh.item[tid] = ((const uint32_t *)itp)[tid];
     for (int o = tid; o < kLeafVoxels; o += blockDim.x) sh.hist[o] = 0;
     if (tid == 0) sh.stash_n = 0;
     __syncthreads();
@@ -1589,7 +1597,7 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
         // the staging entry is clean for the next frame once the leaf's last
         // item is done (a whole-leaf item is the only one; slab items count
         // themselves in the item's spare word, which the plan kernel zeroes)
-        const bool last = slab < 0 || atomicAdd(&md.items[j].pad, 1u) + 1u == (uint32_t)__popc(sh.item[4] & 0xFFu);
+        const bool last = slab < 0 || atomicAdd(&itp->pad, 1u) + 1u == (uint32_t)__popc(sh.item[4] & 0xFFu);
         if (last) {
             md.skeys[pos] = kEmptyKey;
             md.pos_count[pos] = 0u;
@@ -1608,7 +1616,7 @@ static_assert(kWaveItemPairs <= kWaveLds, "a wave item must fit its LDS quarter"
 
 template <int KMAX, bool WAVE, bool ROWS>
 __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapDev &md, LeafShared &sh,
-                                               uint32_t j, unsigned long long lused, bool ok)
+                                               const LeafItem *itp, unsigned long long lused, bool ok)
 {
     const int lane = lane_id(), w = threadIdx.x >> 6;
     uint32_t *wk = sh.a_key + w * kWaveLds;
@@ -1619,7 +1627,7 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
     uint32_t *wo = sh.bin0 + w * 16;             // occupancy words of the leaf before this frame
     int *wp = (int *)sh.cur + w * 8;             // record pages of the leaf's slabs
     uint32_t *wi = sh.cur + 64 + w * 32;         // the leaf's item
-    if (lane < 32) wi[lane] = ((const uint32_t *)&md.items[j])[lane];
+    if (lane < 32) wi[lane] = ((const uint32_t *)itp)[lane];
     wave_sync();
     const uint32_t pos = wi[0], n = wi[1], bstart = wi[2];
     const int islot = (int)wi[3];
@@ -1754,15 +1762,15 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
     const uint32_t nmed = medf + (uint32_t)md.fs->n_lists_tail;
     const uint32_t nsmall = smallf + (uint32_t)(md.fs->n_lists_tail >> 32);
     const uint32_t last = md.hmask;
-    auto med_at = [&](uint32_t m) { return md.med_list[m < medf ? m : last - (m - medf)]; };
-    auto small_at = [&](uint32_t k) { return md.small_list[k < smallf ? k : last - (k - smallf)]; };
+    auto med_at = [&](uint32_t m) { return &md.items[m < medf ? m : last - (m - medf)]; };
+    auto small_at = [&](uint32_t k) { return &md.items_small[k < smallf ? k : last - (k - smallf)]; };
     const uint32_t nw = blockDim.x >> 6, w = threadIdx.x >> 6;
     const uint32_t ngroups = WAVE ? nsmall : (nsmall + nw - 1) / nw;
     const uint32_t nunits = nbig + nmed + ngroups;
     for (uint32_t u = blk; u < nunits; u += nblk) {
         if (u < nbig) {
             const int2 it = md.work[u];
-            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, (uint32_t)it.x, it.y, lused, ok);
+            fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, &md.items_big[it.x], it.y, lused, ok);
         } else if (u < nbig + nmed) {
             fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, med_at(u - nbig), -1, lused, ok);
         } else if (WAVE) {
