@@ -63,17 +63,28 @@ __device__ int32_t map_find(const MapDev &md, unsigned long long key)
     return -1;
 }
 
-// Inserts a leaf known to be absent.  The table is at most half full.
-__device__ void map_insert(const MapDev &md, unsigned long long key, int32_t slot)
+// Inserts a leaf known to be absent, in two steps so that the first probe's
+// round trip can overlap other loads: map_insert_start claims the leaf's home
+// slot if it is free (one compare-and-swap) and map_insert_finish, given that
+// result, probes on if it was taken and stores the slot.  The table is at
+// most half full.
+__device__ __forceinline__ unsigned long long map_insert_start(const MapDev &md, unsigned long long key,
+                                                               uint32_t *h)
 {
-    uint32_t h = leaf_hash(key, md.hmask);
+    *h = leaf_hash(key, md.hmask);
+    return atomicCAS(&md.htab[*h].key, kEmptyKey, key);
+}
+
+__device__ void map_insert_finish(const MapDev &md, unsigned long long key, int32_t slot, uint32_t h,
+                                  unsigned long long prev)
+{
     for (uint32_t probe = 0; probe <= md.hmask; ++probe) {
-        unsigned long long prev = atomicCAS(&md.htab[h].key, kEmptyKey, key);
         if (prev == kEmptyKey) {
             md.htab[h].val = slot;
             return;
         }
         h = (h + 1) & md.hmask;
+        prev = atomicCAS(&md.htab[h].key, kEmptyKey, key);
     }
 }
 
@@ -1341,6 +1352,14 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
     const int islot = (int)sh.item[3];
     const int slot = islot >= 0 ? islot : (int)(lused + (unsigned long long)(-1 - islot));
     const uint32_t ob = slab < 0 ? 0u : 64u * (uint32_t)slab, oe = slab < 0 ? (uint32_t)kLeafVoxels : ob + 64u;
+    // a new leaf is inserted by the item of its lowest touched slab (or its
+    // whole-leaf item); the first probe goes out with the pair loads
+    const bool lead = slab < 0 || (uint32_t)slab == (uint32_t)(__ffs(sh.item[4] & 0xFFu) - 1);
+    const bool inserts = ok && lead && islot < 0 && tid == 0;
+    const unsigned long long lkey = ((unsigned long long)sh.item[7] << 32) | sh.item[6];
+    uint32_t ih = 0;
+    unsigned long long iprev = 0;
+    if (inserts) iprev = map_insert_start(md, lkey, &ih);
     if (tid < kMaskWords) sh.occ0[tid] = sh.item[16 + tid];
     if (tid < kLeafPages) sh.pages[tid] = (int)sh.item[8 + tid];
 
@@ -1576,11 +1595,9 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
     // item) also inserts a new leaf and writes the entries of untouched slabs
     if (ok) {
         const uint32_t tslabs = sh.item[4] & 0xFFu;
-        const bool lead = slab < 0 || (uint32_t)slab == (uint32_t)(__ffs(tslabs) - 1);
-        if (tid == 0 && lead && islot < 0) {
-            const unsigned long long key = ((unsigned long long)sh.item[7] << 32) | sh.item[6];
-            map_insert(md, key, slot);
-            md.leaf_key[slot] = key;
+        if (inserts) {
+            map_insert_finish(md, lkey, slot, ih, iprev);
+            md.leaf_key[slot] = lkey;
         }
         if (tid < kLeafPages) {
             const bool mine = slab < 0 || tid == slab || (lead && !((tslabs >> tid) & 1u));
@@ -1633,6 +1650,12 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
     const int islot = (int)wi[3];
     const int slot = islot >= 0 ? islot : (int)(lused + (unsigned long long)(-1 - islot));
     const bool labels = KMAX > 0 && !ROWS && !WAVE;
+    // a new leaf's first insertion probe goes out with the pair loads
+    const bool inserts = ok && islot < 0 && lane == 0;
+    const unsigned long long lkey = ((unsigned long long)wi[7] << 32) | wi[6];
+    uint32_t ih = 0;
+    unsigned long long iprev = 0;
+    if (inserts) iprev = map_insert_start(md, lkey, &ih);
     // the pairs in registers (four per lane), their keys also in LDS; keys are
     // distinct (a ray visits a voxel once), so a pair's rank is the number of
     // smaller keys, and writing each pair at its rank sorts them by (offset,
@@ -1718,10 +1741,9 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
         atomicAdd(&sh.unew, un);
     }
     if (ok) {
-        if (lane == 0 && islot < 0) {
-            const unsigned long long key = ((unsigned long long)wi[7] << 32) | wi[6];
-            map_insert(md, key, slot);
-            md.leaf_key[slot] = key;
+        if (inserts) {
+            map_insert_finish(md, lkey, slot, ih, iprev);
+            md.leaf_key[slot] = lkey;
         }
         if (lane < kLeafPages) md.leaf_page[(size_t)slot * kLeafPages + lane] = page;
         if (lane < kMaskWords) md.leaf_occ[(size_t)slot * kMaskWords + lane] = occ | tw;
