@@ -124,8 +124,8 @@ struct LossParams {
 };
 
 // Everything the leaf kernel needs of one touched leaf, written by the plan
-// kernel at the leaf's index in the touched list, so that one 128-byte read
-// starts its work.
+// kernel where the leaf kernel's unit of work finds it (see MapDev::items), so
+// that one 128-byte read starts its work.
 struct alignas(16) LeafItem {
     uint32_t pos;             // staging position
     uint32_t n;               // pairs

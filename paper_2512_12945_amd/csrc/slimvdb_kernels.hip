@@ -1331,7 +1331,7 @@ __device__ __forceinline__ void rank_bins(LeafShared &sh, KP bk, VP bv, uint32_t
     }
 }
 
-// One work item of the leaf kernel: the touched leaf of touched index j, all
+// One work item of the leaf kernel: the touched leaf of item *itp, all
 // of it (slab < 0) or, for a leaf with more pairs than LDS holds, the voxels
 // of one x-slab (offsets 64 slab .. 64 slab + 63), so that the slabs of a
 // large leaf run in different workgroups.  Reads every pair of the leaf for
