@@ -828,26 +828,52 @@ __device__ __forceinline__ void combine_lane_pass(const FrameParams &fp, const M
     }
     uint32_t q = 0;
     while (q < n) {
-        // the run of one frame: point indices below the next frame's offset
+        // the run of one frame: point indices below the next frame's offset;
+        // inside a voxel the keys ascend with the point index, so its end is
+        // found by bisection
         const uint32_t end = fp.sub_start[pass_frame(fp, keys[q] & kPidMask) + 1];
-        uint32_t qe = q + 1;
-        while (qe < n && (keys[qe] & kPidMask) < end) ++qe;
-        const uint32_t m = qe - q;
+        uint32_t lo = q + 1, hi = n;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((keys[mid] & kPidMask) < end) lo = mid + 1;
+            else hi = mid;
+        }
+        const uint32_t qe = lo, m = qe - q;
         const float W0 = r[1], W1 = W0 + (float)m;
-        r[0] = tsdf_mean(r[0], W0, W1, tsdf_sum(vals + q, m));
-        r[1] = W1;
-        if (KMAX > 0) {
-            if (m <= 255u) {
-                uint32_t cw[KW];
+        // the run's distances (summed in point order in binary64) and, up to
+        // 255 observations, its class counts as 8-bit fields, read four at a
+        // time
+        const bool packed = KMAX > 0 && m <= 255u;
+        double sum_t = 0.0;
+        uint32_t cw[KW];
 #pragma unroll
-                for (int w = 0; w < KW; ++w) cw[w] = 0u;
-                for (uint32_t t = q; t < qe; ++t) {
-                    const int lab = labs ? labs[t] : point_label(fp, keys[t] & kPidMask);
-                    const int wi = lab >> 2;
-                    const uint32_t inc = 1u << ((lab & 3) << 3);
+        for (int w = 0; w < KW; ++w) cw[w] = 0u;
+        for (uint32_t t0 = q; t0 < qe; t0 += 4) {
+            float v4[4];
+            int l4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t t = t0 + u;
+                v4[u] = t < qe ? vals[t] : 0.0f;
+                l4[u] = (packed && t < qe) ? (labs ? labs[t] : point_label(fp, keys[t] & kPidMask)) : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (t0 + u < qe) sum_t += (double)v4[u];
+            if (packed) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int wi = l4[u] >> 2;  // -1 for no observation
+                    const uint32_t inc = 1u << ((l4[u] & 3) << 3);
 #pragma unroll
                     for (int w = 0; w < KW; ++w) cw[w] += (w == wi) ? inc : 0u;
                 }
+            }
+        }
+        r[0] = tsdf_mean(r[0], W0, W1, sum_t);
+        r[1] = W1;
+        if (KMAX > 0) {
+            if (packed) {
 #pragma unroll
                 for (int k = 0; k < KA; ++k)
                     if (k < K) r[2 + k] += (float)((cw[k >> 2] >> ((k & 3) << 3)) & 0xFFu);
