@@ -1054,7 +1054,11 @@ __device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const Ma
     const int lane = lane_id();
     const bool bf = fp.sem_kind == SLIM_IN_EMB_BF16;
     float *R = md.vox + (size_t)rec * md.rec_stride;
-    const uint32_t p0 = keys[0] & kPidMask;
+    // the point indices and distances of up to 64 observations, one per lane,
+    // requested before the first row
+    uint32_t kl = (uint32_t)lane < n ? keys[lane] & kPidMask : 0u;
+    float vl = (uint32_t)lane < n ? vals[lane] : 0.0f;
+    const uint32_t p0 = (uint32_t)__shfl((int)kl, 0, 64);
     float z0[V], s1[V], s2[V];
     load_row<V>(fp, bf, p0, lane, z0);
 #pragma unroll
@@ -1062,15 +1066,31 @@ __device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const Ma
         s1[i] = 0.0f;
         s2[i] = 0.0f;
     }
-    for (uint32_t q = 1; q < n; q += B) {
+    // binary64 distance sum in point order (Eq. (1)-(2)), from the lanes
+    double sum_t = 0.0;
+    // batches of B rows from observation 0 (whose difference is 0); a batch
+    // never crosses a group of 64 observations
+    for (uint32_t q = 0; q < n; q += B) {
+        if (q > 0 && (q & 63u) == 0) {
+            kl = q + (uint32_t)lane < n ? keys[q + lane] & kPidMask : 0u;
+            vl = q + (uint32_t)lane < n ? vals[q + lane] : 0.0f;
+        }
         float z[B][V];
 #pragma unroll
-        for (int b = 0; b < B; ++b) load_row<V>(fp, bf, q + b < n ? keys[q + b] & kPidMask : p0, lane, z[b]);
+        for (int b = 0; b < B; ++b) {
+            const uint32_t pid = (uint32_t)__shfl((int)kl, (int)((q + b) & 63u), 64);
+            load_row<V>(fp, bf, q + b < n ? pid : p0, lane, z[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const float v = __shfl(vl, (int)((q + b) & 63u), 64);
+            if (q + b < n) sum_t += (double)v;
+        }
 #pragma unroll
         for (int b = 0; b < B; ++b)
 #pragma unroll
             for (int i = 0; i < V; ++i) {
-                const float d = z[b][i] - z0[i];  // 0 for the padding (the first row again)
+                const float d = z[b][i] - z0[i];  // 0 for observation 0 and the padding (its row again)
                 s1[i] += d;
                 s2[i] += d * d;
             }
@@ -1090,7 +1110,7 @@ __device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const Ma
         M[i] = (W0 * m0 + nf * zbar) / W1;
     }
     if (lane == 0) {
-        R[0] = tsdf_mean(D0, W0, W1, tsdf_sum(vals, n));
+        R[0] = tsdf_mean(D0, W0, W1, sum_t);
         R[1] = W1;
     }
 }
