@@ -1055,9 +1055,23 @@ __device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const Ma
     const bool bf = fp.sem_kind == SLIM_IN_EMB_BF16;
     float *R = md.vox + (size_t)rec * md.rec_stride;
     // the point indices and distances of up to 64 observations, one per lane,
-    // requested before the first row
+    // requested before the first row, and (up to 8 components per lane) the
+    // voxel's record with them
+    constexpr bool early = V <= 8;
     uint32_t kl = (uint32_t)lane < n ? keys[lane] & kPidMask : 0u;
     float vl = (uint32_t)lane < n ? vals[lane] : 0.0f;
+    float *M = R + 2 + lane * V, *Bt = R + 2 + 64 * V + lane * V;
+    float m0[early ? V : 1], b0[early ? V : 1];
+    float W0 = 0.0f, D0 = 0.0f;
+    if constexpr (early) {
+        W0 = existed ? R[1] : 0.0f;
+        D0 = existed ? R[0] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < V; ++i) {
+            m0[i] = existed ? M[i] : 0.0f;
+            b0[i] = existed ? Bt[i] : 0.0f;
+        }
+    }
     const uint32_t p0 = (uint32_t)__shfl((int)kl, 0, 64);
     float z0[V], s1[V], s2[V];
     load_row<V>(fp, bf, p0, lane, z0);
@@ -1097,17 +1111,27 @@ __device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const Ma
     }
     // Eqs. (11)-(14) with lambda = W, nu = W / 2
     const float nf = (float)n;
-    const float W0 = existed ? R[1] : 0.0f, W1 = W0 + nf, D0 = existed ? R[0] : 0.0f;
+    if constexpr (!early) {
+        W0 = existed ? R[1] : 0.0f;
+        D0 = existed ? R[0] : 0.0f;
+    }
+    const float W1 = W0 + nf;
     const float cross = W0 * nf / W1;
-    float *M = R + 2 + lane * V, *Bt = R + 2 + 64 * V + lane * V;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
         const float zbar = z0[i] + s1[i] / nf;
         const float scat = fmaxf(s2[i] - s1[i] * s1[i] / nf, 0.0f);
-        const float m0 = existed ? M[i] : 0.0f, b0 = existed ? Bt[i] : 0.0f;
-        const float dm = zbar - m0;
-        Bt[i] = b0 + 0.5f * scat + cross * dm * dm * 0.5f;
-        M[i] = (W0 * m0 + nf * zbar) / W1;
+        float mi, bi;
+        if constexpr (early) {
+            mi = m0[i];
+            bi = b0[i];
+        } else {
+            mi = existed ? M[i] : 0.0f;
+            bi = existed ? Bt[i] : 0.0f;
+        }
+        const float dm = zbar - mi;
+        Bt[i] = bi + 0.5f * scat + cross * dm * dm * 0.5f;
+        M[i] = (W0 * mi + nf * zbar) / W1;
     }
     if (lane == 0) {
         R[0] = tsdf_mean(D0, W0, W1, sum_t);
