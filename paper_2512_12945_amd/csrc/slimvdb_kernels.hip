@@ -911,6 +911,22 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
     constexpr int KA = KMAX > 0 ? KMAX : 1;
     constexpr int NV = (2 + KMAX + 3) / 4;
     const int nv = md.rec_stride / 4, K = fp.K;
+    // up to 24 classes the record is requested first, so its round trip
+    // overlaps the counting (more classes would spill registers)
+    constexpr bool early = KMAX <= 24;
+    float4 *R = (float4 *)(md.vox + (size_t)rec * md.rec_stride);
+    float r[4 * NV];
+    auto load_record = [&]() {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const float4 x = (existed && v < nv) ? R[v] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            r[4 * v + 0] = x.x;
+            r[4 * v + 1] = x.y;
+            r[4 * v + 2] = x.z;
+            r[4 * v + 3] = x.w;
+        }
+    };
+    if constexpr (early) load_record();
     float acc[KA];
 #pragma unroll
     for (int k = 0; k < KA; ++k) acc[k] = 0.0f;
@@ -974,16 +990,7 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
             }
         }
     }
-    float4 *R = (float4 *)(md.vox + (size_t)rec * md.rec_stride);
-    float r[4 * NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const float4 x = (existed && v < nv) ? R[v] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        r[4 * v + 0] = x.x;
-        r[4 * v + 1] = x.y;
-        r[4 * v + 2] = x.z;
-        r[4 * v + 3] = x.w;
-    }
+    if constexpr (!early) load_record();
     // Eq. (1)-(2) with unit weights
     const float nf = (float)n, W0 = r[1], W1 = W0 + nf;
     r[0] = tsdf_mean(r[0], W0, W1, tsdf_sum(vals, n));
