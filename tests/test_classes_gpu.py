@@ -1,0 +1,83 @@
+"""Closed-set parity over class counts that select the other lane-combine
+kernels: up to 16 and up to 32 classes held per lane (K = 12, 30, 32), for
+int32 labels, probability rows and logit rows, one frame at a time; and int32
+labels with 30 classes in multi-frame passes, which must equal one call per
+frame bit for bit.  Semantics are drawn from a seeded generator over all K
+classes; the geometry is the synthetic room and street of the other tests."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2512_12945_amd import slimvdb as sv
+from paper_2512_12945_amd import synth
+
+from _gpu_util import assert_stats_equal, compare_maps, cuda, extract_np, integrate_both, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sv.load()
+
+
+def _semantics(kind, n, K, rng):
+    if kind == sv.IN_LABEL_I32:
+        return rng.integers(0, K, n).astype(np.int32)
+    x = rng.normal(0.0, 1.5, (n, K)).astype(np.float32)
+    if kind == sv.IN_LOGIT_F32:
+        return x
+    e = np.exp(x.astype(np.float64) - x.max(axis=1, keepdims=True))
+    return (e / e.sum(axis=1, keepdims=True)).astype(np.float32)
+
+
+@pytest.mark.parametrize("K", [12, 30, 32])
+@pytest.mark.parametrize("kind", [sv.IN_LABEL_I32, sv.IN_PROB_F32, sv.IN_LOGIT_F32])
+def test_class_widths(K, kind):
+    _say(f"room sequence, K = {K}, kind {kind}")
+    frames = synth.room_sequence(3, seed=12, yaw_span=1.0, width=96, height=72, f=60.0, cx=48.0, cy=36.0)
+    rng = np.random.default_rng([K, kind])
+    g, o = make_pair(0.05, 0.15, 0.0, 100.0, sv.SEM_CLOSED, K=K)
+    for fr in frames:
+        sem = _semantics(kind, fr["points"].shape[0], K, rng)
+        gst, ost = integrate_both(g, o, fr["points"], fr["pose"], sem, kind)
+        assert_stats_equal(gst, ost)
+    err = compare_maps(extract_np(g), o.extract(), 0.15, sv.SEM_CLOSED, K=K, exact_counts=kind == sv.IN_LABEL_I32)
+    _say(f"  errors {err}")
+    g.close()
+
+
+def test_passes_with_30_classes():
+    _say("street sweeps, 30 classes, passes of 2 and 3 against one call per sweep and the oracle")
+    sc = synth.StreetScene(seed=4)
+    rng = np.random.default_rng(30)
+    sweeps = []
+    for t in range(7):
+        sw = sc.sweep(t, nrays=10_000 + 3_000 * t)
+        sweeps.append((sw["points"], sw["pose"], rng.integers(0, 30, sw["points"].shape[0]).astype(np.int32)))
+    ref, o = make_pair(0.1, 0.3, 0.0, 50.0, sv.SEM_CLOSED, K=30)
+    for pts, pose, lab in sweeps:
+        gst, ost = integrate_both(ref, o, pts, pose, lab, sv.IN_LABEL_I32)
+        assert_stats_equal(gst, ost)
+    rx = extract_np(ref)
+    compare_maps(rx, o.extract(), 0.3, sv.SEM_CLOSED, K=30, exact_counts=True)
+    frames = [dict(points=cuda(p), pose=pose, sem=cuda(lab), kind=sv.IN_LABEL_I32) for p, pose, lab in sweeps]
+    for pf in (2, 3):
+        seq = sv.Map(0.1, 0.3, 0.0, 50.0, sv.SEM_CLOSED, 30, 0, 0, 1 << 16, 1 << 22)
+        seq.set_launch_shape(pass_frames=pf)
+        sv.integrate_sequence(seq, frames)
+        assert seq.stats() == ref.stats()
+        sx = extract_np(seq)
+        for k in rx:
+            assert np.array_equal(rx[k], sx[k]), (pf, k)
+        seq.close()
+    ref.close()
