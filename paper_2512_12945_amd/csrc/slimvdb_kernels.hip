@@ -1168,17 +1168,27 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
         s1[j] = 0.0f;
         s2[j] = 0.0f;
     }
+    // the point indices of 64 observations at a time, one per lane; a batch's
+    // indices come from the lanes, so its rows do not wait on a load of them
+    // (batches start at multiples of their size and never cross a window)
+    uint32_t kl = (uint32_t)lane < n ? keys[lane] & kPidMask : 0u;
+    auto window = [&](uint32_t q) {
+        if (q > 0 && (q & 63u) == 0) kl = q + (uint32_t)lane < n ? keys[q + lane] & kPidMask : 0u;
+    };
+    auto pid_at = [&](uint32_t t) { return (uint32_t)__shfl((int)kl, (int)(t & 63u), 64); };
     if (open) {
         float z0[kWaveComps];
-        const uint32_t p0 = keys[0] & kPidMask;
+        const uint32_t p0 = pid_at(0);
 #pragma unroll
         for (int j = 0; j < kWaveComps; ++j) z0[j] = (lane + 64 * j < C) ? load_emb(fp, p0, lane + 64 * j) : 0.0f;
-        for (uint32_t q = 1; q < n; q += kWaveBatch) {
+        // observation 0 enters as its own difference, 0
+        for (uint32_t q = 0; q < n; q += kWaveBatch) {
+            window(q);
             float z[kWaveBatch][kWaveComps];
 #pragma unroll
             for (int b = 0; b < kWaveBatch; ++b) {
-                const bool has = q + b < n;
-                const uint32_t pid = has ? keys[q + b] & kPidMask : p0;
+                const bool has = q + b < n && q + b > 0;
+                const uint32_t pid = pid_at(q + b);
 #pragma unroll
                 for (int j = 0; j < kWaveComps; ++j)
                     z[b][j] = (has && lane + 64 * j < C) ? load_emb(fp, pid, lane + 64 * j) : z0[j];
@@ -1211,10 +1221,13 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
         }
     } else if (fp.sem_kind == SLIM_IN_LABEL_I32) {
         for (uint32_t q = 0; q < n; q += 2 * kWaveBatch) {
+            window(q);
             int lab[2 * kWaveBatch];
 #pragma unroll
-            for (int b = 0; b < 2 * kWaveBatch; ++b)
-                lab[b] = q + b < n ? ((const int32_t *)fp.sem)[keys[q + b] & kPidMask] : -1;
+            for (int b = 0; b < 2 * kWaveBatch; ++b) {
+                const uint32_t pid = pid_at(q + b);
+                lab[b] = q + b < n ? ((const int32_t *)fp.sem)[pid] : -1;
+            }
 #pragma unroll
             for (int b = 0; b < 2 * kWaveBatch; ++b)
 #pragma unroll
@@ -1222,11 +1235,13 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
         }
     } else if (fp.sem_kind == SLIM_IN_PROB_F32) {
         for (uint32_t q = 0; q < n; q += kWaveBatch) {
+            window(q);
             float x[kWaveBatch][kWaveComps];
 #pragma unroll
             for (int b = 0; b < kWaveBatch; ++b) {
                 const bool has = q + b < n;
-                const size_t row = has ? (size_t)(keys[q + b] & kPidMask) * C : 0;
+                const uint32_t pid = pid_at(q + b);
+                const size_t row = has ? (size_t)pid * C : 0;
 #pragma unroll
                 for (int j = 0; j < kWaveComps; ++j)
                     x[b][j] = (has && lane + 64 * j < C) ? ((const float *)fp.sem)[row + lane + 64 * j] : 0.0f;
@@ -1239,11 +1254,13 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
     } else {
         // logits, K <= 64: softmax across the wave
         for (uint32_t q = 0; q < n; q += kWaveBatch) {
+            window(q);
             float l[kWaveBatch];
 #pragma unroll
-            for (int b = 0; b < kWaveBatch; ++b)
-                l[b] = (q + b < n && lane < C) ? ((const float *)fp.sem)[(size_t)(keys[q + b] & kPidMask) * C + lane]
-                                               : -INFINITY;
+            for (int b = 0; b < kWaveBatch; ++b) {
+                const uint32_t pid = pid_at(q + b);
+                l[b] = (q + b < n && lane < C) ? ((const float *)fp.sem)[(size_t)pid * C + lane] : -INFINITY;
+            }
 #pragma unroll
             for (int b = 0; b < kWaveBatch; ++b) {
                 if (q + b >= n) break;
@@ -1263,8 +1280,16 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
             if (comp < C) R[2 + comp] = (existed ? R[2 + comp] : 0.0f) + s1[j];
         }
     }
+    // binary64 distance sum in point order, 64 distances loaded at a time
+    double sum_t = 0.0;
+    for (uint32_t w0 = 0; w0 < n; w0 += 64) {
+        const float vl = w0 + (uint32_t)lane < n ? vals[w0 + lane] : 0.0f;
+        const uint32_t m = min(n - w0, 64u);
+        for (uint32_t t = 0; t < m; ++t)
+            sum_t += (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(vl), (int)t));
+    }
     if (lane == 0) {
-        R[0] = tsdf_mean(D0, W0, W1, tsdf_sum(vals, n));
+        R[0] = tsdf_mean(D0, W0, W1, sum_t);
         R[1] = W1;
     }
 }
