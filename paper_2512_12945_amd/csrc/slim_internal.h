@@ -219,11 +219,11 @@ struct BatchPlan {
     int nmaps;
     int walk_blocks;                 // total blocks of the walk kernel
     int ngroups;
-    int group_kind[16];                   // leaf-kernel variant of each group
-    int group_begin[16], group_size[16];  // slice of the device subset array
+    int group_kind[17];                   // leaf-kernel variant of each group
+    int group_begin[17], group_size[17];  // slice of the device subset array
 };
 
-constexpr int kLeafKinds = 16;  // variants of the leaf kernel (leaf_kernel_kind)
+constexpr int kLeafKinds = 17;  // variants of the leaf kernel (leaf_kernel_kind)
 int leaf_kernel_kind(const FrameParams &fp);
 hipError_t launch_integrate_batched(const MapBatch &mb, const BatchPlan &plan, const LaunchShape &shape,
                                     hipStream_t s);

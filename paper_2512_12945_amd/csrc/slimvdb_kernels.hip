@@ -911,9 +911,9 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
     constexpr int KA = KMAX > 0 ? KMAX : 1;
     constexpr int NV = (2 + KMAX + 3) / 4;
     const int nv = md.rec_stride / 4, K = fp.K;
-    // up to 24 classes the record is requested first, so its round trip
-    // overlaps the counting (more classes would spill registers)
-    constexpr bool early = KMAX <= 24;
+    // up to 24 classes (16 for rows) the record is requested first, so its
+    // round trip overlaps the counting (more would spill registers)
+    constexpr bool early = KMAX <= (ROWS ? 16 : 24);
     float4 *R = (float4 *)(md.vox + (size_t)rec * md.rec_stride);
     float r[4 * NV];
     auto load_record = [&]() {
@@ -959,34 +959,41 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
             for (int k = 0; k < KA; ++k) acc[k] += (float)((cw[k >> 2] >> ((k & 3) << 3)) & 0xFFu);
         }
     }
-    for (uint32_t c0 = 0; (KMAX > 0 && ROWS) && c0 < n; c0 += 8) {
-        uint32_t kk[8];
+    if constexpr (KMAX > 0 && ROWS) {
+        // the rows of RB observations are loaded before any is used (two up to
+        // 24 classes; more would spill registers), then each is added in
+        // point order
+        constexpr int RB = KMAX <= 24 ? 2 : 1;
+        for (uint32_t t0 = 0; t0 < n; t0 += RB) {
+            float x[RB][KA];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) kk[q] = c0 + q < n ? keys[c0 + q] : 0u;
-        for (int q = 0; q < 8; ++q) {
-            if (c0 + q >= n) break;
-            if (KMAX > 0 && ROWS) {
-                const float *row = (const float *)fp.sem + (size_t)(kk[q] & kPidMask) * K;
-                float x[KA];
+            for (int b = 0; b < RB; ++b) {
+                const bool has = t0 + b < n;
+                const float *row = (const float *)fp.sem + (size_t)(has ? keys[t0 + b] & kPidMask : 0u) * K;
 #pragma unroll
-                for (int k = 0; k < KA; ++k) x[k] = k < K ? row[k] : 0.0f;
-                if (fp.sem_kind == SLIM_IN_LOGIT_F32) {
-                    // softmax of the logits, max-subtracted
-                    float mx = x[0];
+                for (int k = 0; k < KA; ++k) x[b][k] = (has && k < K) ? row[k] : 0.0f;
+            }
 #pragma unroll
-                    for (int k = 1; k < KA; ++k)
-                        if (k < K) mx = fmaxf(mx, x[k]);
-                    float den = 0.0f;
+            for (int b = 0; b < RB; ++b) {
+                if (t0 + b < n) {
+                    if (fp.sem_kind == SLIM_IN_LOGIT_F32) {
+                        // softmax of the logits, max-subtracted
+                        float mx = x[b][0];
 #pragma unroll
-                    for (int k = 0; k < KA; ++k) {
-                        x[k] = k < K ? expf(x[k] - mx) : 0.0f;
-                        den += x[k];
+                        for (int k = 1; k < KA; ++k)
+                            if (k < K) mx = fmaxf(mx, x[b][k]);
+                        float den = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < KA; ++k) {
+                            x[b][k] = k < K ? expf(x[b][k] - mx) : 0.0f;
+                            den += x[b][k];
+                        }
+#pragma unroll
+                        for (int k = 0; k < KA; ++k) x[b][k] = x[b][k] / den;
                     }
 #pragma unroll
-                    for (int k = 0; k < KA; ++k) x[k] = x[k] / den;
+                    for (int k = 0; k < KA; ++k) acc[k] += x[b][k];
                 }
-#pragma unroll
-                for (int k = 0; k < KA; ++k) acc[k] += x[k];
             }
         }
     }
@@ -2079,10 +2086,11 @@ __global__ __launch_bounds__(256) void k_frame_commit_batch(MapBatch mb)
 // ---------------------------------------------------------------------------
 
 // Variant of the leaf kernel a frame needs: 0 geometry; 1..4 labels with
-// 8/16/24/32 classes in registers; 5..7 probability or logit rows with 8/16/32;
+// 8/16/24/32 classes in registers; 5..7 probability or logit rows with 8/16/32 (17..24 classes: 16);
 // 8 one wave per voxel (open set, or more than 32 classes); 9 and 10 the
 // most-recent-measurement modes (closed: lane per voxel; open: wave per voxel);
-// 11..15 the open set with L = 64, 128, 256, 512, 1024 read as whole words.
+// 11..15 the open set with L = 64, 128, 256, 512, 1024 read as whole words;
+// 16 probability or logit rows with 24 classes in registers.
 int leaf_kernel_kind(const FrameParams &fp)
 {
     if (fp.last) return fp.L > 0 ? 10 : 9;
@@ -2099,7 +2107,7 @@ int leaf_kernel_kind(const FrameParams &fp)
     if (fp.L > 0 || fp.K > 32) return 8;
     if (fp.K == 0) return 0;
     const bool rows = fp.sem_kind == SLIM_IN_PROB_F32 || fp.sem_kind == SLIM_IN_LOGIT_F32;
-    if (rows) return fp.K > 16 ? 7 : (fp.K > 8 ? 6 : 5);
+    if (rows) return fp.K > 24 ? 7 : (fp.K > 16 ? 16 : (fp.K > 8 ? 6 : 5));
     return fp.K > 24 ? 4 : (fp.K > 16 ? 3 : (fp.K > 8 ? 2 : 1));
 }
 
@@ -2161,6 +2169,7 @@ static void launch_leaf(int kind, const FrameParams &fp, const MapDev &md, int b
     case 5: hipLaunchKernelGGL((k_leaf_fuse<8, false, true>), gl, bl, 0, s, fp, md); break;
     case 6: hipLaunchKernelGGL((k_leaf_fuse<16, false, true>), gl, bl, 0, s, fp, md); break;
     case 7: hipLaunchKernelGGL((k_leaf_fuse<32, false, true>), gl, bl, 0, s, fp, md); break;
+    case 16: hipLaunchKernelGGL((k_leaf_fuse<24, false, true>), gl, bl, 0, s, fp, md); break;
     case 9: hipLaunchKernelGGL((k_leaf_fuse<-1, false, false>), gl, bl, 0, s, fp, md); break;
     case 10: hipLaunchKernelGGL((k_leaf_fuse<-1, true, false>), gl, bl, 0, s, fp, md); break;
     case 11: hipLaunchKernelGGL((k_leaf_fuse<1, true, false>), gl, bl, 0, s, fp, md); break;
@@ -2184,6 +2193,7 @@ static void launch_leaf_batch(int kind, const MapBatch &mb, int blocks, hipStrea
     case 5: hipLaunchKernelGGL((k_leaf_fuse_batch<8, false, true>), gl, bl, 0, s, mb); break;
     case 6: hipLaunchKernelGGL((k_leaf_fuse_batch<16, false, true>), gl, bl, 0, s, mb); break;
     case 7: hipLaunchKernelGGL((k_leaf_fuse_batch<32, false, true>), gl, bl, 0, s, mb); break;
+    case 16: hipLaunchKernelGGL((k_leaf_fuse_batch<24, false, true>), gl, bl, 0, s, mb); break;
     case 9: hipLaunchKernelGGL((k_leaf_fuse_batch<-1, false, false>), gl, bl, 0, s, mb); break;
     case 10: hipLaunchKernelGGL((k_leaf_fuse_batch<-1, true, false>), gl, bl, 0, s, mb); break;
     case 11: hipLaunchKernelGGL((k_leaf_fuse_batch<1, true, false>), gl, bl, 0, s, mb); break;

@@ -1,5 +1,5 @@
 """Closed-set parity over class counts that select the other lane-combine
-kernels: up to 16 and up to 32 classes held per lane (K = 12, 30, 32), for
+kernels: up to 16, 24 and 32 classes held per lane (K = 12, 20, 30, 32), for
 int32 labels, probability rows and logit rows, one frame at a time; and int32
 labels with 30 classes in multi-frame passes, which must equal one call per
 frame bit for bit.  Semantics are drawn from a seeded generator over all K
@@ -40,7 +40,7 @@ def _semantics(kind, n, K, rng):
     return (e / e.sum(axis=1, keepdims=True)).astype(np.float32)
 
 
-@pytest.mark.parametrize("K", [12, 30, 32])
+@pytest.mark.parametrize("K", [12, 20, 30, 32])
 @pytest.mark.parametrize("kind", [sv.IN_LABEL_I32, sv.IN_PROB_F32, sv.IN_LOGIT_F32])
 def test_class_widths(K, kind):
     _say(f"room sequence, K = {K}, kind {kind}")
