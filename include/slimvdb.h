@@ -91,17 +91,23 @@ typedef struct slim_stats {
     int32_t reserved;
 } slim_stats;
 
-/* Creates an empty map on config->device.  Allocates every device buffer the
- * configured capacity needs (leaf table, leaf index, voxel records).  *out
- * receives the handle.  SLIM_ERR_INVALID on a bad configuration,
- * SLIM_ERR_DEVICE if allocation fails. */
+/* Creates an empty map on config->device: the sparse voxel store of Sec. III-A
+ * (voxels near the surface holding signed distance, weight and semantic
+ * parameters; the role of OpenVDB's tree, Sec. II-C, with O(1) lookup and
+ * insertion and no preset bounds), here 8^3-voxel leaves found by a hashed
+ * leaf table, with D and W per voxel and the semantic state of Sec. III-C or
+ * III-D.  Allocates every device buffer the configured
+ * capacity needs (leaf table, leaf index, voxel records).  *out receives the
+ * handle.  SLIM_ERR_INVALID on a bad configuration, SLIM_ERR_DEVICE if
+ * allocation fails. */
 slim_status slim_map_create(const slim_map_config *config, slim_map **out);
 
-/* Frees the map after waiting for all work on its device.  NULL is a no-op. */
+/* Frees the map after waiting for all work on its device.  NULL is a no-op.
+ * (Lifetime of the voxel store of Sec. III-A; no paper equation.) */
 slim_status slim_map_destroy(slim_map *map);
 
-/* Empties the map (no leaves, no voxels) and keeps its capacity.  Queued on
- * `stream`. */
+/* Empties the map (no leaves, no voxels) and keeps its capacity: the empty
+ * store a sequence of frames starts from (Sec. III-A).  Queued on `stream`. */
 slim_status slim_map_reset(slim_map *map, void *stream);
 
 /* Integrates one frame (Sec. III-A to III-D): for each of the n points,
@@ -109,8 +115,11 @@ slim_status slim_map_reset(slim_map *map, void *stream);
  * the ray from the sensor origin, the TSDF update of every voxel on it whose
  * signed distance exceeds -sdf_trunc, and the semantic update of the same
  * voxels with the same unit weight.  pose_host is map_T_sensor, 4x4 row-major
- * double; the sensor origin is its translation.  sem_dev holds the per-point
- * semantics in the layout sem_kind names (NULL for SLIM_IN_NONE).
+ * double; the sensor origin is its translation.  Geometry is computed in
+ * binary32 relative to the origin's voxel (the anchor, floor(t / voxel_size)
+ * in double); an origin 2^20 or more voxels out is anchored at +2^20, and each
+ * point whose walk then leaves |k| < 2^20 is rejected.  sem_dev holds the
+ * per-point semantics in the layout sem_kind names (NULL for SLIM_IN_NONE).
  * Per-voxel results equal one batch update per voxel with all of the frame's
  * observations of that voxel, which is what the paper's per-point recursion
  * reaches (Thm. 1 and 2 are stated for sets); observations are combined in
@@ -136,9 +145,11 @@ slim_status slim_integrate_depth(slim_map *map, const float *depth_dev, int32_t 
                                  const float *intrinsics_host, const double *pose_host, const void *sem_dev,
                                  int32_t sem_kind, void *stream);
 
-/* Synchronises `stream` and copies the map's counters to *out_host.  Returns
- * the first asynchronous error since the previous call (then cleared), else
- * SLIM_OK. */
+/* Synchronises `stream` and copies the map's counters to *out_host: leaves and
+ * voxels of the store (Sec. III-A), and the last frame's points, rejections,
+ * voxel updates and touched/new leaves and voxels (the quantities the
+ * integration of Sec. III-A to III-D produces per frame).  Returns the first
+ * asynchronous error since the previous call (then cleared), else SLIM_OK. */
 slim_status slim_map_stats(slim_map *map, slim_stats *out_host, void *stream);
 
 /* Exports every voxel with W > 0, ordered by leaf coordinate (x, then y, then
@@ -155,9 +166,11 @@ slim_status slim_map_stats(slim_map *map, slim_stats *out_host, void *stream);
 slim_status slim_extract(slim_map *map, int64_t capacity, int32_t *keys_dev, float *d_dev, float *w_dev,
                          float *sem_dev, int64_t *count_host, void *stream);
 
-/* Looks up the voxels holding m world points xyz_dev (float [m x 3]) and
- * writes their state: d_dev, w_dev (float [m]) and, unless NULL, sem_dev
- * (float [m x S]).  Unobserved voxels, and points with non-finite or
+/* Sparse querying of the map (Sec. III-A: the store gives fast querying; O(1)
+ * lookup, Sec. II-C): looks up the voxels holding m world points xyz_dev (float [m x 3]),
+ * voxel floor(x / voxel_size) in binary32, and writes their state: d_dev,
+ * w_dev (float [m]) and, unless NULL, sem_dev (float [m x S], as
+ * slim_extract).  Unobserved voxels, and points with non-finite or
  * out-of-range coordinates, read as all zeros (W = 0).  Queued on `stream`. */
 slim_status slim_query(slim_map *map, const float *xyz_dev, int64_t m, float *d_dev, float *w_dev, float *sem_dev,
                        void *stream);
@@ -221,8 +234,10 @@ slim_status slim_integrate_rays(slim_map *map, const float *ranges_dev, const fl
  * over the M' of the s world points samples_dev (float [s x 3]) whose voxel
  * (floor(x / voxel_size), binary32 division) is in the map.  Writes
  * loss_dev[0..2] = (L, first term, second term) on the device and keeps the
- * per-voxel adjoints dL/dc and dL/dD for slim_backward_rays.  Sums are formed in
- * a fixed order (bitwise repeatable).  Queued on `stream`; the first call on a
+ * per-voxel adjoints dL/dc and dL/dD for slim_backward_rays.  A voxel whose label
+ * is outside [0, K) adds no cross-entropy term and gets dL/dc = 0 (it still
+ * counts in m, and its surface samples count); voxels not listed get zero
+ * adjoints.  Sums are formed in a fixed order (bitwise repeatable).  Queued on `stream`; the first call on a
  * map allocates the adjoint buffers (synchronising).  SLIM_ERR_UNSUPPORTED for
  * open-set or geometry-only maps. */
 slim_status slim_map_loss(slim_map *map, const int32_t *keys_dev, const int32_t *labels_dev, int64_t m,

@@ -9,9 +9,11 @@ rays is
                                               p_v(i) = (a0 + c_vi) / (K a0 + sum_i c_vi)
       + (1/M') sum_s |D(v_s)|                 TSDF at surface samples
 
-over all voxels v of the map (y_v the ground-truth class) and the M' surface
-samples s whose voxel v_s is in the map.  The map is the batch conjugate
-posterior of all observations (Thm. 1; Eq. (1)-(2) with unit weights), so
+over all voxels v of the map (y_v the ground-truth class; a voxel whose label
+is outside [0, K) contributes no cross-entropy term, but still counts in
+1/|V|) and the M' surface samples s whose voxel v_s is in the map.  The map is
+the batch conjugate posterior of all observations (Thm. 1; Eq. (1)-(2) with
+unit weights), so
 
     c_vi = sum over observations j of v of softmax(l_j)_i
     D_v  = (sum over observations j of v of tsdf_j) / W_v
@@ -76,10 +78,15 @@ def map_loss(ex, y, samples, voxel_size, alpha0=1.0):
     M, K = c.shape
     y = np.asarray(y, np.int64)
     tot = K * alpha0 + c.sum(axis=1)
-    cy = c[np.arange(M), y]
-    ce = -np.log((alpha0 + cy) / tot)
+    # a ground-truth label outside [0, K) adds no cross-entropy term and no
+    # dL/dc; the mean still runs over all M listed voxels
+    ok = (y >= 0) & (y < K)
+    yy = np.where(ok, y, 0)
+    cy = c[np.arange(M), yy]
+    ce = np.where(ok, -np.log((alpha0 + cy) / tot), 0.0)
     adj_c = np.repeat((1.0 / tot)[:, None], K, axis=1)
-    adj_c[np.arange(M), y] -= 1.0 / (alpha0 + cy)
+    adj_c[np.arange(M), yy] -= 1.0 / (alpha0 + cy)
+    adj_c[~ok] = 0.0
     adj_c /= M
     idx = KeyIndex(ex["keys"]).find(sample_keys(samples, voxel_size))
     valid = idx >= 0

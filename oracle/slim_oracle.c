@@ -272,7 +272,11 @@ static int band_walk(float vs, int maxsteps, const float o[3], const float u[3],
     float tmax[3], tdel[3];
     for (int a = 0; a < 3; ++a) {
         float s = fmaf(t0, u[a], o[a]);
-        c[a] = (int32_t)floorf(s / vs);
+        float fc = floorf(s / vs);
+        /* a start cell 2^30 or more cells out is far outside the key range;
+         * it is held there (no integer overflow) and the point is rejected */
+        if (!(fabsf(fc) < 1073741824.0f)) fc = fc < 0.0f ? -1073741824.0f : 1073741824.0f;
+        c[a] = (int32_t)fc;
         if (u[a] > 0.0f) {
             step[a] = 1;
             tmax[a] = t0 + fmaf((float)(c[a] + 1), vs, -s) / u[a];

@@ -164,8 +164,6 @@ slim_status validate_config(const slim_map_config *c)
         return fail(SLIM_ERR_UNSUPPORTED, "sdf_trunc above 6 voxel sizes is not supported");
     if (!(c->min_range >= 0.0f) || !(c->max_range > c->min_range) || !std::isfinite(c->max_range))
         return fail(SLIM_ERR_INVALID, "need 0 <= min_range < max_range < inf");
-    if ((double)c->max_range / (double)c->voxel_size >= (double)(1 << 19))
-        return fail(SLIM_ERR_INVALID, "max_range must be below 2^19 voxel sizes");
     if (c->sem_mode == SLIM_SEM_CLOSED || c->sem_mode == SLIM_SEM_CLOSED_LAST) {
         if (c->num_classes < 1 || c->num_classes > 256) return fail(SLIM_ERR_INVALID, "num_classes must be 1..256");
     } else if (c->sem_mode == SLIM_SEM_OPEN || c->sem_mode == SLIM_SEM_OPEN_LAST) {
@@ -381,12 +379,14 @@ slim_status make_frame(slim_map *m, const float *points, const float *ranges, co
     if (((uintptr_t)sem & (kind == SLIM_IN_EMB_BF16 ? 1u : 3u)) != 0)
         return fail(SLIM_ERR_INVALID, "semantic input is misaligned");
 
+    // anchor voxel of the sensor origin; an origin 2^20 or more voxels out is
+    // anchored at +2^20, where every point whose walk leaves |k| < 2^20 is
+    // rejected on its own
     const double vsd = (double)c.voxel_size;
     for (int r = 0; r < 3; ++r) {
         const double ta = pose[4 * r + 3];
-        const double q = std::floor(ta / vsd);
-        if (!(std::fabs(q) < (double)(1 << 19)))
-            return fail(SLIM_ERR_INVALID, "pose translation beyond 2^19 voxel sizes");
+        double q = std::floor(ta / vsd);
+        if (!(std::fabs(q) < (double)kKeyLimit)) q = (double)kKeyLimit;
         fp->a[r] = (int)q;
         fp->t[r] = (float)(ta - (double)fp->a[r] * vsd);
         for (int k = 0; k < 3; ++k) fp->R[3 * r + k] = (float)pose[4 * r + k];

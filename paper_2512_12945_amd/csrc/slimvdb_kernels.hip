@@ -168,13 +168,21 @@ struct WalkState {
     float tm[3], td[3];
 };
 
-__device__ __forceinline__ void walk_start(const FrameParams &fp, const Ray &ry, WalkState &w)
+// Returns false when a start cell lies 2^30 or more cells from the anchor: its
+// key is then outside |k| < 2^20 whatever the anchor, so the point is rejected
+// (and the cell index never overflows an int while the walk steps on).
+constexpr float kCellLimit = 1073741824.0f;  // 2^30
+
+__device__ __forceinline__ bool walk_start(const FrameParams &fp, const Ray &ry, WalkState &w)
 {
     const float vs = fp.vs, t0 = ry.t0;
+    bool ok = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float s = fmaf(t0, ry.u[a], fp.t[a]);
-        w.c[a] = (int)floorf(s / vs);
+        const float fc = floorf(s / vs);
+        ok = ok && fabsf(fc) < kCellLimit;
+        w.c[a] = fabsf(fc) < kCellLimit ? (int)fc : 0;
         if (ry.u[a] > 0.0f) {
             w.stp[a] = 1;
             w.tm[a] = t0 + fmaf((float)(w.c[a] + 1), vs, -s) / ry.u[a];
@@ -189,6 +197,7 @@ __device__ __forceinline__ void walk_start(const FrameParams &fp, const Ray &ry,
             w.td[a] = INFINITY;
         }
     }
+    return ok;
 }
 
 // Axis of the next step (ties step the lowest axis) and the ray parameter of
@@ -218,10 +227,10 @@ __device__ __forceinline__ void walk_step(WalkState &w, int ax)
 // axes step the lowest axis first, one axis per step; the walk stops when the
 // next boundary lies beyond t1, or after maxsteps cells.
 template <class Visit>
-__device__ __forceinline__ void band_walk(const FrameParams &fp, const Ray &ry, Visit &&visit)
+__device__ __forceinline__ bool band_walk(const FrameParams &fp, const Ray &ry, Visit &&visit)
 {
     WalkState w;
-    walk_start(fp, ry, w);
+    if (!walk_start(fp, ry, w)) return false;
     for (int it = 0; it < fp.maxsteps; ++it) {
         visit(w.c[0], w.c[1], w.c[2]);
         float tnext;
@@ -229,6 +238,7 @@ __device__ __forceinline__ void band_walk(const FrameParams &fp, const Ray &ry, 
         if (tnext > ry.t1) break;
         walk_step(w, ax);
     }
+    return true;
 }
 
 // Signed distance (binary32) of a cell centre to the point along the ray;
@@ -368,15 +378,14 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
     int nvis = 0;
     unsigned long long steps[2] = {0ull, 0ull}, kept = 0ull;
     if (valid) {
-        bool inrange = true;
         unsigned long long cur = kEmptyKey;
         uint32_t clen = 0, cslab = 0;
         WalkState w;
-        walk_start(fp, ry, w);
+        bool inrange = walk_start(fp, ry, w);
         c0[0] = w.c[0];
         c0[1] = w.c[1];
         c0[2] = w.c[2];
-        for (int it = 0; it < fp.maxsteps; ++it) {
+        for (int it = 0; it < (inrange ? fp.maxsteps : 0); ++it) {
             const int kx = fp.a[0] + w.c[0], ky = fp.a[1] + w.c[1], kz = fp.a[2] + w.c[2];
             if (!(key_ok(kx) && key_ok(ky) && key_ok(kz))) {
                 inrange = false;
@@ -1873,7 +1882,6 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
                                                 uint32_t blk, uint32_t nblk)
 {
     const DevState *st = md.st;
-    const uint32_t nt = md.fs->n_touched.v;
     const uint32_t nbig = min(md.fs->work_big.v, md.work_cap);
     const unsigned long long lused = st->leaves_used;
     const bool ok = md.fs->frame_err.v == 0 && st->pass_failed == 0 &&
@@ -2323,11 +2331,19 @@ __device__ __forceinline__ float block_sum(float v, float *red)
     return r;
 }
 
+// Clears the sample counts and the adjoints of every record in use, so that a
+// voxel the loss does not list (or lists with a label outside [0, K)) carries
+// zero adjoints into the backward.
 __global__ __launch_bounds__(256) void k_loss_clear(MapDev md, LossParams lp)
 {
     const size_t n = (size_t)md.st->pages_used * kPageVoxels;
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        lp.adj_cnt[i] = 0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += stride) lp.adj_cnt[i] = 0;
+    // adj_stride is a multiple of 4 floats
+    float4 *a4 = (float4 *)lp.adj;
+    const size_t n4 = n * (size_t)(lp.adj_stride / 4);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += stride)
+        a4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // Surface samples: per voxel count (integer, so order-free) and block partials
@@ -2372,15 +2388,19 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_voxels(FrameParams fp, Ma
     if (i < lp.m) {
         const long long rec = voxel_record(md, lp.keys[3 * i], lp.keys[3 * i + 1], lp.keys[3 * i + 2]);
         const int y = lp.labels[i];
-        if (rec >= 0 && y >= 0 && y < K) {
+        if (rec >= 0) {
             const float *R = md.vox + (size_t)rec * md.rec_stride;
-            float tot = (float)K * lp.alpha0;
-            for (int k = 0; k < K; ++k) tot += R[2 + k];
-            const float ay = lp.alpha0 + R[2 + y];
-            ce = -logf(ay / tot);
             float *A = lp.adj + (size_t)rec * lp.adj_stride;
-            const float g = inv_m / tot;
-            for (int k = 0; k < K; ++k) A[k] = k == y ? g - inv_m / ay : g;
+            // a label outside [0, K) adds no cross-entropy term (dL/dc = 0);
+            // the voxel's surface samples still count
+            if (y >= 0 && y < K) {
+                float tot = (float)K * lp.alpha0;
+                for (int k = 0; k < K; ++k) tot += R[2 + k];
+                const float ay = lp.alpha0 + R[2 + y];
+                ce = -logf(ay / tot);
+                const float g = inv_m / tot;
+                for (int k = 0; k < K; ++k) A[k] = k == y ? g - inv_m / ay : g;
+            }
             const float D = R[0];
             const float sg = D > 0.0f ? 1.0f : (D < 0.0f ? -1.0f : 0.0f);
             A[K] = sg * (float)lp.adj_cnt[rec] * inv_mp;
@@ -2439,7 +2459,7 @@ __global__ __launch_bounds__(256) void k_backward_rays(FrameParams fp, MapDev md
         bool inrange = true;
         unsigned long long cur = kEmptyKey;
         int slot = -1;
-        band_walk(fp, ry, [&](int cx, int cy, int cz) {
+        const bool started = band_walk(fp, ry, [&](int cx, int cy, int cz) {
             const int kx = fp.a[0] + cx, ky = fp.a[1] + cy, kz = fp.a[2] + cz;
             if (!(key_ok(kx) && key_ok(ky) && key_ok(kz))) {
                 inrange = false;
@@ -2461,9 +2481,11 @@ __global__ __launch_bounds__(256) void k_backward_rays(FrameParams fp, MapDev md
 #pragma unroll
             for (int k = 0; k < KMAX; ++k)
                 if (k < K) G[k] += A[k];
-            if (sdf < fp.tau) gr += A[K] / md.vox[(size_t)rec * md.rec_stride + 1];
+            // a voxel no loss sample landed in has a zero adjoint (and may be an
+            // unobserved record of an observed slab, W = 0)
+            if (sdf < fp.tau && A[K] != 0.0f) gr += A[K] / md.vox[(size_t)rec * md.rec_stride + 1];
         });
-        valid = inrange;
+        valid = started && inrange;
     }
     const float sc = grad_scale ? grad_scale[0] : 1.0f;
     float l[KMAX];
@@ -2866,10 +2888,13 @@ __global__ __launch_bounds__(256) void k_render(const MapDev md, const RenderPar
         const float vs = rp.vs, t0 = rp.t0, h = 0.5f * vs;
         int c[3], stp[3];
         float tm[3], td[3];
+        bool start_ok = true;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const float s = fmaf(t0, u[a], rp.t[a]);
-            c[a] = (int)floorf(s / vs);
+            const float fc = floorf(s / vs);
+            start_ok = start_ok && fabsf(fc) < kCellLimit;
+            c[a] = fabsf(fc) < kCellLimit ? (int)fc : 0;
             if (u[a] > 0.0f) {
                 stp[a] = 1;
                 tm[a] = t0 + fmaf((float)(c[a] + 1), vs, -s) / u[a];
@@ -2888,7 +2913,7 @@ __global__ __launch_bounds__(256) void k_render(const MapDev md, const RenderPar
         int slot = -1;
         bool have_prev = false;
         float Dp = 0.0f, sp = 0.0f;
-        for (int it = 0; it < rp.maxsteps; ++it) {
+        for (int it = 0; it < (start_ok ? rp.maxsteps : 0); ++it) {
             const int kx = rp.a[0] + c[0], ky = rp.a[1] + c[1], kz = rp.a[2] + c[2];
             if (!(key_ok(kx) && key_ok(ky) && key_ok(kz))) break;
             const unsigned long long lk = pack_leaf(kx >> 3, ky >> 3, kz >> 3);

@@ -395,6 +395,17 @@ def primitive_embeddings(scene, prim, L, seed, t, noise=0.1):
     return to_bf16_bits(z)
 
 
+def batched_draws(seed=4, nmaps=32, n_lo=10_000, n_hi=130_000):
+    """(trajectory index t, ray count n) of each map of the many-map workload."""
+    rng = _rng(seed, 9)
+    draws = []
+    for _ in range(nmaps):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        t = int(rng.integers(0, 100))
+        draws.append((t, n))
+    return draws
+
+
 def batched_workload(seed=4, nmaps=32, n_lo=10_000, n_hi=130_000, closed_maps=16, K=20, L=256, beams=128,
                      workers=1):
     """Many independent maps, one frame each: the first n_i rays (azimuth-major)
@@ -402,12 +413,7 @@ def batched_workload(seed=4, nmaps=32, n_lo=10_000, n_hi=130_000, closed_maps=16
     in [n_lo, n_hi].  Maps below `closed_maps` get int32 labels (K classes), the
     others bf16 embeddings of size L.  Returns a list of dicts (kind, frame)."""
     scene = StreetScene(seed=2, beams=beams)
-    rng = _rng(seed, 9)
-    draws = []
-    for i in range(nmaps):
-        n = int(rng.integers(n_lo, n_hi + 1))
-        t = int(rng.integers(0, 100))
-        draws.append((t, n))
+    draws = batched_draws(seed, nmaps, n_lo, n_hi)
     if workers > 1 and nmaps >= 4:
         import concurrent.futures as cf
         import multiprocessing as mp
@@ -500,7 +506,9 @@ class OpenRoomScene:
         ok = (depth >= self.depth_range[0]) & (depth <= self.depth_range[1])
         pts = (self.rays_c * depth[:, None]).astype(np.float32)
         pts[~ok] = np.nan
-        out = dict(points=pts, pose=pose, obj=obj.astype(np.int32))
+        # the depth image (z along the optical axis, NaN where invalid)
+        dimg = np.where(ok, depth, np.nan).astype(np.float32).reshape(self.height, self.width)
+        out = dict(points=pts, pose=pose, obj=obj.astype(np.int32), depth=dimg)
         if with_embeddings:
             # row blocks keep the temporaries small; the normal draws continue
             # one stream across blocks, so the result equals one whole-frame draw

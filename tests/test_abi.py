@@ -46,7 +46,7 @@ def _cfg(**kw):
     (dict(sdf_trunc=0.7), sv.ERR_UNSUPPORTED),
     (dict(min_range=-1.0), sv.ERR_INVALID),
     (dict(max_range=0.0), sv.ERR_INVALID),
-    (dict(max_range=1e6), sv.ERR_INVALID),
+    (dict(max_range=float("inf")), sv.ERR_INVALID),
     (dict(sem_mode=7), sv.ERR_INVALID),
     (dict(sem_mode=5), sv.ERR_INVALID),
     (dict(sem_mode=sv.SEM_CLOSED_LAST, num_classes=0), sv.ERR_INVALID),

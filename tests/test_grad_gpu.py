@@ -30,17 +30,20 @@ def setup():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     sv.load()
+    # the differentiation workload as stated: 16 sweeps of 65,536 rays with
+    # 20-class logits, 10k surface samples
     sc = synth.StreetScene(seed=2)
-    frames = [sc.ray_sweep(t) for t in range(3)]
+    frames = [sc.ray_sweep(t) for t in range(16)]
     om = oracle.OracleMap(VS, TAU, 0.0, 50.0, oracle.SEM_CLOSED, K)
     for fr in frames:
         om.integrate(ol.rays_to_points(fr["ranges"], fr["dirs"]), fr["pose"], fr["logits"], oracle.IN_LOGIT_F32)
     ex = om.extract()
     y = sc.nearest_class((ex["keys"] + 0.5) * np.float64(np.float32(VS)))
-    samples = sc.surface_samples(frames, count=3000)
+    samples = sc.surface_samples(frames, count=10000)
     lo = ol.map_loss(ex, y, samples, VS)
-    grads = [ol.frame_gradients(om, fr, ex, lo)[:2] for fr in frames]
-    return frames, ex, y, samples, lo, grads
+    index = ol.KeyIndex(ex["keys"])
+    grads = [ol.frame_gradients(om, fr, ex, lo, index)[:2] for fr in frames]
+    return frames, ex, y, samples, lo, grads, om
 
 
 def _run(frames, ex, y, samples, gmap):
@@ -55,8 +58,8 @@ def _run(frames, ex, y, samples, gmap):
 
 
 def test_loss_and_gradients_match_oracle(setup):
-    frames, ex, y, samples, lo, grads = setup
-    _say(f"3 ray sweeps, {lo['M']} voxels, {lo['Mp']} samples in the map")
+    frames, ex, y, samples, lo, grads, _ = setup
+    _say(f"{len(frames)} ray sweeps, {lo['M']} voxels, {lo['Mp']} samples in the map")
     gmap = sv.Map(VS, TAU, 0.0, 50.0, sv.SEM_CLOSED, K, 0, 0, 1 << 16, 1 << 22)
     loss, gr, gl = _run(frames, ex, y, samples, gmap)
     gx = extract_np(gmap)
@@ -75,9 +78,37 @@ def test_loss_and_gradients_match_oracle(setup):
 
 
 def test_backward_is_deterministic(setup):
-    frames, ex, y, samples, lo, grads = setup
+    frames, ex, y, samples, lo, grads, _ = setup
     gmap = sv.Map(VS, TAU, 0.0, 50.0, sv.SEM_CLOSED, K, 0, 0, 1 << 16, 1 << 22)
     a = _run(frames, ex, y, samples, gmap)
     b = _run(frames, ex, y, samples, gmap)
     assert float(a[0]) == float(b[0])
     assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_labels_outside_classes_are_skipped(setup):
+    """Ground-truth labels outside [0, K) add no cross-entropy term and no
+    dL/dc (the mean still counts them); the adjoint buffers are cleared, so a
+    second loss on the same map with other labels leaves no stale adjoint."""
+    frames, ex, y, samples, lo, grads, om = setup
+    frames = frames[:2]
+    o2 = oracle.OracleMap(VS, TAU, 0.0, 50.0, oracle.SEM_CLOSED, K)
+    for fr in frames:
+        o2.integrate(ol.rays_to_points(fr["ranges"], fr["dirs"]), fr["pose"], fr["logits"], oracle.IN_LOGIT_F32)
+    ex2 = o2.extract()
+    rng = np.random.default_rng(3)
+    y2 = synth.StreetScene(seed=2).nearest_class((ex2["keys"] + 0.5) * np.float64(np.float32(VS)))
+    bad = rng.random(len(y2)) < 0.2
+    y2 = np.where(bad, np.where(rng.random(len(y2)) < 0.5, -1, K), y2).astype(np.int32)
+    lo2 = ol.map_loss(ex2, y2, samples, VS)
+    gmap = sv.Map(VS, TAU, 0.0, 50.0, sv.SEM_CLOSED, K, 0, 0, 1 << 16, 1 << 22)
+    # a first loss with valid labels leaves adjoints in every listed voxel
+    _run(frames, ex2, np.clip(y2, 0, K - 1), samples, gmap)
+    loss, gr, gl = _run(frames, ex2, y2, samples, gmap)
+    _say(f"  {int(bad.sum())} of {len(y2)} labels outside [0, {K}); loss gpu {float(loss):.9g} oracle {lo2['loss']:.9g}")
+    assert abs(float(loss) - lo2["loss"]) / lo2["loss"] < 1e-5
+    for f, fr in enumerate(frames):
+        g_logit, g_r, _ = ol.frame_gradients(o2, fr, ex2, lo2)
+        sl, sr = np.abs(g_logit).max(), np.abs(g_r).max()
+        assert (np.abs(gl[f] - g_logit) / (np.abs(g_logit) + sl)).max() < 1e-5
+        assert (np.abs(gr[f] - g_r) / (np.abs(g_r) + sr)).max() < 1e-5
