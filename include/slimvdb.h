@@ -166,6 +166,22 @@ slim_status slim_map_stats(slim_map *map, slim_stats *out_host, void *stream);
 slim_status slim_extract(slim_map *map, int64_t capacity, int32_t *keys_dev, float *d_dev, float *w_dev,
                          float *sem_dev, int64_t *count_host, void *stream);
 
+/* Maximum leaves of a map that slim_extract_noalloc exports. */
+#define SLIM_EXTRACT_NOALLOC_MAX_LEAVES (1LL << 20)
+
+/* As slim_extract, for callers that cannot allocate device memory (code around
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, outputs and errors, and it calls no hipMalloc, hipFree or
+ * other allocating routine.  Its per-leaf scratch (16 bytes a leaf) is a
+ * fixed device array of the library of 16 MiB, one per GPU, held until the
+ * process ends; a map with more than SLIM_EXTRACT_NOALLOC_MAX_LEAVES leaves is
+ * refused with SLIM_ERR_CAPACITY before anything is queued.  Every call on one
+ * GPU shares that array: calls that overlap on one GPU (several host threads,
+ * or streams not synchronised with each other) race and must not be made.
+ * Synchronises `stream` before returning, as slim_extract does. */
+slim_status slim_extract_noalloc(slim_map *map, int64_t capacity, int32_t *keys_dev, float *d_dev, float *w_dev,
+                                 float *sem_dev, int64_t *count_host, void *stream);
+
 /* Sparse querying of the map (Sec. III-A: the store gives fast querying; O(1)
  * lookup, Sec. II-C): looks up the voxels holding m world points xyz_dev (float [m x 3]),
  * voxel floor(x / voxel_size) in binary32, and writes their state: d_dev,

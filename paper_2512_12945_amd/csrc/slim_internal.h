@@ -250,6 +250,16 @@ constexpr int kLossThreads = 256;
 hipError_t launch_extract(const MapDev &md, int nsem, long long nleaves, unsigned long long *tmp_keys,
                           int32_t *tmp_slots, uint32_t *tmp_offsets, int32_t *keys, float *d, float *w, float *sem,
                           hipStream_t s);
+// Allocation-free extract: its per-leaf scratch (key 8 B, slot 4 B, voxel
+// offset 4 B) lives in a file-scope device array of the library, one copy per
+// GPU, for at most kNoAllocMaxLeaves leaves.
+constexpr long long kNoAllocMaxLeaves = 1ll << 20;
+constexpr int kNoAllocMaxDevices = 64;
+// With the device current, resolves that GPU's address of the array (once per
+// device; later calls return at once).
+hipError_t noalloc_scratch_setup(int device);
+// The address resolved for `device`, or nullptr if setup has not succeeded.
+void *noalloc_scratch(int device);
 // Semantic read-out (slim_predict).
 struct PredictParams {
     float vs, alpha0, inv_temp, threshold;

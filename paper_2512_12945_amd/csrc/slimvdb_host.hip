@@ -100,6 +100,7 @@ struct slim_map {
     int prof_head = 0, prof_count = 0;
     double prof_ms[kNumProfiled] = {};
     long long prof_n[kNumProfiled] = {};
+    hipError_t noalloc_err = hipSuccess;  // outcome of the scratch address setup at create
     // loss adjoints (allocated by the first slim_map_loss)
     float *adj = nullptr;
     int32_t *adj_cnt = nullptr;
@@ -315,6 +316,9 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
         delete m;
         return fail(SLIM_ERR_DEVICE, "map initialisation failed");
     }
+    // the device address of the allocation-free extract's scratch on this GPU
+    // (a failure here is reported by slim_extract_noalloc, not by create)
+    m->noalloc_err = noalloc_scratch_setup(config->device);
     *out = m;
     return SLIM_OK;
 }
@@ -768,6 +772,40 @@ slim_status slim_extract(slim_map *m, int64_t capacity, int32_t *keys, float *d,
     }
     HIP_OK(launch_extract(m->md, m->nsem, st.leaves, m->ext_keys, m->ext_slots, m->ext_offsets, keys, d, w,
                           m->nsem ? sem : nullptr, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return SLIM_OK;
+}
+
+slim_status slim_extract_noalloc(slim_map *m, int64_t capacity, int32_t *keys, float *d, float *w, float *sem,
+                                 int64_t *count, void *stream)
+{
+    g_err[0] = 0;
+    if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
+    if (!count) return fail(SLIM_ERR_INVALID, "count is NULL");
+    slim_stats st;
+    slim_status r = slim_map_stats(m, &st, stream);
+    if (r) return r;
+    *count = st.voxels;
+    if (capacity == 0) return SLIM_OK;
+    if (capacity < st.voxels) return fail(SLIM_ERR_INVALID, "capacity %lld < voxel count %lld",
+                                          (long long)capacity, (long long)st.voxels);
+    if (st.voxels > 0 && (!keys || !d || !w)) return fail(SLIM_ERR_INVALID, "output pointer is NULL");
+    if (st.leaves > kNoAllocMaxLeaves)
+        return fail(SLIM_ERR_CAPACITY, "the map has %lld leaves; slim_extract_noalloc handles at most %lld",
+                    (long long)st.leaves, kNoAllocMaxLeaves);
+    if (m->noalloc_err != hipSuccess)
+        return fail(SLIM_ERR_DEVICE, "scratch address of device %d unavailable: %s", m->cfg.device,
+                    hipGetErrorString(m->noalloc_err));
+    void *ptr = noalloc_scratch(m->cfg.device);
+    if (!ptr) return fail(SLIM_ERR_DEVICE, "scratch address of device %d unavailable", m->cfg.device);
+    DeviceGuard g(m->cfg.device);
+    hipStream_t s = (hipStream_t)stream;
+    // keys, slots and offsets of the leaves, each array sized for the maximum;
+    // every entry the kernels read is written first by this call
+    unsigned long long *tk = (unsigned long long *)ptr;
+    int32_t *ts = (int32_t *)(tk + kNoAllocMaxLeaves);
+    uint32_t *to = (uint32_t *)(ts + kNoAllocMaxLeaves);
+    HIP_OK(launch_extract(m->md, m->nsem, st.leaves, tk, ts, to, keys, d, w, m->nsem ? sem : nullptr, s));
     HIP_OK(hipStreamSynchronize(s));
     return SLIM_OK;
 }

@@ -30,6 +30,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "slim_internal.h"
 #include "slimvdb.h"
 
@@ -2695,6 +2697,38 @@ hipError_t launch_extract(const MapDev &md, int nsem, long long nleaves, unsigne
     hipLaunchKernelGGL(k_extract, dim3((unsigned)std::min<long long>(nleaves, 8192)), dim3(256), 0, s, md, nleaves,
                        nsem, tmp_slots, tmp_offsets, keys, d, w, sem);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free extract (slim_extract_noalloc): the leaves'
+// keys, then their slots, then their voxel offsets, for at most
+// kNoAllocMaxLeaves leaves.  Each GPU the library runs on holds its own copy
+// until the process ends.  In host code `scratch` names a host-side stand-in:
+// kernels get the device address that noalloc_scratch_setup resolved.
+static __device__ __align__(256) unsigned char scratch[kNoAllocMaxLeaves * 16];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kNoAllocMaxDevices];
+}  // namespace
+
+hipError_t noalloc_scratch_setup(int device)
+{
+    if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kNoAllocMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 // Record of the voxel holding world point (x, y, z), floor(x / vs) in binary32;

@@ -22,7 +22,7 @@ KERNELS = ("ray_walk_emit", "leaf_plan", "pair_bucket", "leaf_fuse", "frame_comm
 
 EXPORTS = ("slim_map_create", "slim_map_destroy", "slim_map_reset", "slim_integrate", "slim_integrate_rays",
            "slim_integrate_depth",
-           "slim_map_stats", "slim_extract", "slim_query", "slim_predict", "slim_render", "slim_map_loss",
+           "slim_map_stats", "slim_extract", "slim_extract_noalloc", "slim_query", "slim_predict", "slim_render", "slim_map_loss",
            "slim_backward_rays",
            "slim_integrate_batched", "slim_integrate_sequence", "slim_set_launch_shape", "slim_profile_enable",
            "slim_profile_read",
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
         L.slim_backward_rays.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.slim_map_stats.argtypes = [vp, ctypes.POINTER(Stats), vp]
         L.slim_extract.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
+        L.slim_extract_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.POINTER(i64), vp]
         L.slim_query.argtypes = [vp, vp, i64, vp, vp, vp, vp]
         L.slim_predict.argtypes = [vp, vp, i64, ctypes.POINTER(PredictParams), vp, vp, vp, vp]
         L.slim_render.argtypes = [vp, vp, vp, i32, i32, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]
@@ -217,18 +218,21 @@ class Map:
         _check(self._L.slim_map_stats(self.h, ctypes.byref(st), _stream(self.device)))
         return st.as_dict()
 
-    def extract(self):
-        """All voxels with W > 0 as cuda tensors: keys (M, 3) int32, D, W (M,), sem (M, S)."""
+    def extract(self, noalloc=False):
+        """All voxels with W > 0 as cuda tensors: keys (M, 3) int32, D, W (M,), sem (M, S).
+        noalloc: through slim_extract_noalloc (the library allocates nothing;
+        the output tensors are still allocated here, by torch)."""
+        fn = self._L.slim_extract_noalloc if noalloc else self._L.slim_extract
         cnt = ctypes.c_int64()
         s = _stream(self.device)
-        _check(self._L.slim_extract(self.h, 0, None, None, None, None, ctypes.byref(cnt), s))
+        _check(fn(self.h, 0, None, None, None, None, ctypes.byref(cnt), s))
         M = cnt.value
         keys = torch.empty((max(M, 1), 3), dtype=torch.int32, device=self.device)
         d = torch.empty(max(M, 1), dtype=torch.float32, device=self.device)
         w = torch.empty(max(M, 1), dtype=torch.float32, device=self.device)
         sem = torch.empty((max(M, 1), max(self.nsem, 1)), dtype=torch.float32, device=self.device)
-        _check(self._L.slim_extract(self.h, max(M, 1), _ptr(keys), _ptr(d), _ptr(w),
-                                    _ptr(sem) if self.nsem else None, ctypes.byref(cnt), s))
+        _check(fn(self.h, max(M, 1), _ptr(keys), _ptr(d), _ptr(w), _ptr(sem) if self.nsem else None,
+                  ctypes.byref(cnt), s))
         M = cnt.value
         return dict(keys=keys[:M], D=d[:M], W=w[:M], sem=sem[:M, : self.nsem])
 
