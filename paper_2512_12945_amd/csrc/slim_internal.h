@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "slimvdb.h"
+
 namespace slim {
 
 constexpr uint64_t kEmptyKey = ~0ull;        // free slot of a leaf table
@@ -26,6 +28,8 @@ constexpr int kLeafThreads = 256;
 constexpr int kLeafBatch = 8;                // loads in flight per thread in the leaf kernel
 constexpr int kLeafLdsPairs = kLeafBatch * kLeafThreads;  // pairs a leaf holds in LDS at once
 constexpr int kNumProfiled = 5;
+constexpr int kAccFrames = 4;        // frames of a pass the accumulating leaf kernel takes
+constexpr int kAccWavePairs = 128;   // accumulated leaves with at most this many pairs are one wave's work
 constexpr int kPassFrames = 8;               // most frames integrated in one pass
 constexpr int kMaxLeafBlocksPerCu = 32;
 
@@ -98,6 +102,15 @@ struct FrameParams {
     uint32_t sub_start[kPassFrames + 1];  // offset of each frame of the pass, then the pass's total
     const void *sub_sem[kPassFrames];     // per-point semantics of each frame of the pass
 };
+
+// Frames whose voxels only gain integers (counts, class counts of int32 labels
+// with K <= 32, fixed-point distance sums): their leaves are accumulated in any
+// order, without sorting, and several such frames can share one pass.
+__host__ __device__ inline bool accum_path(const FrameParams &fp)
+{
+    if (fp.last || fp.L > 0) return false;
+    return fp.K == 0 || (fp.K <= 32 && fp.sem_kind == SLIM_IN_LABEL_I32);
+}
 
 // The walk of a multi-frame pass: each frame's rays, one block range per frame.
 struct PassWalk {

@@ -523,12 +523,6 @@ slim_status integrate_overlapped(slim_map *m, const std::vector<FrameParams> &fp
 
 // Frames a multi-frame pass can take: geometry, or int32 labels with at most
 // 32 classes, Bayesian mode.
-bool pass_kind(const FrameParams &fp)
-{
-    if (fp.last || fp.L > 0) return false;
-    if (fp.K == 0) return true;
-    return fp.sem_kind == SLIM_IN_LABEL_I32 && fp.K <= 32;
-}
 
 // The pass of frames [t0, t1): its walk (each frame's rays, point indices
 // offset per frame so that every observation key stays distinct and
@@ -573,7 +567,8 @@ slim_status integrate_passes(slim_map *m, const std::vector<FrameParams> &fps, h
     for (int t = 0; t < count;) {
         int t1 = t + 1;
         int64_t tot = fps[t].n;
-        while (t < count - 1 && t1 < count - 1 && t1 - t < m->pass_frames && fps[t1].sem_kind == fps[t].sem_kind &&
+        while (t < count - 1 && t1 < count - 1 && t1 - t < std::min(m->pass_frames, kAccFrames) &&
+               fps[t1].sem_kind == fps[t].sem_kind &&
                tot + fps[t1].n < kMaxPoints) {
             tot += fps[t1].n;
             ++t1;
@@ -650,7 +645,7 @@ slim_status slim_integrate_sequence(slim_map *m, const slim_frame *frames, int32
     if (count == 1) return integrate_frame(m, fps[0], stream);
     if (m->pass_frames > 1 && count > 2) {
         bool all = true;
-        for (int i = 0; i < count && all; ++i) all = pass_kind(fps[i]);
+        for (int i = 0; i < count && all; ++i) all = accum_path(fps[i]);
         if (all) return integrate_passes(m, fps, s);
     }
     return integrate_overlapped(m, fps, 0, count, s);

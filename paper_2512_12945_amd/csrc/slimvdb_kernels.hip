@@ -11,18 +11,24 @@
 //                     it as new), number record pages for newly touched 8x8
 //                     slabs, allocate its pair bucket.
 //   3. pair_bucket    one lane per pair: scatter into its leaf's bucket.
-//   4. leaf_fuse      one workgroup per touched leaf: counting sort of the
-//                     bucket by voxel offset in LDS, then by point index inside
-//                     each voxel, and the conjugate combine of every touched
-//                     voxel in point order -- Eq. (1)-(2) for D and W, Eq. (6)
-//                     for the class counts, Eqs. (11)-(14) with
-//                     lambda = 2 nu = W for the open-set mean and beta.
+//   4. leaf_acc       geometry and int32 labels (K <= 32): one workgroup per
+//                     touched leaf (or one wave per small leaf) adds every pair
+//                     into its voxel's LDS accumulators with integer atomics --
+//                     observation counts, class counts, fixed-point distance
+//                     sums -- and one lane per touched voxel applies them, Eq.
+//                     (1)-(2) for D and W and Eq. (6) for the class counts.
+//      leaf_fuse      probability or logit rows, the open set, the most-recent
+//                     modes: counting sort of the bucket by voxel offset in LDS,
+//                     then by point index inside each voxel, and the combine of
+//                     every touched voxel in point order (the open set's Eqs.
+//                     (11)-(14) with lambda = 2 nu = W in k_voxel_combine).
 //   5. frame_commit   one workgroup: counters, status, frame reset.
 // Kernels 1-3 only read the map, and kernel 4 writes it only if the frame's new
 // leaves and record pages fit (decided from totals that kernel 2 completed), so
 // a frame that does not fit changes nothing.  No floating-point atomics are
-// used: each voxel's sums are formed in point order, so results are bitwise
-// repeatable and independent of launch shapes.
+// used: integer sums are exact in any order and every floating-point sum runs
+// in point order, so results are bitwise repeatable and independent of launch
+// shapes.
 //
 // The geometric decision path (pose, ray, walk, gate) is a fixed sequence of
 // binary32 operations; build with -ffp-contract=off so that only the fmaf()
@@ -601,8 +607,14 @@ __device__ __forceinline__ int32_t point_label(const FrameParams &fp, uint32_t p
 // 2. leaf planning
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, uint32_t nblk)
+__device__ __forceinline__ void leaf_plan_range(const FrameParams &fp, const MapDev &md, uint32_t blk, uint32_t nblk)
 {
+    // work lists: the sorting leaf kernel splits a leaf with more pairs than
+    // LDS holds into x-slab items and gives a wave leaves of up to
+    // kWaveItemPairs pairs; the accumulating one takes every leaf whole
+    const bool acc = accum_path(fp);
+    const uint32_t big_lim = acc ? 0xFFFFFFFFu : (uint32_t)kLeafLdsPairs;
+    const uint32_t small_lim = acc ? (uint32_t)kAccWavePairs : (uint32_t)kWaveItemPairs;
     const uint32_t nt = md.fs->n_touched.v;
     const unsigned long long pused = md.st->pages_used;
     const uint32_t stride = nblk * blockDim.x;
@@ -637,14 +649,14 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
         // a leaf with more pairs than the leaf kernel holds in LDS becomes one
         // work item per touched x-slab
         const uint32_t tslabs = act ? md.pos_slab[pos] & 0xFFu : 0u;
-        const bool big = act && npairs > (uint32_t)kLeafLdsPairs;
+        const bool big = act && npairs > big_lim;
         // the other leaves: one workgroup each, or one wave each if small
-        const bool small = act && npairs <= (uint32_t)kWaveItemPairs;
+        const bool small = act && npairs <= small_lim;
         const bool med = act && !big && !small;
         // the larger workgroup and wave leaves are listed from the front of
         // their arrays, the smaller ones from the back
         const bool medf = med && npairs > (uint32_t)kLeafLdsPairs / 2, medb = med && !medf;
-        const bool smallf = small && npairs > (uint32_t)kWaveItemPairs / 4, smallb = small && !smallf;
+        const bool smallf = small && npairs > small_lim / 4, smallb = small && !smallf;
         // eight reservations with six atomics in flight together (two list
         // counters share each 64-bit word)
         const uint32_t want[4] = {(act && slot < 0) ? 1u : 0u, (uint32_t)__popc(need), npairs,
@@ -715,14 +727,14 @@ __device__ __forceinline__ void leaf_plan_range(const MapDev &md, uint32_t blk, 
     }
 }
 
-__global__ __launch_bounds__(256) void k_leaf_plan(MapDev md)
+__global__ __launch_bounds__(256) void k_leaf_plan(FrameParams fp, MapDev md)
 {
-    leaf_plan_range(md, blockIdx.x, gridDim.x);
+    leaf_plan_range(fp, md, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void k_leaf_plan_batch(MapBatch mb)
 {
-    for (int i = 0; i < mb.nmaps; ++i) leaf_plan_range(mb.mds[i], blockIdx.x, gridDim.x);
+    for (int i = 0; i < mb.nmaps; ++i) leaf_plan_range(mb.fps[i], mb.mds[i], blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -798,133 +810,52 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Eq. (1)-(2) with unit weights: the frame's n truncated distances are summed
-// in point order in binary64 (a voxel can gather thousands), and the running
-// mean is formed in binary64 before rounding to the stored binary32.
-__device__ __forceinline__ double tsdf_sum(const float *vals, uint32_t n)
+// Eq. (1)-(2) with unit weights.  Each truncated distance is taken as the
+// fixed-point integer q = rint(tsdf 2^k), where 2^k is the largest power of two
+// with tau 2^k <= 2^40, and a frame's q are summed in 64-bit integers: the sum
+// is exact, so it does not depend on the order of the observations, and it
+// differs from the real sum of the distances by at most n 2^-(k+1) (n
+// observations: 2^-42 tau each), far inside the tolerance.  The running mean
+// is formed in binary64 and rounded once to the stored binary32.
+struct FixScale {
+    float s;     // 2^k
+    double inv;  // 2^-k
+};
+
+__device__ __forceinline__ FixScale fix_scale(const FrameParams &fp)
 {
-    double sum_t = 0.0;
-    for (uint32_t q = 0; q < n; ++q) sum_t += (double)vals[q];
-    return sum_t;
+    int e;
+    (void)frexpf(fp.tau, &e);  // tau < 2^e
+    return {ldexpf(1.0f, 40 - e), ldexp(1.0, e - 40)};
 }
 
-__device__ __forceinline__ float tsdf_mean(float D0, float W0, float W1, double sum_t)
+__device__ __forceinline__ long long fix_q(float tsdf, float s) { return __float2ll_rn(tsdf * s); }
+
+__device__ __forceinline__ long long tsdf_sum(const float *vals, uint32_t n, float s)
 {
-    return (float)(((double)W0 * (double)D0 + sum_t) / (double)W1);
+    long long sum = 0;
+    for (uint32_t q = 0; q < n; ++q) sum += fix_q(vals[q], s);
+    return sum;
 }
 
-// One voxel of a multi-frame pass (geometry, or int32 labels): its
-// observations are ordered by frame, then by point, and each frame's run
-// updates the record exactly as that frame integrated alone would -- Eq.
-// (1)-(2) with the frame's binary64 sum and one rounding, Eq. (6) with the
-// frame's exact class counts -- so the pass equals the frames one by one.
-template <int KMAX>
-__device__ __forceinline__ void combine_lane_pass(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
-                                                  const float *vals, const int32_t *labs, uint32_t n, long long rec,
-                                                  bool existed)
+__device__ __forceinline__ float tsdf_mean(float D0, float W0, float W1, long long sum, double inv)
 {
-    constexpr int KA = KMAX > 0 ? KMAX : 1;
-    constexpr int NV = (2 + KMAX + 3) / 4;
-    constexpr int KW = (KA + 3) / 4;
-    const int nv = md.rec_stride / 4, K = fp.K;
-    float4 *R = (float4 *)(md.vox + (size_t)rec * md.rec_stride);
-    float r[4 * NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const float4 x = (existed && v < nv) ? R[v] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        r[4 * v + 0] = x.x;
-        r[4 * v + 1] = x.y;
-        r[4 * v + 2] = x.z;
-        r[4 * v + 3] = x.w;
-    }
-    uint32_t q = 0;
-    while (q < n) {
-        // the run of one frame: point indices below the next frame's offset;
-        // inside a voxel the keys ascend with the point index, so its end is
-        // found by bisection
-        const uint32_t end = fp.sub_start[pass_frame(fp, keys[q] & kPidMask) + 1];
-        uint32_t lo = q + 1, hi = n;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if ((keys[mid] & kPidMask) < end) lo = mid + 1;
-            else hi = mid;
-        }
-        const uint32_t qe = lo, m = qe - q;
-        const float W0 = r[1], W1 = W0 + (float)m;
-        // the run's distances (summed in point order in binary64) and, up to
-        // 255 observations, its class counts as 8-bit fields, read four at a
-        // time
-        const bool packed = KMAX > 0 && m <= 255u;
-        double sum_t = 0.0;
-        uint32_t cw[KW];
-#pragma unroll
-        for (int w = 0; w < KW; ++w) cw[w] = 0u;
-        for (uint32_t t0 = q; t0 < qe; t0 += 4) {
-            float v4[4];
-            int l4[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t t = t0 + u;
-                v4[u] = t < qe ? vals[t] : 0.0f;
-                l4[u] = (packed && t < qe) ? (labs ? labs[t] : point_label(fp, keys[t] & kPidMask)) : -1;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (t0 + u < qe) sum_t += (double)v4[u];
-            if (packed) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int wi = l4[u] >> 2;  // -1 for no observation
-                    const uint32_t inc = 1u << ((l4[u] & 3) << 3);
-#pragma unroll
-                    for (int w = 0; w < KW; ++w) cw[w] += (w == wi) ? inc : 0u;
-                }
-            }
-        }
-        r[0] = tsdf_mean(r[0], W0, W1, sum_t);
-        r[1] = W1;
-        if (KMAX > 0) {
-            if (packed) {
-#pragma unroll
-                for (int k = 0; k < KA; ++k)
-                    if (k < K) r[2 + k] += (float)((cw[k >> 2] >> ((k & 3) << 3)) & 0xFFu);
-            } else {
-#pragma unroll
-                for (int k = 0; k < KA; ++k) {
-                    if (k >= K) break;
-                    uint32_t c = 0;
-                    for (uint32_t t = q; t < qe; ++t)
-                        c += (labs ? labs[t] : point_label(fp, keys[t] & kPidMask)) == k ? 1u : 0u;
-                    r[2 + k] += (float)c;
-                }
-            }
-        }
-        q = qe;
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-        if (v < nv) R[v] = make_float4(r[4 * v + 0], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
+    return (float)(((double)W0 * (double)D0 + (double)sum * inv) / (double)W1);
 }
 
 // One voxel, one lane: its n observations sit at keys[0..n) / vals[0..n) in
-// point order.  Closed set with K <= KMAX classes in registers (KMAX = 0:
-// geometry only); ROWS: probability or logit rows, else int32 labels.  The
-// record moves as 16-byte vectors.
-template <int KMAX, bool ROWS>
+// point order.  Closed set with probability or logit rows and K <= KMAX
+// classes in registers.  The record moves as 16-byte vectors.
+template <int KMAX>
 __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
-                                             const float *vals, const int32_t *labs, uint32_t n, long long rec,
-                                             bool existed)
+                                             const float *vals, uint32_t n, long long rec, bool existed)
 {
-    if (!ROWS && fp.nsub > 1) {
-        combine_lane_pass<KMAX>(fp, md, keys, vals, labs, n, rec, existed);
-        return;
-    }
-    constexpr int KA = KMAX > 0 ? KMAX : 1;
+    static_assert(KMAX > 0, "rows of at least one class");
     constexpr int NV = (2 + KMAX + 3) / 4;
     const int nv = md.rec_stride / 4, K = fp.K;
-    // up to 24 classes (16 for rows) the record is requested first, so its
-    // round trip overlaps the counting (more would spill registers)
-    constexpr bool early = KMAX <= (ROWS ? 16 : 24);
+    // up to 16 classes the record is requested first, so its round trip
+    // overlaps the rows (more would spill registers)
+    constexpr bool early = KMAX <= 16;
     float4 *R = (float4 *)(md.vox + (size_t)rec * md.rec_stride);
     float r[4 * NV];
     auto load_record = [&]() {
@@ -938,85 +869,54 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
         }
     };
     if constexpr (early) load_record();
-    float acc[KA];
+    float acc[KMAX];
 #pragma unroll
-    for (int k = 0; k < KA; ++k) acc[k] = 0.0f;
-    if (KMAX > 0 && !ROWS) {
-        // class counts as 8-bit fields, four classes to a word, added into acc
-        // every 255 observations (exact integers either way, so acc holds the
-        // same values as a sum of ones)
-        constexpr int KW = (KA + 3) / 4;
-        for (uint32_t c0 = 0; c0 < n; c0 += 255u) {
-            const uint32_t c1 = min(n, c0 + 255u);
-            uint32_t cw[KW];
+    for (int k = 0; k < KMAX; ++k) acc[k] = 0.0f;
+    // the rows of RB observations are loaded before any is used (two up to 24
+    // classes; more would spill registers), then each is added in point order
+    constexpr int RB = KMAX <= 24 ? 2 : 1;
+    for (uint32_t t0 = 0; t0 < n; t0 += RB) {
+        float x[RB][KMAX];
 #pragma unroll
-            for (int w = 0; w < KW; ++w) cw[w] = 0u;
-            for (uint32_t q0 = c0; q0 < c1; q0 += 8) {
-                int lab[8];
+        for (int b = 0; b < RB; ++b) {
+            const bool has = t0 + b < n;
+            const float *row = (const float *)fp.sem + (size_t)(has ? keys[t0 + b] & kPidMask : 0u) * K;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const uint32_t t = q0 + q;
-                    lab[q] = t < c1 ? (labs ? labs[t] : point_label(fp, keys[t] & kPidMask)) : -1;
-                }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int wi = lab[q] >> 2;  // -1 for no observation
-                    const uint32_t inc = 1u << ((lab[q] & 3) << 3);
-#pragma unroll
-                    for (int w = 0; w < KW; ++w) cw[w] += (w == wi) ? inc : 0u;
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < KA; ++k) acc[k] += (float)((cw[k >> 2] >> ((k & 3) << 3)) & 0xFFu);
+            for (int k = 0; k < KMAX; ++k) x[b][k] = (has && k < K) ? row[k] : 0.0f;
         }
-    }
-    if constexpr (KMAX > 0 && ROWS) {
-        // the rows of RB observations are loaded before any is used (two up to
-        // 24 classes; more would spill registers), then each is added in
-        // point order
-        constexpr int RB = KMAX <= 24 ? 2 : 1;
-        for (uint32_t t0 = 0; t0 < n; t0 += RB) {
-            float x[RB][KA];
 #pragma unroll
-            for (int b = 0; b < RB; ++b) {
-                const bool has = t0 + b < n;
-                const float *row = (const float *)fp.sem + (size_t)(has ? keys[t0 + b] & kPidMask : 0u) * K;
+        for (int b = 0; b < RB; ++b) {
+            if (t0 + b < n) {
+                if (fp.sem_kind == SLIM_IN_LOGIT_F32) {
+                    // softmax of the logits, max-subtracted
+                    float mx = x[b][0];
 #pragma unroll
-                for (int k = 0; k < KA; ++k) x[b][k] = (has && k < K) ? row[k] : 0.0f;
-            }
+                    for (int k = 1; k < KMAX; ++k)
+                        if (k < K) mx = fmaxf(mx, x[b][k]);
+                    float den = 0.0f;
 #pragma unroll
-            for (int b = 0; b < RB; ++b) {
-                if (t0 + b < n) {
-                    if (fp.sem_kind == SLIM_IN_LOGIT_F32) {
-                        // softmax of the logits, max-subtracted
-                        float mx = x[b][0];
-#pragma unroll
-                        for (int k = 1; k < KA; ++k)
-                            if (k < K) mx = fmaxf(mx, x[b][k]);
-                        float den = 0.0f;
-#pragma unroll
-                        for (int k = 0; k < KA; ++k) {
-                            x[b][k] = k < K ? expf(x[b][k] - mx) : 0.0f;
-                            den += x[b][k];
-                        }
-#pragma unroll
-                        for (int k = 0; k < KA; ++k) x[b][k] = x[b][k] / den;
+                    for (int k = 0; k < KMAX; ++k) {
+                        x[b][k] = k < K ? expf(x[b][k] - mx) : 0.0f;
+                        den += x[b][k];
                     }
 #pragma unroll
-                    for (int k = 0; k < KA; ++k) acc[k] += x[b][k];
+                    for (int k = 0; k < KMAX; ++k) x[b][k] = x[b][k] / den;
                 }
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) acc[k] += x[b][k];
             }
         }
     }
     if constexpr (!early) load_record();
     // Eq. (1)-(2) with unit weights
     const float nf = (float)n, W0 = r[1], W1 = W0 + nf;
-    r[0] = tsdf_mean(r[0], W0, W1, tsdf_sum(vals, n));
+    const FixScale fx = fix_scale(fp);
+    r[0] = tsdf_mean(r[0], W0, W1, tsdf_sum(vals, n, fx.s), fx.inv);
     r[1] = W1;
-    // Eq. (6): concentrations grow by the (expected) class counts
+    // Eq. (6): concentrations grow by the expected class counts
 #pragma unroll
-    for (int k = 0; k < KA; ++k)
-        if (KMAX > 0 && k < K) r[2 + k] += acc[k];
+    for (int k = 0; k < KMAX; ++k)
+        if (k < K) r[2 + k] += acc[k];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
         if (v < nv) R[v] = make_float4(r[4 * v + 0], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
@@ -1105,8 +1005,9 @@ __device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const Ma
         s1[i] = 0.0f;
         s2[i] = 0.0f;
     }
-    // binary64 distance sum in point order (Eq. (1)-(2)), from the lanes
-    double sum_t = 0.0;
+    // fixed-point distance sum (Eq. (1)-(2)), from the lanes
+    const FixScale fx = fix_scale(fp);
+    long long sum_t = 0;
     // batches of B rows from observation 0 (whose difference is 0); a batch
     // never crosses a group of 64 observations
     for (uint32_t q = 0; q < n; q += B) {
@@ -1123,7 +1024,7 @@ __device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const Ma
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const float v = __shfl(vl, (int)((q + b) & 63u), 64);
-            if (q + b < n) sum_t += (double)v;
+            if (q + b < n) sum_t += fix_q(v, fx.s);
         }
 #pragma unroll
         for (int b = 0; b < B; ++b)
@@ -1159,7 +1060,7 @@ __device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const Ma
         M[i] = (W0 * mi + nf * zbar) / W1;
     }
     if (lane == 0) {
-        R[0] = tsdf_mean(D0, W0, W1, sum_t);
+        R[0] = tsdf_mean(D0, W0, W1, sum_t, fx.inv);
         R[1] = W1;
     }
 }
@@ -1298,16 +1199,14 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
             if (comp < C) R[2 + comp] = (existed ? R[2 + comp] : 0.0f) + s1[j];
         }
     }
-    // binary64 distance sum in point order, 64 distances loaded at a time
-    double sum_t = 0.0;
-    for (uint32_t w0 = 0; w0 < n; w0 += 64) {
-        const float vl = w0 + (uint32_t)lane < n ? vals[w0 + lane] : 0.0f;
-        const uint32_t m = min(n - w0, 64u);
-        for (uint32_t t = 0; t < m; ++t)
-            sum_t += (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(vl), (int)t));
-    }
+    // fixed-point distance sum, 64 distances loaded at a time, one per lane
+    const FixScale fx = fix_scale(fp);
+    long long sum_t = 0;
+    for (uint32_t w0 = 0; w0 < n; w0 += 64)
+        sum_t += w0 + (uint32_t)lane < n ? fix_q(vals[w0 + lane], fx.s) : 0ll;
+    for (int d = 32; d > 0; d >>= 1) sum_t += __shfl_xor(sum_t, d, 64);
     if (lane == 0) {
-        R[0] = tsdf_mean(D0, W0, W1, sum_t);
+        R[0] = tsdf_mean(D0, W0, W1, sum_t, fx.inv);
         R[1] = W1;
     }
 }
@@ -1339,7 +1238,8 @@ __device__ __forceinline__ void combine_last_lane(const FrameParams &fp, const M
     float4 *R = (float4 *)(md.vox + (size_t)rec * md.rec_stride);
     const float4 r = existed ? R[0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float nf = (float)n, W1 = r.y + nf;
-    R[0] = make_float4(tsdf_mean(r.x, r.y, W1, tsdf_sum(vals, n)), W1, (float)cls, 0.0f);
+    const FixScale fx = fix_scale(fp);
+    R[0] = make_float4(tsdf_mean(r.x, r.y, W1, tsdf_sum(vals, n, fx.s), fx.inv), W1, (float)cls, 0.0f);
 }
 
 // Open set, one wave per voxel: lane l copies components l, l + 64, ... of the
@@ -1352,7 +1252,8 @@ __device__ __forceinline__ void combine_last_wave(const FrameParams &fp, const M
     for (int comp = lane_id(); comp < fp.L; comp += 64) R[2 + comp] = load_emb(fp, pid, comp);
     if (lane_id() == 0) {
         const float W0 = existed ? R[1] : 0.0f, D0 = existed ? R[0] : 0.0f, W1 = W0 + (float)n;
-        R[0] = tsdf_mean(D0, W0, W1, tsdf_sum(vals, n));
+        const FixScale fx = fix_scale(fp);
+        R[0] = tsdf_mean(D0, W0, W1, tsdf_sum(vals, n, fx.s), fx.inv);
         R[1] = W1;
     }
 }
@@ -1387,9 +1288,9 @@ __device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t k)
 
 template <int KMAX, bool WAVE, bool ROWS>
 __device__ void combine_range(const FrameParams &fp, const MapDev &md, LeafShared &sh, const uint32_t *keys,
-                              const float *vals, const int32_t *labs, uint32_t o0, uint32_t o1, uint32_t base)
+                              const float *vals, uint32_t o0, uint32_t o1, uint32_t base)
 {
-    if (!WAVE) {
+    if constexpr (!WAVE) {
         // thread t takes the touched offsets of rank t, t + blockDim.x, ... in
         // [o0, o1), so a leaf with at most blockDim.x touched voxels loads its
         // records in one round
@@ -1408,13 +1309,10 @@ __device__ void combine_range(const FrameParams &fp, const MapDev &md, LeafShare
             const uint32_t n = sh.hist[o];
             const long long rec = (long long)sh.pages[o >> 6] * kPageVoxels + (o & (kPageVoxels - 1));
             const bool existed = (sh.occ0[o >> 5] >> (o & 31)) & 1u;
-            if (KMAX < 0)
+            if constexpr (KMAX < 0)
                 combine_last_lane(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base), n, rec, existed);
             else
-                combine_lane<(KMAX < 0 ? 0 : KMAX), ROWS>(fp, md, keys + (sh.bin0[o] - base),
-                                                          vals + (sh.bin0[o] - base),
-                                                          labs ? labs + (sh.bin0[o] - base) : nullptr, n, rec,
-                                                          existed);
+                combine_lane<KMAX>(fp, md, keys + (sh.bin0[o] - base), vals + (sh.bin0[o] - base), n, rec, existed);
         }
     } else {
         const uint32_t wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -1658,14 +1556,6 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
             }
         }
         __syncthreads();
-        const int32_t *labs = nullptr;
-        if (KMAX > 0 && !ROWS && !WAVE && fits && ok) {
-            // the labels of the sorted pairs, gathered once into the free binning array
-            for (uint32_t t = tid; t < hi - lo; t += blockDim.x)
-                sh.b_key[t] = (uint32_t)point_label(fp, sh.a_key[t] & kPidMask);
-            __syncthreads();
-            labs = (const int32_t *)sh.b_key;
-        }
         if (ok && WAVE) {
             // wave combines run in their own kernel over every voxel of the frame:
             // the sorted pairs go to the pair buffers at their bucket positions,
@@ -1704,7 +1594,7 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
             // sorted pairs of bin o sit at keys[bin0[o] - base]
             const uint32_t *ck = fits ? sh.a_key : md.pair_key + bstart;
             const float *cv = fits ? sh.a_val : md.pair_tsdf + bstart;
-            combine_range<KMAX, WAVE, ROWS>(fp, md, sh, ck, cv, labs, o0, o1, fits ? lo : 0u);
+            combine_range<KMAX, WAVE, ROWS>(fp, md, sh, ck, cv, o0, o1, fits ? lo : 0u);
         }
         __syncthreads();
         o0 = o1;
@@ -1759,7 +1649,6 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
     uint32_t *wk = sh.a_key + w * kWaveLds;
     float *wv = sh.a_val + w * kWaveLds;
     uint32_t *seg = sh.b_key + w * kWaveLds;     // voxel segment starts
-    int32_t *wl = (int32_t *)sh.b_val + w * kWaveLds;  // labels of the sorted pairs
     uint32_t *wt = sh.hist + w * 16;             // touched-offset mask (16 words)
     uint32_t *wo = sh.bin0 + w * 16;             // occupancy words of the leaf before this frame
     int *wp = (int *)sh.cur + w * 8;             // record pages of the leaf's slabs
@@ -1769,7 +1658,6 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
     const uint32_t pos = wi[0], n = wi[1], bstart = wi[2];
     const int islot = (int)wi[3];
     const int slot = islot >= 0 ? islot : (int)(lused + (unsigned long long)(-1 - islot));
-    const bool labels = KMAX > 0 && !ROWS && !WAVE;
     // a new leaf's first insertion probe goes out with the pair loads
     const bool inserts = ok && islot < 0 && lane == 0;
     const unsigned long long lkey = ((unsigned long long)wi[7] << 32) | wi[6];
@@ -1783,7 +1671,6 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
     uint32_t *uk = sh.b_key + w * kWaveLds;  // unsorted keys, padded to a multiple of 4
     uint32_t kq[4];
     float vq[4];
-    int32_t lq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const uint32_t i = lane + 64 * q;
@@ -1791,7 +1678,6 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
         const uint2 e = has ? md.srt_kv[bstart + i] : make_uint2(0xFFFFFFFFu, 0u);
         kq[q] = e.x;
         vq[q] = __uint_as_float(e.y);
-        lq[q] = (has && labels) ? md.srt_lab[bstart + i] : 0;
         if (i < ((n + 3u) & ~3u)) uk[i] = kq[q];
     }
     const uint32_t occ = lane < kMaskWords ? wi[16 + lane] : 0u;
@@ -1815,7 +1701,6 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
         if (lane + 64 * q < n) {
             wk[rq[q]] = kq[q];
             wv[rq[q]] = vq[q];
-            wl[rq[q]] = lq[q];
         }
     wave_sync();
     // voxel segments: starts where the offset changes
@@ -1842,11 +1727,10 @@ __device__ __forceinline__ void fuse_wave_item(const FrameParams &fp, const MapD
             const uint32_t ow = wo[o >> 5];
             const long long rec = (long long)pg * kPageVoxels + (o & (kPageVoxels - 1));
             const bool existed = (ow >> (o & 31)) & 1u;
-            if (KMAX < 0)
+            if constexpr (KMAX < 0)
                 combine_last_lane(fp, md, wk + b0, wv + b0, b1 - b0, rec, existed);
             else
-                combine_lane<(KMAX < 0 ? 0 : KMAX), ROWS>(fp, md, wk + b0, wv + b0, labels ? wl + b0 : nullptr,
-                                                          b1 - b0, rec, existed);
+                combine_lane<KMAX>(fp, md, wk + b0, wv + b0, b1 - b0, rec, existed);
         }
     }
     // statistics and leaf bookkeeping
@@ -1914,7 +1798,7 @@ __device__ __forceinline__ void leaf_fuse_range(const FrameParams &fp, const Map
             fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, &md.items_big[it.x], it.y, lused, ok);
         } else if (u < nbig + nmed) {
             fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, med_at(u - nbig), -1, lused, ok);
-        } else if (WAVE) {
+        } else if constexpr (WAVE) {
             fuse_item<KMAX, WAVE, ROWS>(fp, md, sh, small_at(u - nbig - nmed), -1, lused, ok);
         } else {
             const uint32_t k = (u - nbig - nmed) * nw + w;
@@ -1945,6 +1829,381 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_fuse_batch(MapBatch mb)
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// 4'. per-leaf accumulation: geometry, or int32 labels with K <= 32 (Bayesian)
+// ---------------------------------------------------------------------------
+//
+// Everything such a frame adds to a voxel is an integer: its observation count
+// (W grows by it, Eq. (1)-(2)), its class counts (Eq. (6)) and its fixed-point
+// distance sum.  Integer sums do not depend on the order of their terms, so a
+// leaf's pairs are not sorted at all: each pair adds into its voxel's LDS
+// accumulators with integer atomics (one set per frame of a multi-frame pass),
+// then one lane per touched voxel applies them to the record, frame after
+// frame.  The record is bitwise the same whatever order the pairs arrive in.
+
+template <int KMAX, int FR>
+struct AccShared {
+    static constexpr int KW = KMAX > 0 ? (KMAX + 1) / 2 : 1;  // class counts as 16-bit fields, two to a word
+    union {
+        struct {  // one leaf per workgroup, indexed by voxel offset
+            unsigned long long sum[FR][kLeafVoxels];
+            uint32_t cnt[FR][kLeafVoxels];
+            uint32_t lab[kLeafVoxels][KW];
+        } b;
+        struct {  // one leaf per wave, indexed by rank among the leaf's touched voxels
+            unsigned long long sum[FR][kAccWavePairs];
+            uint32_t cnt[FR][kAccWavePairs];
+            uint32_t lab[kAccWavePairs][KW];
+        } w[4];
+    };
+    uint32_t touch[4][kMaskWords];  // touched offsets of the workgroup's leaf, or of each wave's
+    uint32_t pre[4][kMaskWords];    // touched offsets below each mask word (wave leaves)
+    uint32_t item[4][32];           // the leaf item of the workgroup, or of each wave
+    uint32_t uold, unew;
+};
+
+// Class counts of a voxel with more than 65535 observations in a unit (whose
+// 16-bit counts may have wrapped), counted again from the unit's pairs, one
+// class at a time, and added to its record.  Slow, and only for such voxels.
+__device__ __noinline__ void acc_recount(const FrameParams &fp, const MapDev &md, long long rec, const uint2 *gkv,
+                                         const int32_t *glab, uint32_t npairs, uint32_t o)
+{
+    float *R = md.vox + (size_t)rec * md.rec_stride;
+    for (int k = 0; k < fp.K; ++k) {
+        uint32_t c = 0;
+        for (uint32_t t = 0; t < npairs; ++t) c += ((gkv[t].x >> kPidBits) == o && glab[t] == k) ? 1u : 0u;
+        R[2 + k] += (float)c;
+    }
+}
+
+// Applies one voxel's accumulators to its record: Eq. (1)-(2) frame after frame
+// (each frame's run exactly as that frame alone), then Eq. (6).  sum and cnt
+// point at frame 0's entry, the frames fstride apart; lab holds the 16-bit
+// class counts.  A voxel with more than 65535 observations in the unit may have
+// wrapped a 16-bit count: its labels are then counted again from the unit's
+// pairs (gkv, glab, npairs), which only a workgroup unit passes.
+template <int KMAX, int FR>
+__device__ __forceinline__ void acc_apply(const FrameParams &fp, const MapDev &md, long long rec, bool existed,
+                                          const unsigned long long *sum, const uint32_t *cnt, int fstride,
+                                          const uint32_t *lab, int nf, const FixScale &fx, const uint2 *gkv,
+                                          const int32_t *glab, uint32_t npairs, uint32_t o)
+{
+    constexpr int NV = (2 + KMAX + 3) / 4;
+    const int nv = md.rec_stride / 4, K = fp.K;
+    float4 *R = (float4 *)(md.vox + (size_t)rec * md.rec_stride);
+    float r[4 * NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const float4 x = (existed && v < nv) ? R[v] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        r[4 * v + 0] = x.x;
+        r[4 * v + 1] = x.y;
+        r[4 * v + 2] = x.z;
+        r[4 * v + 3] = x.w;
+    }
+    uint32_t ntot = 0;
+#pragma unroll
+    for (int f = 0; f < FR; ++f) {
+        const uint32_t c = f < nf ? cnt[f * fstride] : 0u;
+        if (c) {
+            const float W0 = r[1], W1 = W0 + (float)c;
+            r[0] = tsdf_mean(r[0], W0, W1, (long long)sum[f * fstride], fx.inv);
+            r[1] = W1;
+            ntot += c;
+        }
+    }
+    const bool wrapped = ntot > 0xFFFFu;
+    if constexpr (KMAX > 0) {
+        if (!wrapped) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < K) r[2 + k] += (float)((lab[k >> 1] >> ((k & 1) << 4)) & 0xFFFFu);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        if (v < nv) R[v] = make_float4(r[4 * v + 0], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
+    if (KMAX > 0 && wrapped) acc_recount(fp, md, rec, gkv, glab, npairs, o);
+}
+
+// A leaf with more than kAccWavePairs pairs, whole, by one workgroup of
+// kLeafThreads threads: its pairs stream through registers (kLeafBatch loads in
+// flight per thread) into accumulators indexed by voxel offset.
+template <int KMAX, int FR>
+__device__ __forceinline__ void acc_block_unit(const FrameParams &fp, const MapDev &md, AccShared<KMAX, FR> &sh,
+                                               const LeafItem *itp, unsigned long long lused, bool ok,
+                                               const FixScale &fx, int nf)
+{
+    const int tid = threadIdx.x;
+    if (tid < 32) sh.item[0][tid] = ((const uint32_t *)itp)[tid];
+    {
+        uint4 *p = (uint4 *)&sh.b;
+        constexpr int nvec = (int)(sizeof(sh.b) / 16);
+        for (int i = tid; i < nvec; i += blockDim.x) p[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    __syncthreads();
+    const uint32_t *it = sh.item[0];
+    const uint32_t pos = it[0], n = it[1], bstart = it[2];
+    const int islot = (int)it[3];
+    const int slot = islot >= 0 ? islot : (int)(lused + (unsigned long long)(-1 - islot));
+    // a new leaf's first insertion probe goes out with the pair loads
+    const bool inserts = ok && islot < 0 && tid == 0;
+    const unsigned long long lkey = ((unsigned long long)it[7] << 32) | it[6];
+    uint32_t ih = 0;
+    unsigned long long iprev = 0;
+    if (inserts) iprev = map_insert_start(md, lkey, &ih);
+    const uint2 *gkv = md.srt_kv + bstart;
+    const int32_t *glab = md.srt_lab + bstart;
+    for (uint32_t t0 = 0; t0 < n; t0 += kLeafBatch * blockDim.x) {
+        uint32_t rk[kLeafBatch];
+        float rv[kLeafBatch];
+        int32_t rl[kLeafBatch];
+#pragma unroll
+        for (int u = 0; u < kLeafBatch; ++u) {
+            const uint32_t t = t0 + u * blockDim.x + tid;
+            const uint2 e = t < n ? gkv[t] : make_uint2(0u, 0u);
+            rk[u] = e.x;
+            rv[u] = __uint_as_float(e.y);
+            rl[u] = (KMAX > 0 && t < n) ? glab[t] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kLeafBatch; ++u)
+            if (t0 + u * blockDim.x + tid < n) {
+                const uint32_t o = rk[u] >> kPidBits;
+                const int f = FR > 1 ? pass_frame(fp, rk[u] & kPidMask) : 0;
+                atomicAdd(&sh.b.cnt[f][o], 1u);
+                atomicAdd(&sh.b.sum[f][o], (unsigned long long)fix_q(rv[u], fx.s));
+                if constexpr (KMAX > 0) atomicAdd(&sh.b.lab[o][rl[u] >> 1], 1u << ((rl[u] & 1) << 4));
+            }
+    }
+    __syncthreads();
+    {
+        // touched offsets: wave w covers offsets 64 w + [0, 64) and 256 + 64 w + [0, 64)
+        uint32_t c0 = 0, c1 = 0;
+#pragma unroll
+        for (int f = 0; f < FR; ++f)
+            if (f < nf) {
+                c0 += sh.b.cnt[f][tid];
+                c1 += sh.b.cnt[f][tid + 256];
+            }
+        const unsigned long long b0 = __ballot(c0 != 0u), b1 = __ballot(c1 != 0u);
+        const int w = tid >> 6;
+        if (lane_id() == 0) {
+            sh.touch[0][2 * w] = (uint32_t)b0;
+            sh.touch[0][2 * w + 1] = (uint32_t)(b0 >> 32);
+            sh.touch[0][8 + 2 * w] = (uint32_t)b1;
+            sh.touch[0][9 + 2 * w] = (uint32_t)(b1 >> 32);
+        }
+    }
+    __syncthreads();
+    // thread t takes the touched offsets of rank t, t + blockDim.x, ...
+    uint32_t ntouch = 0;
+#pragma unroll
+    for (int w = 0; w < kMaskWords; ++w) ntouch += __popc(sh.touch[0][w]);
+    if (ok) {
+        for (uint32_t r = tid; r < ntouch; r += blockDim.x) {
+            uint32_t w = 0, before = 0, bits = 0;
+            for (; w < (uint32_t)kMaskWords; ++w) {
+                bits = sh.touch[0][w];
+                const uint32_t c = __popc(bits);
+                if (r < before + c) break;
+                before += c;
+            }
+            const uint32_t o = (w << 5) + select_bit(bits, r - before);
+            const long long rec = (long long)(int)it[8 + (o >> 6)] * kPageVoxels + (o & (kPageVoxels - 1));
+            const bool existed = (it[16 + (o >> 5)] >> (o & 31)) & 1u;
+            acc_apply<KMAX, FR>(fp, md, rec, existed, &sh.b.sum[0][o], &sh.b.cnt[0][o], kLeafVoxels, sh.b.lab[o], nf,
+                                fx, gkv, glab, n, o);
+        }
+    }
+    if (tid == 0) {
+        uint32_t uo = 0, un = 0;
+        for (int w = 0; w < kMaskWords; ++w) {
+            uo += __popc(sh.touch[0][w] & it[16 + w]);
+            un += __popc(sh.touch[0][w] & ~it[16 + w]);
+        }
+        sh.uold += uo;
+        sh.unew += un;
+    }
+    // leaf bookkeeping: the unit owns the whole leaf
+    if (ok) {
+        if (inserts) {
+            map_insert_finish(md, lkey, slot, ih, iprev);
+            md.leaf_key[slot] = lkey;
+        }
+        if (tid < kLeafPages) md.leaf_page[(size_t)slot * kLeafPages + tid] = (int)it[8 + tid];
+        if (tid < kMaskWords) md.leaf_occ[(size_t)slot * kMaskWords + tid] = it[16 + tid] | sh.touch[0][tid];
+    }
+    if (tid == 0) {
+        md.skeys[pos] = kEmptyKey;
+        md.pos_count[pos] = 0u;
+        md.pos_slab[pos] = 0u;
+    }
+    __syncthreads();
+}
+
+// A leaf with at most kAccWavePairs pairs, by one wave (two pairs per lane):
+// accumulators indexed by the rank of the voxel among the leaf's touched
+// voxels.  Waves run such leaves independently, four per workgroup.
+template <int KMAX, int FR>
+__device__ __forceinline__ void acc_wave_unit(const FrameParams &fp, const MapDev &md, AccShared<KMAX, FR> &sh,
+                                              const LeafItem *itp, unsigned long long lused, bool ok,
+                                              const FixScale &fx, int nf)
+{
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    auto &A = sh.w[w];
+    uint32_t *wi = sh.item[w], *wt = sh.touch[w], *wp = sh.pre[w];
+    if (lane < 32) wi[lane] = ((const uint32_t *)itp)[lane];
+    if (lane < kMaskWords) wt[lane] = 0u;
+    {
+        uint4 *p = (uint4 *)&A;
+        constexpr int nvec = (int)(sizeof(A) / 16);
+        for (int i = lane; i < nvec; i += 64) p[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    wave_sync();
+    const uint32_t pos = wi[0], n = wi[1], bstart = wi[2];
+    const int islot = (int)wi[3];
+    const int slot = islot >= 0 ? islot : (int)(lused + (unsigned long long)(-1 - islot));
+    const bool inserts = ok && islot < 0 && lane == 0;
+    const unsigned long long lkey = ((unsigned long long)wi[7] << 32) | wi[6];
+    uint32_t ih = 0;
+    unsigned long long iprev = 0;
+    if (inserts) iprev = map_insert_start(md, lkey, &ih);
+    uint32_t kq[2];
+    float vq[2];
+    int32_t lq[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const uint32_t i = lane + 64 * q;
+        const bool has = i < n;
+        const uint2 e = has ? md.srt_kv[bstart + i] : make_uint2(0u, 0u);
+        kq[q] = e.x;
+        vq[q] = __uint_as_float(e.y);
+        lq[q] = (KMAX > 0 && has) ? md.srt_lab[bstart + i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+        if (lane + 64 * q < n) {
+            const uint32_t o = kq[q] >> kPidBits;
+            atomicOr(&wt[o >> 5], 1u << (o & 31));
+        }
+    wave_sync();
+    // rank of a touched offset: the touched offsets below its mask word, plus
+    // those below it in the word
+    const uint32_t pc = lane < kMaskWords ? (uint32_t)__popc(wt[lane]) : 0u;
+    const uint32_t incl = wave_incl_scan(pc);
+    if (lane < kMaskWords) wp[lane] = incl - pc;
+    const uint32_t nvox = (uint32_t)__shfl((int)incl, kMaskWords - 1, 64);
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+        if (lane + 64 * q < n) {
+            const uint32_t o = kq[q] >> kPidBits;
+            const uint32_t ci = wp[o >> 5] + (uint32_t)__popc(wt[o >> 5] & ((1u << (o & 31)) - 1u));
+            const int f = FR > 1 ? pass_frame(fp, kq[q] & kPidMask) : 0;
+            atomicAdd(&A.cnt[f][ci], 1u);
+            atomicAdd(&A.sum[f][ci], (unsigned long long)fix_q(vq[q], fx.s));
+            if constexpr (KMAX > 0) atomicAdd(&A.lab[ci][lq[q] >> 1], 1u << ((lq[q] & 1) << 4));
+        }
+    wave_sync();
+    if (ok) {
+        for (uint32_t ci = lane; ci < nvox; ci += 64) {
+            // offset of rank ci: its mask word, then its bit there
+            uint32_t wd = 0;
+            while (wd + 1 < (uint32_t)kMaskWords && wp[wd + 1] <= ci) ++wd;
+            const uint32_t o = (wd << 5) + select_bit(wt[wd], ci - wp[wd]);
+            const long long rec = (long long)(int)wi[8 + (o >> 6)] * kPageVoxels + (o & (kPageVoxels - 1));
+            const bool existed = (wi[16 + (o >> 5)] >> (o & 31)) & 1u;
+            acc_apply<KMAX, FR>(fp, md, rec, existed, &A.sum[0][ci], &A.cnt[0][ci], kAccWavePairs, A.lab[ci], nf, fx,
+                                nullptr, nullptr, 0u, o);
+        }
+    }
+    // statistics and leaf bookkeeping
+    const uint32_t tw = lane < kMaskWords ? wt[lane] : 0u;
+    const uint32_t occ = lane < kMaskWords ? wi[16 + lane] : 0u;
+    uint32_t uo = __popc(tw & occ), un = __popc(tw & ~occ);
+    for (int d = 32; d > 0; d >>= 1) {
+        uo += __shfl_xor(uo, d, 64);
+        un += __shfl_xor(un, d, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&sh.uold, uo);
+        atomicAdd(&sh.unew, un);
+    }
+    if (ok) {
+        if (inserts) {
+            map_insert_finish(md, lkey, slot, ih, iprev);
+            md.leaf_key[slot] = lkey;
+        }
+        if (lane < kLeafPages) md.leaf_page[(size_t)slot * kLeafPages + lane] = (int)wi[8 + lane];
+        if (lane < kMaskWords) md.leaf_occ[(size_t)slot * kMaskWords + lane] = occ | tw;
+    }
+    if (lane == 0) {
+        md.skeys[pos] = kEmptyKey;
+        md.pos_count[pos] = 0u;
+        md.pos_slab[pos] = 0u;
+    }
+    wave_sync();
+}
+
+// The accumulation kernel's work of one map's frame for blocks blk, blk + nblk,
+// ...: the leaves done by a workgroup (the larger ones first), then groups of
+// four small leaves, one per wave.  Block statistics go to md.blk_stats[blk].
+template <int KMAX, int FR>
+__device__ __forceinline__ void leaf_acc_range(const FrameParams &fp, const MapDev &md, AccShared<KMAX, FR> &sh,
+                                               uint32_t blk, uint32_t nblk)
+{
+    const DevState *st = md.st;
+    const unsigned long long lused = st->leaves_used;
+    const bool ok = md.fs->frame_err.v == 0 && st->pass_failed == 0 &&
+                    lused + md.fs->new_leaves.v <= (unsigned long long)md.max_leaves &&
+                    st->pages_used + md.fs->new_pages.v <= (unsigned long long)md.max_pages;
+    if (threadIdx.x == 0) {
+        sh.uold = 0;
+        sh.unew = 0;
+    }
+    __syncthreads();
+    const uint32_t medf = (uint32_t)md.fs->n_lists, smallf = (uint32_t)(md.fs->n_lists >> 32);
+    const uint32_t nmed = medf + (uint32_t)md.fs->n_lists_tail;
+    const uint32_t nsmall = smallf + (uint32_t)(md.fs->n_lists_tail >> 32);
+    const uint32_t last = md.hmask;
+    const uint32_t nw = blockDim.x >> 6, w = threadIdx.x >> 6;
+    const uint32_t nunits = nmed + (nsmall + nw - 1) / nw;
+    const FixScale fx = fix_scale(fp);
+    const int nf = fp.nsub > 1 ? fp.nsub : 1;
+    for (uint32_t u = blk; u < nunits; u += nblk) {
+        if (u < nmed) {
+            acc_block_unit<KMAX, FR>(fp, md, sh, &md.items[u < medf ? u : last - (u - medf)], lused, ok, fx, nf);
+        } else {
+            const uint32_t k = (u - nmed) * nw + w;
+            if (k < nsmall)
+                acc_wave_unit<KMAX, FR>(fp, md, sh, &md.items_small[k < smallf ? k : last - (k - smallf)], lused, ok,
+                                        fx, nf);
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) md.blk_stats[blk] = make_uint2(sh.uold, sh.unew);
+    __syncthreads();
+}
+
+template <int KMAX, int FR>
+__global__ __launch_bounds__(kLeafThreads, 3) void k_leaf_acc(FrameParams fp, MapDev md)
+{
+    __shared__ AccShared<KMAX, FR> sh;
+    leaf_acc_range<KMAX, FR>(fp, md, sh, blockIdx.x, gridDim.x);
+}
+
+// The maps mb.subset[0 .. nsubset) of a batch (one frame each), all of this kernel's kind.
+template <int KMAX>
+__global__ __launch_bounds__(kLeafThreads, 3) void k_leaf_acc_batch(MapBatch mb)
+{
+    __shared__ AccShared<KMAX, 1> sh;
+    for (int q = 0; q < mb.nsubset; ++q) {
+        const int i = mb.subset[q];
+        leaf_acc_range<KMAX, 1>(mb.fps[i], mb.mds[i], sh, blockIdx.x, gridDim.x);
+    }
+}
 
 // One wave per voxel descriptor of the frame (open set, wide class counts,
 // most-recent open set): the combine of the wave-per-voxel leaf kernels, run
@@ -2170,12 +2429,19 @@ static void launch_voxel_combine_batch(int kind, const MapBatch &mb, int blocks,
 static void launch_leaf(int kind, const FrameParams &fp, const MapDev &md, int blocks, hipStream_t s)
 {
     const dim3 gl(blocks), bl(kLeafThreads);
+    if (kind <= 4) {
+        // accumulating kernel with one set of accumulators per frame of the pass
+        const int fr = fp.nsub <= 1 ? 1 : (fp.nsub == 2 ? 2 : 4);
+        const int kmax = kind * 8;
+#define SLIM_ACC(K, F) \
+    if (kmax == K && fr == F) hipLaunchKernelGGL((k_leaf_acc<K, F>), gl, bl, 0, s, fp, md);
+        SLIM_ACC(0, 1) SLIM_ACC(0, 2) SLIM_ACC(0, 4) SLIM_ACC(8, 1) SLIM_ACC(8, 2) SLIM_ACC(8, 4)
+        SLIM_ACC(16, 1) SLIM_ACC(16, 2) SLIM_ACC(16, 4) SLIM_ACC(24, 1) SLIM_ACC(24, 2) SLIM_ACC(24, 4)
+        SLIM_ACC(32, 1) SLIM_ACC(32, 2) SLIM_ACC(32, 4)
+#undef SLIM_ACC
+        return;
+    }
     switch (kind) {
-    case 0: hipLaunchKernelGGL((k_leaf_fuse<0, false, false>), gl, bl, 0, s, fp, md); break;
-    case 1: hipLaunchKernelGGL((k_leaf_fuse<8, false, false>), gl, bl, 0, s, fp, md); break;
-    case 2: hipLaunchKernelGGL((k_leaf_fuse<16, false, false>), gl, bl, 0, s, fp, md); break;
-    case 3: hipLaunchKernelGGL((k_leaf_fuse<24, false, false>), gl, bl, 0, s, fp, md); break;
-    case 4: hipLaunchKernelGGL((k_leaf_fuse<32, false, false>), gl, bl, 0, s, fp, md); break;
     case 5: hipLaunchKernelGGL((k_leaf_fuse<8, false, true>), gl, bl, 0, s, fp, md); break;
     case 6: hipLaunchKernelGGL((k_leaf_fuse<16, false, true>), gl, bl, 0, s, fp, md); break;
     case 7: hipLaunchKernelGGL((k_leaf_fuse<32, false, true>), gl, bl, 0, s, fp, md); break;
@@ -2195,11 +2461,11 @@ static void launch_leaf_batch(int kind, const MapBatch &mb, int blocks, hipStrea
 {
     const dim3 gl(blocks), bl(kLeafThreads);
     switch (kind) {
-    case 0: hipLaunchKernelGGL((k_leaf_fuse_batch<0, false, false>), gl, bl, 0, s, mb); break;
-    case 1: hipLaunchKernelGGL((k_leaf_fuse_batch<8, false, false>), gl, bl, 0, s, mb); break;
-    case 2: hipLaunchKernelGGL((k_leaf_fuse_batch<16, false, false>), gl, bl, 0, s, mb); break;
-    case 3: hipLaunchKernelGGL((k_leaf_fuse_batch<24, false, false>), gl, bl, 0, s, mb); break;
-    case 4: hipLaunchKernelGGL((k_leaf_fuse_batch<32, false, false>), gl, bl, 0, s, mb); break;
+    case 0: hipLaunchKernelGGL((k_leaf_acc_batch<0>), gl, bl, 0, s, mb); break;
+    case 1: hipLaunchKernelGGL((k_leaf_acc_batch<8>), gl, bl, 0, s, mb); break;
+    case 2: hipLaunchKernelGGL((k_leaf_acc_batch<16>), gl, bl, 0, s, mb); break;
+    case 3: hipLaunchKernelGGL((k_leaf_acc_batch<24>), gl, bl, 0, s, mb); break;
+    case 4: hipLaunchKernelGGL((k_leaf_acc_batch<32>), gl, bl, 0, s, mb); break;
     case 5: hipLaunchKernelGGL((k_leaf_fuse_batch<8, false, true>), gl, bl, 0, s, mb); break;
     case 6: hipLaunchKernelGGL((k_leaf_fuse_batch<16, false, true>), gl, bl, 0, s, mb); break;
     case 7: hipLaunchKernelGGL((k_leaf_fuse_batch<32, false, true>), gl, bl, 0, s, mb); break;
@@ -2233,7 +2499,7 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const La
     }
     rec(1);
     rec(2);
-    hipLaunchKernelGGL(k_leaf_plan, dim3(shape.plan_blocks), dim3(256), 0, s, md);
+    hipLaunchKernelGGL(k_leaf_plan, dim3(shape.plan_blocks), dim3(256), 0, s, fp, md);
     rec(3);
     rec(4);
     const long long want = ((long long)fp.n * fp.maxsteps + 255) / 256;
@@ -2267,7 +2533,7 @@ hipError_t launch_after_walk(const FrameParams &fp, const MapDev &md_in, const L
 {
     MapDev md = md_in;
     md.leaf_blocks = shape.leaf_blocks;
-    hipLaunchKernelGGL(k_leaf_plan, dim3(shape.plan_blocks), dim3(256), 0, s, md);
+    hipLaunchKernelGGL(k_leaf_plan, dim3(shape.plan_blocks), dim3(256), 0, s, fp, md);
     const long long want = ((long long)fp.n * fp.maxsteps + 255) / 256;
     const int bb = (int)std::max<long long>(1, std::min<long long>(want, shape.bucket_blocks));
     hipLaunchKernelGGL(k_pair_bucket, dim3(bb), dim3(256), 0, s, fp, md);
