@@ -5,14 +5,18 @@ spinning sensor (65,536 points per sweep) driving along a synthetic street of
 boxes and cylinders, voxel 0.1 m, truncation 0.3 m, 20 closed-set classes
 given as per-point labels with 10 % flicker.  One step integrates one sweep
 into the growing map (ray walk, leaf allocation, TSDF fusion, Dirichlet
-update).  All sweeps are generated and copied to the GPU before timing.
+update).  All sweeps are generated and copied to the GPU before timing.  The
+timed steps go through slim_integrate_sequence in one call (multi-frame passes,
+bitwise the same map as one call per sweep).
 
-Prints one JSON line.  Besides points/s it reports voxel updates/s, the
-fraction of the HBM roofline of the dominant kernel (algorithmic bytes over
-its average duration, HIP events on the stream it runs on) and of the whole
-step, and the CPU oracle timed on a bounded sample of the same sweeps.
+Prints one JSON line.  Besides points/s it reports voxel updates/s, the HBM
+roofline of the dominant kernel of that same path (algorithmic bytes over its
+average duration, HIP events on the stream it runs on) and of the whole step,
+the per-sweep median / p10 / p90, further legs (tiny room, open-set RGB-D
+through the depth ingest, differentiation, many maps, render), and the CPU
+oracle on a bounded sample of the same sweeps, pinned to one core.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-diff] ...
 """
 from __future__ import annotations
 
@@ -40,6 +44,9 @@ def parse():
     ap.add_argument("--diff-reps", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true", help="skip the many-map batched measurement")
     ap.add_argument("--no-open", action="store_true", help="skip the open-set RGB-D measurement")
+    ap.add_argument("--no-room", action="store_true", help="skip the tiny room measurement")
+    ap.add_argument("--no-render", action="store_true", help="skip the render measurement")
+    ap.add_argument("--no-single", action="store_true", help="skip the one-call-per-sweep comparison")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run plain device copies of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -49,25 +56,254 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def diff_bench(sv, synth, torch, scene, frames=16, reps=5, vs=0.1, tau=0.3, ncls=20):
+def pct(xs):
+    xs = np.asarray(xs, np.float64)
+    return {"median": float(np.median(xs)), "p10": float(np.percentile(xs, 10)), "p90": float(np.percentile(xs, 90))}
+
+
+def frame_bytes(st, n_pts, b_pts, b_sem, S_v):
+    """Algorithmic HBM bytes of one frame: every point read once (b_pts of
+    geometry, b_sem of semantics), every voxel that existed read and written
+    (2 S_v), every new voxel written (S_v).  Returns (geometry part, semantics +
+    state part): the walk reads the geometry, the leaf (or voxel-combine) stage
+    the semantics and the voxel state."""
+    return (n_pts * b_pts,
+            n_pts * b_sem + st["voxels_old_last"] * 2 * S_v + st["voxels_new_last"] * S_v)
+
+
+def counts(per):
+    return dict(pairs=sum(s["pairs_last"] for s in per), valid=sum(s["points_last"] - s["rejected_last"] for s in per),
+                u_old=sum(s["voxels_old_last"] for s in per), u_new=sum(s["voxels_new_last"] for s in per))
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/leaf_acc_lidar_street_hbm_traffic.md), or None when the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        text = open(os.path.join(root, "profiles", "leaf_acc_lidar_street_hbm_traffic.md")).read()
+        line = [ln for ln in text.splitlines() if ln.startswith("TRAFFIC-JSON ")][0]
+        rec = json.loads(line[len("TRAFFIC-JSON "):])
+        h = hashlib.sha256()
+        for f in ("slimvdb_kernels.hip", "slim_internal.h"):
+            h.update(open(os.path.join(root, "paper_2512_12945_amd", "csrc", f), "rb").read())
+        if h.hexdigest() != rec["kernel_source_sha256"]:
+            return None
+        return rec["per_launch_bytes"].get(kernel)
+    except (OSError, IndexError, ValueError, KeyError):
+        return None
+
+
+def lidar_leg(args, sv, synth, torch, dev):
+    """The headline: LiDAR street sweeps through slim_integrate_sequence."""
+    K, W = args.steps, args.warmup
+    vs, tau, rmax, ncls = 0.1, 0.3, 50.0, 20
+    S_v, b_sem = 8 + 4 * ncls, 4
+    scene = synth.StreetScene(seed=2)
+    t0 = time.time()
+    sweeps = scene.sweeps(range(W + K), workers=min(8, os.cpu_count() or 1))
+    log(f"generated {W + K} sweeps in {time.time() - t0:.1f}s")
+    pts = [torch.from_numpy(s["points"]).to(dev) for s in sweeps]
+    lab = [torch.from_numpy(s["label"]).to(dev) for s in sweeps]
+    frames = [dict(points=pts[i], pose=sweeps[i]["pose"], sem=lab[i], kind=sv.IN_LABEL_I32) for i in range(W + K)]
+    torch.cuda.synchronize()
+    n_pts = sweeps[0]["points"].shape[0]
+    gmap = sv.Map(vs, tau, 0.0, rmax, sv.SEM_CLOSED, ncls, 0, 0, max_leaves=1 << 18, max_voxels=1 << 24)
+
+    # counting pass: the per-frame counters (bitwise the same on every path)
+    per = []
+    for f in frames:
+        gmap.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+        per.append(gmap.stats())
+    final_voxels = per[-1]["voxels"]
+    geo = [frame_bytes(s, n_pts, 12, b_sem, S_v) for s in per]
+
+    # headline: the timed sweeps in one slim_integrate_sequence call
+    gmap.reset()
+    sv.integrate_sequence(gmap, frames[:W])
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    sv.integrate_sequence(gmap, frames[W:W + K])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - start
+    assert gmap.stats()["voxels"] == final_voxels, "timed pass diverged from the counting pass"
+
+    # the same call with kernel events: one launch set per pass (the walk then
+    # not beside the previous pass), per-stage times and per-pass spans
+    gmap.reset()
+    sv.integrate_sequence(gmap, frames[:W])
+    gmap.profile(True)
+    gmap.profile_read()
+    gmap.profile_sets()
+    start = time.perf_counter()
+    sv.integrate_sequence(gmap, frames[W:W + K])
+    torch.cuda.synchronize()
+    elapsed_events = time.perf_counter() - start
+    kern = gmap.profile_read()
+    sets = gmap.profile_sets()
+    gmap.profile(False)
+    assert gmap.stats()["voxels"] == final_voxels, "timed pass diverged from the counting pass"
+    assert sum(f for f, _, _ in sets) == K, "launch sets do not cover the timed sweeps"
+    full = max(f for f, _, _ in sets)
+    fi, leaf_bytes, leaf_ms, walk_bytes, walk_ms, per_sweep = W, 0.0, 0.0, 0.0, 0.0, []
+    for f, ms, span in sets:
+        if f == full:
+            leaf_bytes += sum(geo[i][1] for i in range(fi, fi + f))
+            leaf_ms += ms["leaf_fuse"]
+            walk_bytes += sum(geo[i][0] for i in range(fi, fi + f))
+            walk_ms += ms["ray_walk_emit"]
+            per_sweep.append(span / f)
+        fi += f
+    n_full = sum(1 for f, _, _ in sets if f == full)
+    leaf_gbs = leaf_bytes / (leaf_ms / 1e3) / 1e9
+    stage_ms = {k: sum(ms[k] for f, ms, _ in sets if f == full) / n_full for k in sv.KERNELS}
+
+    out = {"elapsed": elapsed, "elapsed_events": elapsed_events, "n_pts": n_pts, "per": per, "geo": geo,
+           "gmap": gmap, "sweeps": sweeps, "frames": frames, "scene": scene}
+    acc = counts(per[W:W + K])
+    b_alg = sum(sum(g) for g in geo[W:W + K])
+    out["acc"], out["b_alg"] = acc, b_alg
+    out["roofline"] = {"kernel": "leaf_fuse", "kernel_symbol": f"slim::k_leaf_acc<24, {full}>",
+                       "launch_set": f"{full}-sweep passes of slim_integrate_sequence ({n_full} launches timed)",
+                       "bound": "hbm", "achieved": leaf_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": leaf_gbs / HBM_PEAK_GBS, "traffic": measured_traffic("leaf_acc"),
+                       "alg_bytes_per_launch": leaf_bytes / n_full, "avg_launch_ms": leaf_ms / n_full}
+    out["pass_stage_ms"] = stage_ms
+    out["per_sweep_ms"] = pct(per_sweep)
+    out["walk_roofline_frac"] = walk_bytes / (walk_ms / 1e3) / 1e9 / HBM_PEAK_GBS
+    if not args.no_single:
+        # for comparison: one slim_integrate call per sweep
+        gmap.reset()
+        for f in frames[:W]:
+            gmap.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+        torch.cuda.synchronize()
+        ts = []
+        for f in frames[W:W + K]:
+            s0 = time.perf_counter()
+            gmap.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - s0)
+        assert gmap.stats()["voxels"] == final_voxels
+        out["single_ms"] = pct(np.array(ts) * 1e3)
+    return out
+
+
+def room_leg(sv, synth, torch, dev, reps=50):
+    """The tiny room: one 64x64 frame of 5-class probabilities into a fresh map
+    (reset between repetitions, not timed); latency of one integration."""
+    fr = synth.room_frame(seed=1)
+    p = torch.from_numpy(fr["points"]).to(dev)
+    s = torch.from_numpy(fr["prob"]).to(dev)
+    g = sv.Map(0.05, 0.15, 0.0, 100.0, sv.SEM_CLOSED, 5, 0, 0, 1 << 12, 1 << 18)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for r in range(reps + 5):
+        g.reset()
+        ev0.record()
+        g.integrate(p, fr["pose"], s, sv.IN_PROB_F32)
+        ev1.record()
+        torch.cuda.synchronize()
+        if r >= 5:
+            ts.append(ev0.elapsed_time(ev1))
+    st = g.stats()
+    g.close()
+    n = p.shape[0]
+    lat = pct(ts)
+    b = sum(frame_bytes(st, n, 12, 20, 28))
+    return {"workload": "tiny room: one 64x64 pinhole frame (4,096 points), voxel 0.05 m, trunc 0.15 m, 5 classes "
+                        "as fp32 probabilities, into a fresh map",
+            "ms_per_frame": lat, "points_per_s": n / (lat["median"] / 1e3),
+            "voxel_updates_per_s": st["pairs_last"] / (lat["median"] / 1e3), "voxels": st["voxels"],
+            "alg_bytes": b, "path_roofline_frac": b / (lat["median"] / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+
+def open_leg(sv, synth, torch, dev, warm=2, steps=6):
+    """Open-set RGB-D: 640x480 depth images (307,200 pixels) with 512-d bf16
+    embeddings through slim_integrate_depth, voxel 0.02 m, trunc 0.06 m."""
+    L = 512
+    S_v, b_sem = 8 + 8 * L, 2 * L
+    t0 = time.time()
+    sc = synth.OpenRoomScene(L=L)
+    fr = sc.frames(range(warm + steps), workers=min(8, os.cpu_count() or 1))
+    depth = [torch.from_numpy(f["depth"]).to(dev) for f in fr]
+    emb = [torch.from_numpy(f["emb"]).to(dev) for f in fr]
+    poses = [f["pose"] for f in fr]
+    intr = (sc.f, sc.f, sc.cx, sc.cy)
+    n_pts = sc.width * sc.height
+    del fr
+    torch.cuda.synchronize()
+    log(f"open-set frames ready in {time.time() - t0:.1f}s")
+    g = sv.Map(0.02, 0.06, 0.0, 10.0, sv.SEM_OPEN, 0, L, 0, max_leaves=1 << 14, max_voxels=1 << 21)
+
+    def run(idx):
+        for i in idx:
+            g.integrate_depth(depth[i], intr, poses[i], emb[i], sv.IN_EMB_BF16)
+
+    per = []
+    for i in range(warm + steps):
+        run([i])
+        per.append(g.stats())
+    g.reset()
+    run(range(warm))
+    g.profile(True)
+    g.profile_read()
+    run(range(warm, warm + steps))
+    kern = g.profile_read()
+    g.profile(False)
+    g.reset()
+    run(range(warm))
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    run(range(warm, warm + steps))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - start
+    assert g.stats()["voxels"] == per[-1]["voxels"]
+    g.close()
+    geo = [frame_bytes(s, n_pts, 4, b_sem, S_v) for s in per[warm:]]
+    b_alg = sum(sum(x) for x in geo)
+    acc = counts(per[warm:])
+    kalg = {"ray_walk_emit": sum(x[0] for x in geo), "voxel_combine": sum(x[1] for x in geo)}
+    dom = max(kern, key=lambda k: kern[k][0])
+    dom_ms, dom_n = kern[dom]
+    dom_gbs = kalg.get(dom, 0.0) / (dom_ms / 1e3) / 1e9 if dom_ms > 0 else 0.0
+    return {"workload": "open-set RGB-D through the depth ingest: 640x480 depth images (307,200 pixels), room of "
+                        "50 boxes, orbit 0.5 deg/frame, 512-d bf16 embeddings, voxel 0.02 m, trunc 0.06 m",
+            "frames_timed": steps, "first_timed_frame": warm, "points_per_s": n_pts * steps / el,
+            "ms_per_frame": el / steps * 1e3, "voxel_updates_per_s": acc["pairs"] / el,
+            "valid_points_per_s": acc["valid"] / el, "alg_bytes_per_frame": b_alg / steps,
+            "path_roofline_frac": b_alg / el / 1e9 / HBM_PEAK_GBS,
+            "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in kern.items()},
+            "roofline": {"kernel": dom, "bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": dom_gbs / HBM_PEAK_GBS, "alg_bytes_per_launch": kalg.get(dom, 0.0) / max(dom_n, 1),
+                         "avg_launch_ms": dom_ms / max(dom_n, 1)}}
+
+
+def diff_leg(sv, synth, torch, dev, scene, frames=16, reps=5, vs=0.1, tau=0.3, ncls=20):
     """Differentiation workload: 16 ray sweeps (ranges, directions, 20-class
     logits) integrated into a fresh map, the map loss, and its backward w.r.t.
     logits and ranges; times the plain forward and forward + backward."""
     t0 = time.time()
     sw = [scene.ray_sweep(t) for t in range(frames)]
-    dev = torch.device("cuda", 0)
     ranges = torch.from_numpy(np.stack([s["ranges"] for s in sw])).to(dev)
     dirs = torch.from_numpy(np.stack([s["dirs"] for s in sw])).to(dev)
     logits = torch.from_numpy(np.stack([s["logits"] for s in sw])).to(dev)
     poses = [s["pose"] for s in sw]
     gmap = sv.Map(vs, tau, 0.0, 50.0, sv.SEM_CLOSED, ncls, 0, 0, max_leaves=1 << 18, max_voxels=1 << 24)
+    S_v, n = 8 + 4 * ncls, ranges.shape[1]
 
     def forward():
         gmap.reset()
         for f in range(frames):
             gmap.integrate_rays(ranges[f], dirs[f], poses[f], logits[f], sv.IN_LOGIT_F32)
 
-    forward()
+    gmap.reset()
+    per = []
+    for f in range(frames):
+        gmap.integrate_rays(ranges[f], dirs[f], poses[f], logits[f], sv.IN_LOGIT_F32)
+        per.append(gmap.stats())
     ex = gmap.extract()
     keys = ex["keys"]
     labels = torch.from_numpy(scene.nearest_class((keys.cpu().numpy() + 0.5) * np.float64(np.float32(vs)))).to(dev)
@@ -95,25 +331,41 @@ def diff_bench(sv, synth, torch, scene, frames=16, reps=5, vs=0.1, tau=0.3, ncls
 
     t_fwd = timed(forward)
     t_fb = timed(fwd_bwd)
-    return {"workload": f"{frames} LiDAR ray sweeps x {ranges.shape[1]} rays, 20-class logits, map loss = "
+    gmap.profile(True)
+    gmap.profile_read()
+    forward()
+    kern = gmap.profile_read()
+    gmap.profile(False)
+    gmap.close()
+    # forward: ranges 4 B + directions 12 B + 20 fp32 logits per ray, voxel state 88 B
+    geo = [frame_bytes(s, n, 16, 4 * ncls, S_v) for s in per]
+    b_alg = sum(sum(x) for x in geo)
+    leaf_b = sum(x[1] for x in geo)
+    leaf_ms, leaf_n = kern["leaf_fuse"]
+    return {"workload": f"{frames} LiDAR ray sweeps x {n} rays, 20-class logits, map loss = "
                         "Dirichlet-predictive cross-entropy over all voxels + mean |D| at 10k surface samples",
             "fwd_ms": t_fwd, "fwd_bwd_ms": t_fb, "ratio": t_fb / t_fwd, "voxels": int(keys.shape[0]),
-            "points_per_s_fwd_bwd": frames * ranges.shape[1] / (t_fb / 1e3)}
+            "points_per_s_fwd_bwd": frames * n / (t_fb / 1e3),
+            "fwd_alg_bytes": b_alg, "fwd_path_roofline_frac": b_alg / (t_fwd / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "fwd_kernel_ms_per_sweep": {k: v[0] / max(v[1], 1) for k, v in kern.items()},
+            "fwd_roofline": {"kernel": "leaf_fuse", "bound": "hbm",
+                             "achieved": leaf_b / (leaf_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": leaf_b / (leaf_ms / 1e3) / 1e9 / HBM_PEAK_GBS}}
 
 
-def batched_bench(sv, synth, torch, reps=10, log_fn=log):
+def batched_leg(sv, synth, torch, dev, reps=10):
     """Many-map workload: 32 independent maps, one frame each with 10k-130k
     rays of a 128-beam street sweep; 16 maps 20-class closed set (int32
     labels), 16 maps 256-d open set (bf16 embeddings).  The launch shape comes
-    from the autotuner.  Times, in steady state (each map already holds its
-    frame once, so every voxel exists), one batched call per replay (eager and
-    graph) against one plain integration per map on the same stream."""
+    from the autotuner.  Times the first (allocating) batched call on fresh
+    maps, then, in steady state (each map already holds its frame, so every
+    voxel exists), one batched call per replay (eager and graph) against one
+    plain integration per map on the same stream."""
     from paper_2512_12945_amd import autotune
 
     t0 = time.time()
     w = synth.batched_workload(workers=min(8, os.cpu_count() or 1))
-    dev = torch.device("cuda", 0)
-    frames, cfgs = [], []
+    frames, cfgs, sizes = [], [], []
     for item in w:
         if item["mode"] == "closed":
             frames.append(dict(points=torch.from_numpy(item["points"]).to(dev), pose=item["pose"],
@@ -121,20 +373,26 @@ def batched_bench(sv, synth, torch, reps=10, log_fn=log):
             cfgs.append(dict(voxel_size=0.1, sdf_trunc=0.3, min_range=0.0, max_range=50.0, sem_mode=sv.SEM_CLOSED,
                              num_classes=item["K"], embed_dim=0, device=0, max_leaves=1 << 15,
                              max_voxels=1 << 21))
+            sizes.append((4, 8 + 4 * item["K"]))
         else:
             frames.append(dict(points=torch.from_numpy(item["points"]).to(dev), pose=item["pose"],
                                sem=torch.from_numpy(item["emb"]).to(dev), kind=sv.IN_EMB_BF16))
             cfgs.append(dict(voxel_size=0.1, sdf_trunc=0.3, min_range=0.0, max_range=50.0, sem_mode=sv.SEM_OPEN,
                              num_classes=0, embed_dim=item["L"], device=0, max_leaves=1 << 15,
                              max_voxels=1 << 21))
+            sizes.append((2 * item["L"], 8 + 8 * item["L"]))
     torch.cuda.synchronize()
-    log_fn(f"batched inputs ready in {time.time() - t0:.1f}s: {sum(x['n'] for x in w)} points over {len(w)} maps")
+    log(f"batched inputs ready in {time.time() - t0:.1f}s: {sum(x['n'] for x in w)} points over {len(w)} maps")
     shape = autotune.tune(cfgs, frames, cache_path=os.path.join(os.environ.get("TMPDIR", "/tmp"),
-                                                                "slimvdb_autotune.json"), log=log_fn)
+                                                                "slimvdb_autotune.json"), log=log)
     maps = [sv.Map(**c) for c in cfgs]
-    maps[0].set_launch_shape(*shape)
-    for m in maps[1:]:
+    for m in maps:
         m.set_launch_shape(*shape)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    sv.integrate_batched(maps, frames, use_graph=False)
+    torch.cuda.synchronize()
+    t_first = (time.perf_counter() - s0) * 1e3
 
     def sequential():
         for m, f in zip(maps, frames):
@@ -157,149 +415,82 @@ def batched_bench(sv, synth, torch, reps=10, log_fn=log):
     st = [m.stats() for m in maps]
     npts = sum(x["n"] for x in w)
     pairs = sum(s["pairs_last"] for s in st)
+    b_alg = sum(sum(frame_bytes(s, f["points"].shape[0], 12, b, S)) for s, f, (b, S) in zip(st, frames, sizes))
     for m in maps:
         m.close()
     return {"workload": "32 maps, one street-sweep frame each with 10k-130k rays (128 beams); 16 maps 20-class "
                         "int32 labels, 16 maps 256-d bf16 embeddings; voxel 0.1 m, trunc 0.3 m; steady state",
             "points": npts, "pairs": pairs, "launch_shape": list(shape),
-            "sequential_ms": t_seq, "batched_ms": t_eager, "batched_graph_ms": t_graph,
+            "first_launch_ms": t_first, "sequential_ms": t_seq, "batched_ms": t_eager, "batched_graph_ms": t_graph,
             "speedup_graph_vs_sequential": t_seq / t_graph,
-            "points_per_s_graph": npts / (t_graph / 1e3)}
+            "points_per_s_graph": npts / (t_graph / 1e3), "alg_bytes": b_alg,
+            "path_roofline_frac_graph": b_alg / (t_graph / 1e3) / 1e9 / HBM_PEAK_GBS}
 
 
-def run_sequence(torch, gmap, seq, W, K, sv=None):
-    """Integrates seq[0:W] (warm-up) and times seq[W:W+K], three passes over a
-    reset map: one with stats after every frame (the counts), one with kernel
-    events (per-kernel time), one plain (the step time); with sv, a fourth
-    pass integrates the timed frames with one slim_integrate_sequence call."""
-    per = []
-    for f in seq:
-        gmap.integrate(*f)
-        per.append(gmap.stats())
-    gmap.reset()
-
-    def warm():
-        for f in seq[:W]:
-            gmap.integrate(*f)
-        torch.cuda.synchronize()
-
-    warm()
-    gmap.profile(True)
-    gmap.profile_read()
-    start = time.perf_counter()
-    for f in seq[W:W + K]:
-        gmap.integrate(*f)
-    torch.cuda.synchronize()
-    elapsed_events = time.perf_counter() - start
-    kern = gmap.profile_read()
-    gmap.profile(False)
-    assert gmap.stats()["voxels"] == per[-1]["voxels"], "timed pass diverged from the counting pass"
-    gmap.reset()
-    warm()
-    start = time.perf_counter()
-    for f in seq[W:W + K]:
-        gmap.integrate(*f)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - start
-    assert gmap.stats()["voxels"] == per[-1]["voxels"], "timed pass diverged from the counting pass"
-    out = dict(per=per, kern=kern, elapsed=elapsed, elapsed_events=elapsed_events)
-    if sv is not None:
-        # the same frames through slim_integrate_sequence (one call for the timed frames)
-        frames = [dict(points=f[0], pose=f[1], sem=f[2], kind=f[3]) for f in seq]
-        gmap.reset()
-        if W:
-            sv.integrate_sequence(gmap, frames[:W])
-        torch.cuda.synchronize()
-        start = time.perf_counter()
-        sv.integrate_sequence(gmap, frames[W:W + K])
-        torch.cuda.synchronize()
-        out["elapsed_sequence"] = time.perf_counter() - start
-        assert gmap.stats()["voxels"] == per[-1]["voxels"], "sequence pass diverged from the counting pass"
+def render_leg(sv, synth, torch, gmap, scene, t_pose, reps=10):
+    """Ray-marched render of the LiDAR map from a forward-looking pinhole
+    camera at the sensor position of sweep t_pose (90 deg horizontal field of
+    view), at the two image sizes of the paper's render timing."""
+    pose = scene.pose(t_pose).copy()
+    R = synth.camera_rotation(np.array([np.cos(0.0), np.sin(0.0), 0.0]))
+    pose[:3, :3] = R @ np.eye(3)
+    out = {}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for wd, ht in ((691, 256), (1209, 448)):
+        intr = (wd / 2.0, wd / 2.0, wd / 2.0, ht / 2.0)
+        ts = []
+        for r in range(reps + 3):
+            ev0.record()
+            res = gmap.render(pose, intr, wd, ht, 0.3, 50.0)
+            ev1.record()
+            torch.cuda.synchronize()
+            if r >= 3:
+                ts.append(ev0.elapsed_time(ev1))
+        hits = int(torch.isfinite(res["depth"]).sum())
+        lat = pct(ts)
+        # written: depth 4 B, key 12 B, label 4 B per pixel; read at least the
+        # surface voxel's record (88 B) per hit
+        b = wd * ht * 20 + hits * 88
+        out[f"{wd}x{ht}"] = {"ms": lat, "pixels_per_s": wd * ht / (lat["median"] / 1e3), "hit_fraction": hits / (wd * ht),
+                             "alg_bytes_lower_bound": b,
+                             "hbm_frac_lower_bound": b / (lat["median"] / 1e3) / 1e9 / HBM_PEAK_GBS}
+    out["workload"] = (f"LiDAR street map after the timed sweeps, pinhole camera at the sensor pose of sweep "
+                       f"{t_pose} looking along +x, 90 deg horizontal field of view, near 0.3 m, far 50 m")
+    out["paper_context"] = "NanoVDB render, RTX 3090: 2.1 ms at 691x256, 3.9 ms at 1209x448 (another GPU)"
     return out
 
 
-def account(timed, n_pts, b_sem, S_v):
-    """Algorithmic HBM bytes of the timed frames: every point read once
-    (12 B of coordinates plus b_sem of semantics), every voxel that existed read
-    and written (2 S_v), every new voxel written (S_v).  Split by kernel: the
-    walk reads the coordinates, the fused leaf kernel the semantics and state."""
-    P = sum(s["pairs_last"] for s in timed)
-    valid = sum(s["points_last"] - s["rejected_last"] for s in timed)
-    u_old = sum(s["voxels_old_last"] for s in timed)
-    u_new = sum(s["voxels_new_last"] for s in timed)
-    K = len(timed)
-    bytes_points = n_pts * K * 12
-    bytes_sem = n_pts * K * b_sem
-    bytes_state = u_old * 2 * S_v + u_new * S_v
-    kalg = {"ray_walk_emit": bytes_points, "leaf_plan": 0, "pair_bucket": 0, "leaf_fuse": bytes_sem + bytes_state,
-            "frame_commit": 0}
-    return dict(pairs=P, valid=valid, u_old=u_old, u_new=u_new, kalg=kalg,
-                b_alg=bytes_points + bytes_sem + bytes_state)
+def cpu_leg(sweeps, vs, tau, rmax, ncls, budget):
+    """The oracle as it stands, single-threaded, pinned to one core of the host."""
+    import oracle  # test infrastructure: the CPU baseline leg only
 
-
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/leaf_fuse_lidar_street_hbm_traffic.md), or None when the kernel
-    sources changed since the counters were taken."""
-    import hashlib
-
-    root = os.path.dirname(os.path.abspath(__file__))
+    nproc = os.cpu_count()
+    aff = sorted(os.sched_getaffinity(0))
+    model = "unknown"
     try:
-        text = open(os.path.join(root, "profiles", "leaf_fuse_lidar_street_hbm_traffic.md")).read()
-        line = [ln for ln in text.splitlines() if ln.startswith("TRAFFIC-JSON ")][0]
-        rec = json.loads(line[len("TRAFFIC-JSON "):])
-        h = hashlib.sha256()
-        for f in ("slimvdb_kernels.hip", "slim_internal.h"):
-            h.update(open(os.path.join(root, "paper_2512_12945_amd", "csrc", f), "rb").read())
-        if h.hexdigest() != rec["kernel_source_sha256"]:
-            return None
-        return rec["per_launch_bytes"].get(kernel)
-    except (OSError, IndexError, ValueError, KeyError):
-        return None
-
-
-def dominant(kern, kalg, K):
-    """Kernel with the most time, its achieved algorithmic GB/s (bytes per
-    launch over its average event-timed duration) and its bytes per launch."""
-    dom = max(kern, key=lambda k: kern[k][0])
-    dom_ms, dom_n = kern[dom]
-    avg_s = dom_ms / 1e3 / max(dom_n, 1)
-    per_launch = kalg[dom] / K
-    return dom, (per_launch / avg_s / 1e9 if avg_s > 0 else 0.0), per_launch
-
-
-def open_bench(sv, synth, torch, warm=2, steps=6, log_fn=log):
-    """Open-set RGB-D workload: 640x480 depth frames (307,200 points) of a room
-    with 50 boxes on a 0.5 deg/frame orbit, per-pixel 512-d bf16 embeddings,
-    voxel 0.02 m, trunc 0.06 m.  Integrates `warm` frames, then times `steps`
-    more; reports points/s, voxel updates/s and the roofline of the dominant
-    kernel as for the LiDAR sweep."""
-    L = 512
-    t0 = time.time()
-    sc = synth.OpenRoomScene(L=L)
-    fr = sc.frames(range(warm + steps), workers=min(8, os.cpu_count() or 1))
-    dev = torch.device("cuda", 0)
-    seq = [(torch.from_numpy(f["points"]).to(dev), f["pose"], torch.from_numpy(f["emb"]).to(dev), sv.IN_EMB_BF16)
-           for f in fr]
-    n_pts = fr[0]["points"].shape[0]
-    del fr
-    torch.cuda.synchronize()
-    log_fn(f"open-set frames ready in {time.time() - t0:.1f}s")
-    gmap = sv.Map(0.02, 0.06, 0.0, 10.0, sv.SEM_OPEN, 0, L, 0, max_leaves=1 << 14, max_voxels=1 << 21)
-    run = run_sequence(torch, gmap, seq, warm, steps)
-    gmap.close()
-    acc = account(run["per"][warm:warm + steps], n_pts, 2 * L, 8 + 8 * L)
-    dom, dom_gbs, dom_bytes = dominant(run["kern"], acc["kalg"], steps)
-    el = run["elapsed"]
-    return {"workload": "open-set RGB-D: 640x480 depth frames (307,200 points), room of 50 boxes, orbit 0.5 deg/frame, "
-                        "512-d bf16 embeddings, voxel 0.02 m, trunc 0.06 m",
-            "frames_timed": steps, "first_timed_frame": warm, "points_per_s": n_pts * steps / el,
-            "ms_per_frame": el / steps * 1e3, "voxel_updates_per_s": acc["pairs"] / el,
-            "valid_points_per_s": acc["valid"] / el, "alg_bytes_per_frame": acc["b_alg"] / steps,
-            "path_roofline_frac": acc["b_alg"] / el / 1e9 / HBM_PEAK_GBS,
-            "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in run["kern"].items()},
-            "roofline": {"kernel": dom, "bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": dom_gbs / HBM_PEAK_GBS, "alg_bytes_per_launch": dom_bytes}}
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    os.sched_setaffinity(0, {aff[0]})
+    try:
+        o = oracle.OracleMap(vs, tau, 0.0, rmax, oracle.SEM_CLOSED, ncls)
+        done, tcpu = 0, 0.0
+        while done < len(sweeps) and tcpu < budget:
+            s = sweeps[done]
+            c0 = time.perf_counter()
+            o.integrate(s["points"], s["pose"], s["label"], oracle.IN_LABEL_I32)
+            tcpu += time.perf_counter() - c0
+            done += 1
+    finally:
+        os.sched_setaffinity(0, set(aff))
+    n_pts = sweeps[0]["points"].shape[0]
+    return {"value": n_pts * done / tcpu, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"sweeps 0..{done - 1} of the same street ({done} x {n_pts} points), single-threaded FP64 "
+                      f"oracle pinned to core {aff[0]}, {tcpu:.1f} s",
+            "nproc": nproc, "affinity_cores": len(aff), "cpu_model": model}
 
 
 def main():
@@ -316,41 +507,18 @@ def main():
     from paper_2512_12945_amd import synth
 
     K, W = args.steps, args.warmup
-    vs, tau, rmax, ncls = 0.1, 0.3, 50.0, 20
-    scene = synth.StreetScene(seed=2)
-    t0 = time.time()
-    sweeps = scene.sweeps(range(W + K), workers=min(8, os.cpu_count() or 1))
-    log(f"generated {W + K} sweeps in {time.time() - t0:.1f}s")
     dev = torch.device("cuda", 0)
-    pts = [torch.from_numpy(s["points"]).to(dev) for s in sweeps]
-    lab = [torch.from_numpy(s["label"]).to(dev) for s in sweeps]
-    poses = [s["pose"] for s in sweeps]
-    torch.cuda.synchronize()
-    n_pts = sweeps[0]["points"].shape[0]
-
-    gmap = sv.Map(vs, tau, 0.0, rmax, sv.SEM_CLOSED, ncls, 0, 0, max_leaves=1 << 18, max_voxels=1 << 24)
-    seq = [(pts[i], poses[i], lab[i], sv.IN_LABEL_I32) for i in range(W + K)]
-    run = run_sequence(torch, gmap, seq, W, K, sv)
-    gmap.close()
-    # the headline is the faster of the two public paths for a stream of sweeps:
-    # one slim_integrate call per sweep, or one slim_integrate_sequence call
-    # (walk of sweep t + 1 beside the rest of sweep t; bitwise the same map)
-    use_seq = run["elapsed_sequence"] < run["elapsed"]
-    elapsed_noev = run["elapsed_sequence"] if use_seq else run["elapsed"]
-    b_sem = 4  # int32 label
-    acc = account(run["per"][W:W + K], n_pts, b_sem, 8 + 4 * ncls)
-    dom, dom_gbs, dom_bytes = dominant(run["kern"], acc["kalg"], K)
-    P, valid, b_alg = acc["pairs"], acc["valid"], acc["b_alg"]
-    ms_step = elapsed_noev / K * 1e3
+    run = lidar_leg(args, sv, synth, torch, dev)
+    el, acc, b_alg, n_pts = run["elapsed"], run["acc"], run["b_alg"], run["n_pts"]
 
     result = {
         "metric": METRIC,
-        "value": n_pts * K / elapsed_noev,
+        "value": n_pts * K / el,
         "unit": "points/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": ms_step,
+        "ms_per_step": el / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -358,34 +526,42 @@ def main():
         "data": "synthetic",
         "config": {"workload": "lidar-street: 64x1024 sweeps (65,536 points), voxel 0.1 m, trunc 0.3 m, "
                                "20 classes as int32 labels, 10% flicker; map grows over the sweeps",
-                   "points_per_step": n_pts, "voxel_size": vs, "sdf_trunc": tau, "num_classes": ncls,
+                   "points_per_step": n_pts, "voxel_size": 0.1, "sdf_trunc": 0.3, "num_classes": 20,
                    "first_timed_sweep": W,
-                   "api": "slim_integrate_sequence, all timed sweeps in one call (two-sweep passes, the default)"
-                   if use_seq
-                   else "slim_integrate, one call per sweep"},
-        "ms_per_step_single_calls": run["elapsed"] / K * 1e3,
-        "ms_per_step_sequence": run["elapsed_sequence"] / K * 1e3,
-        "voxel_updates_per_s": P / elapsed_noev,
-        "valid_points_per_s": valid / elapsed_noev,
-        "ms_per_step_with_kernel_events": run["elapsed_events"] / K * 1e3,
+                   "api": "slim_integrate_sequence, all timed sweeps in one call (multi-frame passes, default 4)"},
+        "voxel_updates_per_s": acc["pairs"] / el,
+        "valid_points_per_s": acc["valid"] / el,
         "alg_bytes_per_step": b_alg / K,
-        "path_roofline_frac": (b_alg / elapsed_noev / 1e9) / HBM_PEAK_GBS,
-        "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in run["kern"].items()},
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": dom_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom_gbs / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
-                     "alg_bytes_per_launch": dom_bytes},
+        "path_roofline_frac": b_alg / el / 1e9 / HBM_PEAK_GBS,
+        "per_sweep_ms_from_pass_events": run["per_sweep_ms"],
+        "ms_per_step_with_kernel_events": run["elapsed_events"] / K * 1e3,
+        "pass_stage_ms": run["pass_stage_ms"],
+        "walk_roofline_frac": run["walk_roofline_frac"],
+        "roofline": run["roofline"],
     }
+    if "single_ms" in run:
+        result["ms_per_step_single_calls"] = run["single_ms"]
+    log(f"lidar {el / K * 1e3:.4f} ms/sweep, leaf {result['roofline']['frac']:.3f} of HBM peak")
+
+    if not args.no_render:
+        result["render"] = render_leg(sv, synth, torch, run["gmap"], run["scene"], (W + K) // 2)
+        log(f"render {result['render']}")
+    run["gmap"].close()
+
+    if not args.no_room:
+        result["room"] = room_leg(sv, synth, torch, dev)
+        log(f"room {result['room']}")
 
     if not args.no_diff:
-        result["fwd_bwd"] = diff_bench(sv, synth, torch, scene, reps=args.diff_reps)
+        result["fwd_bwd"] = diff_leg(sv, synth, torch, dev, run["scene"], reps=args.diff_reps)
         log(f"fwd+bwd {result['fwd_bwd']}")
 
     if not args.no_open:
-        result["open_set"] = open_bench(sv, synth, torch)
+        result["open_set"] = open_leg(sv, synth, torch, dev)
         log(f"open set {result['open_set']}")
 
     if not args.no_batched:
-        result["batched"] = batched_bench(sv, synth, torch)
+        result["batched"] = batched_leg(sv, synth, torch, dev)
         log(f"batched {result['batched']}")
 
     if args.copy_calib:
@@ -399,19 +575,7 @@ def main():
         del src, dst
 
     if not args.no_cpu:
-        import oracle  # test infrastructure: the CPU baseline leg only
-
-        o = oracle.OracleMap(vs, tau, 0.0, rmax, oracle.SEM_CLOSED, ncls)
-        done, tcpu = 0, 0.0
-        while done < len(sweeps) and tcpu < args.cpu_seconds:
-            s = sweeps[done]
-            c0 = time.perf_counter()
-            o.integrate(s["points"], s["pose"], s["label"], oracle.IN_LABEL_I32)
-            tcpu += time.perf_counter() - c0
-            done += 1
-        result["cpu_baseline"] = {"value": n_pts * done / tcpu, "unit": "points/s", "cores": 1, "kind": "oracle",
-                                  "sample": f"sweeps 0..{done - 1} of the same street ({done} x {n_pts} points), "
-                                            f"single-threaded FP64 oracle, {tcpu:.1f} s"}
+        result["cpu_baseline"] = cpu_leg(run["sweeps"], 0.1, 0.3, 50.0, 20, args.cpu_seconds)
     print(json.dumps(result), flush=True)
 
 

@@ -302,10 +302,10 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
  * statistics afterwards are the same as after count calls of slim_integrate /
  * slim_integrate_rays (bit for bit).  Geometry-only and label maps (int32
  * labels, at most 32 classes, Bayesian mode) take consecutive frames in
- * multi-frame passes (up to slim_launch_shape.pass_frames, default 2; the last
- * frame alone): one ray walk over all their rays, one plan, bucketing, leaf
- * kernel and commit, each voxel applying its frames' observations frame by
- * frame, Eq. (1)-(2) and Eq. (6) as for a frame alone.  This form returns after
+ * multi-frame passes (up to slim_launch_shape.pass_frames and at most 4,
+ * default 4; the last frame alone): one ray walk over all their rays, one
+ * plan, bucketing, leaf kernel and commit, each voxel applying its frames'
+ * observations frame by frame, Eq. (1)-(2) and Eq. (6) as for a frame alone.  This form returns after
  * the GPU has finished the call's work: a pass that exceeds the map's
  * capacity or staging table is not applied, and its frames and the later ones
  * are then integrated again one at a time, as per-frame calls would.  Other
@@ -321,25 +321,40 @@ slim_status slim_integrate_sequence(slim_map *map, const slim_frame *frames_host
 /* Grid sizes of the grid-stride kernels of integration: leaf planning and pair
  * bucketing blocks, and leaf-kernel blocks per compute unit (1 .. 32); and
  * pass_frames, the most frames slim_integrate_sequence takes in one pass
- * (0: the default 2, 1: one at a time, at most 8).  Results do not depend on
- * any of them (each voxel is reduced in frame and point order); they only move
- * time.  NULL restores the defaults.  Batched calls use the shape of maps[0]. */
+ * (0: the default 4, 1: one at a time, at most 8; passes take at most 4).
+ * Results do not depend on any of them (each voxel's sums are exact integers
+ * or formed in frame and point order); they only move time.  NULL restores
+ * the defaults.  Batched calls use the shape of maps[0]. */
 typedef struct slim_launch_shape {
     int32_t plan_blocks, bucket_blocks, leaf_blocks_per_cu, pass_frames;
 } slim_launch_shape;
 slim_status slim_set_launch_shape(slim_map *map, const slim_launch_shape *shape);
 
-/* Kernel timing.  While enabled, slim_integrate (and each pass of
- * slim_integrate_sequence) brackets each of its kernels
- * with HIP events on the stream it launches on; slim_profile_read returns the
- * accumulated per-kernel time in milliseconds and launch counts (index 0 ray
- * walk and pair emission, 1 leaf planning, 2 pair bucketing, 3 per-leaf sort,
- * reduce and combine, 4 commit) and resets them.  Reading synchronises
- * `stream`.  n_kernels is the length of ms_host and launches_host; the call
- * writes min(n_kernels, 5) entries. */
+/* Kernel timing (measurement support, not part of the method).  While
+ * enabled, slim_integrate (and each pass or single frame of
+ * slim_integrate_sequence) brackets each stage of integration with HIP events
+ * on the stream it launches on: index 0 ray walk and pair emission, 1 leaf
+ * planning, 2 pair bucketing, 3 leaf kernel (accumulation, or sort and
+ * combine), 4 wave-per-voxel combine (no kernel, and about zero time, for
+ * frames whose leaf kernel combines its voxels itself), 5 commit.
+ * slim_profile_read returns the accumulated per-stage time in milliseconds
+ * and launch counts and resets them; n_kernels is the length of ms_host and
+ * launches_host, and the call writes min(n_kernels, 6) entries.  Reading
+ * synchronises `stream`. */
 slim_status slim_profile_enable(slim_map *map, int32_t enable);
 slim_status slim_profile_read(slim_map *map, double *ms_host, int64_t *launches_host, int32_t n_kernels,
                               void *stream);
+
+/* The same timing per launch set (one slim_integrate call, or one pass or
+ * single frame of slim_integrate_sequence), oldest first, for the sets
+ * recorded since the previous call (at most 65536 are kept): frames_host[i]
+ * frames in set i, ms_host[6 i + k] the time of its stage k (indexed as
+ * slim_profile_read), span_ms_host[i] the time from the start of its first
+ * stage to the end of its last.  Writes min(capacity, *count_host) sets,
+ * *count_host receives the number recorded; clears the record.  Synchronises
+ * `stream`. */
+slim_status slim_profile_sets(slim_map *map, int32_t capacity, int32_t *frames_host, double *ms_host,
+                              double *span_ms_host, int32_t *count_host, void *stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *slim_last_error(void);

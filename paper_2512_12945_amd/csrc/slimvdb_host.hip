@@ -52,6 +52,7 @@ class DeviceGuard {
 };
 
 constexpr int kProfRing = 256;  // frames whose kernel events may be outstanding
+constexpr size_t kMaxProfSets = 1 << 16;  // launch sets kept for slim_profile_sets
 
 }  // namespace
 
@@ -68,7 +69,7 @@ struct BatchCtx {
     std::vector<long long> sig;   // what the captured graph was built for
 };
 
-constexpr int kDefaultPassFrames = 2;
+constexpr int kDefaultPassFrames = 4;
 
 struct slim_map {
     slim_map_config cfg;
@@ -98,8 +99,16 @@ struct slim_map {
     bool prof = false;
     std::vector<hipEvent_t> ev;  // kProfRing * 2 * kNumProfiled
     int prof_head = 0, prof_count = 0;
+    int prof_frames[kProfRing] = {};  // frames of each launch set in the ring
     double prof_ms[kNumProfiled] = {};
     long long prof_n[kNumProfiled] = {};
+    // per launch set, until slim_profile_sets reads them
+    struct ProfSet {
+        int frames;
+        double ms[kNumProfiled];
+        double span;
+    };
+    std::vector<ProfSet> prof_sets;
     hipError_t noalloc_err = hipSuccess;  // outcome of the scratch address setup at create
     // loss adjoints (allocated by the first slim_map_loss)
     float *adj = nullptr;
@@ -241,12 +250,19 @@ slim_status drain_profile(slim_map *m, bool wait)
         hipEvent_t *e = &m->ev[(size_t)slot * 2 * kNumProfiled];
         if (!wait && hipEventQuery(e[2 * kNumProfiled - 1]) != hipSuccess) break;
         HIP_OK(hipEventSynchronize(e[2 * kNumProfiled - 1]));
+        slim_map::ProfSet set;
+        set.frames = m->prof_frames[slot];
         for (int k = 0; k < kNumProfiled; ++k) {
             float ms = 0.0f;
             HIP_OK(hipEventElapsedTime(&ms, e[2 * k], e[2 * k + 1]));
             m->prof_ms[k] += ms;
             m->prof_n[k] += 1;
+            set.ms[k] = ms;
         }
+        float span = 0.0f;
+        HIP_OK(hipEventElapsedTime(&span, e[0], e[2 * kNumProfiled - 1]));
+        set.span = span;
+        if (m->prof_sets.size() < kMaxProfSets) m->prof_sets.push_back(set);
         m->prof_count--;
     }
     return SLIM_OK;
@@ -443,6 +459,7 @@ slim_status integrate_frame(slim_map *m, const FrameParams &fp, void *stream, co
             }
         }
         ev = &m->ev[(size_t)m->prof_head * 2 * kNumProfiled];
+        m->prof_frames[m->prof_head] = fp.nsub > 1 ? fp.nsub : 1;
         m->prof_head = (m->prof_head + 1) % kProfRing;
         m->prof_count++;
     }
@@ -1149,6 +1166,29 @@ slim_status slim_profile_read(slim_map *m, double *ms, int64_t *launches, int32_
         m->prof_ms[k] = 0.0;
         m->prof_n[k] = 0;
     }
+    return SLIM_OK;
+}
+
+slim_status slim_profile_sets(slim_map *m, int32_t capacity, int32_t *frames, double *ms, double *span_ms,
+                              int32_t *count, void *stream)
+{
+    g_err[0] = 0;
+    if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
+    if (!count || capacity < 0 || (capacity > 0 && (!frames || !ms || !span_ms)))
+        return fail(SLIM_ERR_INVALID, "bad output arrays");
+    DeviceGuard g(m->cfg.device);
+    HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    slim_status r = drain_profile(m, true);
+    if (r) return r;
+    const int n = (int)m->prof_sets.size();
+    *count = n;
+    for (int i = 0; i < std::min(n, capacity); ++i) {
+        const slim_map::ProfSet &ps = m->prof_sets[(size_t)i];
+        frames[i] = ps.frames;
+        for (int k = 0; k < kNumProfiled; ++k) ms[(size_t)i * kNumProfiled + k] = ps.ms[k];
+        span_ms[i] = ps.span;
+    }
+    m->prof_sets.clear();
     return SLIM_OK;
 }
 

@@ -2509,11 +2509,13 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const La
     rec(6);
     const int kind = leaf_kernel_kind(fp);
     launch_leaf(kind, fp, md, shape.leaf_blocks, s);
-    launch_voxel_combine(kind, fp, md, shape.leaf_blocks, s);
     rec(7);
     rec(8);
-    hipLaunchKernelGGL(k_frame_commit, dim3(1), dim3(256), 0, s, fp, md);
+    launch_voxel_combine(kind, fp, md, shape.leaf_blocks, s);
     rec(9);
+    rec(10);
+    hipLaunchKernelGGL(k_frame_commit, dim3(1), dim3(256), 0, s, fp, md);
+    rec(11);
     return hipGetLastError();
 }
 

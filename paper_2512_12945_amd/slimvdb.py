@@ -18,14 +18,14 @@ LIB_PATH = os.path.join(HERE, "libslimvdb.so")
 OK, ERR_INVALID, ERR_CAPACITY, ERR_DEVICE, ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 SEM_NONE, SEM_CLOSED, SEM_OPEN, SEM_CLOSED_LAST, SEM_OPEN_LAST = 0, 1, 2, 3, 4
 IN_NONE, IN_LABEL_I32, IN_PROB_F32, IN_LOGIT_F32, IN_EMB_BF16, IN_EMB_F32 = range(6)
-KERNELS = ("ray_walk_emit", "leaf_plan", "pair_bucket", "leaf_fuse", "frame_commit")
+KERNELS = ("ray_walk_emit", "leaf_plan", "pair_bucket", "leaf_fuse", "voxel_combine", "frame_commit")
 
 EXPORTS = ("slim_map_create", "slim_map_destroy", "slim_map_reset", "slim_integrate", "slim_integrate_rays",
            "slim_integrate_depth",
            "slim_map_stats", "slim_extract", "slim_extract_noalloc", "slim_query", "slim_predict", "slim_render", "slim_map_loss",
            "slim_backward_rays",
            "slim_integrate_batched", "slim_integrate_sequence", "slim_set_launch_shape", "slim_profile_enable",
-           "slim_profile_read",
+           "slim_profile_read", "slim_profile_sets",
            "slim_last_error")
 
 
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
         L.slim_set_launch_shape.argtypes = [vp, ctypes.POINTER(LaunchShape)]
         L.slim_profile_enable.argtypes = [vp, i32]
         L.slim_profile_read.argtypes = [vp, vp, vp, i32, vp]
+        L.slim_profile_sets.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(i32), vp]
         L.slim_last_error.restype = ctypes.c_char_p
         for f in EXPORTS[:-1]:
             getattr(L, f).restype = i32
@@ -260,6 +261,18 @@ class Map:
 
     def profile(self, enable=True):
         _check(self._L.slim_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_sets(self, capacity=1 << 16):
+        """Per launch set since the last call: list of (frames, {kernel: ms}, span_ms)."""
+        fr = np.zeros(capacity, np.int32)
+        ms = np.zeros((capacity, len(KERNELS)), np.float64)
+        sp = np.zeros(capacity, np.float64)
+        cnt = ctypes.c_int32()
+        _check(self._L.slim_profile_sets(self.h, capacity, fr.ctypes.data_as(ctypes.c_void_p),
+                                         ms.ctypes.data_as(ctypes.c_void_p), sp.ctypes.data_as(ctypes.c_void_p),
+                                         ctypes.byref(cnt), _stream(self.device)))
+        n = min(cnt.value, capacity)
+        return [(int(fr[i]), dict(zip(KERNELS, ms[i].tolist())), float(sp[i])) for i in range(n)]
 
     def profile_read(self):
         ms = np.zeros(len(KERNELS), np.float64)

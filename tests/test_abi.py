@@ -78,6 +78,8 @@ def test_null_arguments():
     assert L.slim_extract_noalloc(None, 0, None, None, None, None, ctypes.byref(cnt), None) == sv.ERR_INVALID
     assert L.slim_query(None, None, 0, None, None, None, None) == sv.ERR_INVALID
     assert L.slim_profile_enable(None, 1) == sv.ERR_INVALID
+    cnt32 = ctypes.c_int32()
+    assert L.slim_profile_sets(None, 0, None, None, None, ctypes.byref(cnt32), None) == sv.ERR_INVALID
     assert L.slim_map_destroy(None) == sv.OK
 
 

@@ -172,16 +172,24 @@ def test_sequence_passes_with_kernel_timing(sweeps):
     ref, seq = _map(), _map()
     for f in sweeps:
         ref.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+    seq.set_launch_shape(pass_frames=2)
     seq.profile(True)
     seq.profile_read()
+    seq.profile_sets()
     sv.integrate_sequence(seq, sweeps)
     kern = seq.profile_read()
+    sets = seq.profile_sets()
     seq.profile(False)
     assert ref.stats() == seq.stats()
     _same(extract_np(ref), extract_np(seq))
     # 9 frames in passes of 2 with the last alone: 4 passes + 1 single frame
     assert all(n == 5 for _, n in kern.values()), kern
-    assert all(ms > 0 for ms, _ in kern.values()), kern
+    # label frames combine inside the leaf kernel: the voxel-combine stage is empty
+    assert all(ms > 0 for k, (ms, _) in kern.items() if k != "voxel_combine"), kern
+    assert [f for f, _, _ in sets] == [2, 2, 2, 2, 1], sets
+    for f, ms, span in sets:
+        assert span >= max(ms.values()) > 0
+    assert abs(sum(ms["leaf_fuse"] for _, ms, _ in sets) - kern["leaf_fuse"][0]) <= 1e-6 * kern["leaf_fuse"][0] + 1e-9
 
 
 def test_sequence_probability_rows_and_mixed_kinds(sweeps):
