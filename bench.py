@@ -387,7 +387,7 @@ def batched_leg(sv, synth, torch, dev, reps=10):
                                                                 "slimvdb_autotune.json"), log=log)
     maps = [sv.Map(**c) for c in cfgs]
     for m in maps:
-        m.set_launch_shape(*shape)
+        m.set_launch_shape(**shape)
     torch.cuda.synchronize()
     s0 = time.perf_counter()
     sv.integrate_batched(maps, frames, use_graph=False)
@@ -412,6 +412,11 @@ def batched_leg(sv, synth, torch, dev, reps=10):
     t_seq = timed(sequential)
     t_eager = timed(lambda: sv.integrate_batched(maps, frames, use_graph=False))
     t_graph = timed(lambda: sv.integrate_batched(maps, frames, use_graph=True))
+    # the other batched form with the same split and tiles, for comparison
+    other = 2 if shape["batch_mode"] == 1 else 1
+    maps[0].set_launch_shape(**dict(shape, batch_mode=other))
+    t_other = timed(lambda: sv.integrate_batched(maps, frames, use_graph=True))
+    maps[0].set_launch_shape(**shape)
     st = [m.stats() for m in maps]
     npts = sum(x["n"] for x in w)
     pairs = sum(s["pairs_last"] for s in st)
@@ -420,9 +425,10 @@ def batched_leg(sv, synth, torch, dev, reps=10):
         m.close()
     return {"workload": "32 maps, one street-sweep frame each with 10k-130k rays (128 beams); 16 maps 20-class "
                         "int32 labels, 16 maps 256-d bf16 embeddings; voxel 0.1 m, trunc 0.3 m; steady state",
-            "points": npts, "pairs": pairs, "launch_shape": list(shape),
+            "points": npts, "pairs": pairs, "launch_shape": shape,
             "first_launch_ms": t_first, "sequential_ms": t_seq, "batched_ms": t_eager, "batched_graph_ms": t_graph,
             "speedup_graph_vs_sequential": t_seq / t_graph,
+            ("per_stage_graph_ms" if other == 2 else "persistent_graph_ms"): t_other,
             "points_per_s_graph": npts / (t_graph / 1e3), "alg_bytes": b_alg,
             "path_roofline_frac_graph": b_alg / (t_graph / 1e3) / 1e9 / HBM_PEAK_GBS}
 

@@ -287,12 +287,14 @@ typedef struct slim_frame {
 } slim_frame;
 
 /* Integrates frames[i] into maps[i] for i < nmaps, for maps of any mix of
- * modes, classes and embedding sizes on one device, as one launch per kernel
- * stage for all maps (six launches in all) instead of five per map.  Results
- * are identical to nmaps calls of slim_integrate.  With use_graph != 0 the
- * launches are captured once into a HIP graph, which later calls with the same
- * maps, the same per-map walk grid (ceil(n_i / 256) blocks) and the same launch
- * shape replay; point counts, poses and buffers may change between replays.
+ * modes, classes and embedding sizes on one device, as one persistent launch
+ * for all maps (or, by slim_launch_shape.batch_mode, one launch per kernel
+ * stage for all maps) instead of six per map.  Results are identical to nmaps
+ * calls of slim_integrate.  With use_graph != 0 the work is captured once into
+ * a HIP graph (the descriptor copy and the launch), which later calls with the
+ * same maps, the same per-map walk grid (ceil(n_i / 256) blocks) and the same
+ * launch shape replay; point counts, poses and buffers may change between
+ * replays.
  * Maps must be distinct.  The launch resources belong to maps[0] (the first
  * call allocates them, synchronising).  Queued on `stream`. */
 slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const slim_frame *frames, int32_t use_graph,
@@ -322,11 +324,23 @@ slim_status slim_integrate_sequence(slim_map *map, const slim_frame *frames_host
  * bucketing blocks, and leaf-kernel blocks per compute unit (1 .. 32); and
  * pass_frames, the most frames slim_integrate_sequence takes in one pass
  * (0: the default 4, 1: one at a time, at most 8; passes take at most 4).
+ * batch_mode picks the form of slim_integrate_batched: 1 one persistent launch
+ * whose workgroups take ray-chunk, planning, bucketing, leaf-tile, combine and
+ * commit items of every map from a queue, 2 one launch per stage, 0 the
+ * default (1).  In the persistent launch the three grid sizes are the numbers
+ * of planning, bucketing and leaf-tile (and combine) items of the whole batch,
+ * shared between the maps in proportion to their rays, and walk_chunk is the
+ * size of a ray-chunk item in blocks of 256 rays (1 .. 64, 0: the default 4).
+ * Leaf tiles: a touched leaf with at most wave_pairs pairs is one wave's work
+ * (16 .. 256, capped at 128 for accumulated frames; 0: the cap), and a sorted
+ * leaf with more than slab_pairs pairs is split into one item per x-slab
+ * (512 .. 2048; 0: 2048, what the leaf kernel's LDS holds).
  * Results do not depend on any of them (each voxel's sums are exact integers
  * or formed in frame and point order); they only move time.  NULL restores
  * the defaults.  Batched calls use the shape of maps[0]. */
 typedef struct slim_launch_shape {
     int32_t plan_blocks, bucket_blocks, leaf_blocks_per_cu, pass_frames;
+    int32_t batch_mode, walk_chunk, wave_pairs, slab_pairs;
 } slim_launch_shape;
 slim_status slim_set_launch_shape(slim_map *map, const slim_launch_shape *shape);
 

@@ -205,6 +205,10 @@ struct MapDev {
     uint4 *vox_list;      // wave-combine voxels: (record, pairs | existed << 31, first sorted pair, 0)
     uint2 *blk_stats;     // per leaf-kernel block: (voxels updated that existed, voxels created)
     int leaf_blocks;      // grid of the leaf kernel of the current frame (<= kMaxLeafBlocksPerCu * CUs)
+    // leaf tiles of the current frame: leaves with at most wave_pairs pairs are
+    // one wave's work, sorted leaves with more than slab_pairs pairs are split
+    // into x-slab items (0: the largest the kernels hold)
+    int wave_pairs, slab_pairs;
     DevState *st;
     FrameState *fs;       // the staging buffer's frame counters
     long long max_leaves, max_pages;
@@ -219,11 +223,16 @@ struct MapBatch {
     int nmaps, nsubset;
 };
 
-// Grid sizes of the grid-stride kernels (results do not depend on them).
+// Grid sizes of the grid-stride kernels, and the work split of the persistent
+// batched launch (results do not depend on any of them).
 struct LaunchShape {
     int plan_blocks;    // leaf planning
     int bucket_blocks;  // pair bucketing
     int leaf_blocks;    // per-leaf sort and combine (also the size of blk_stats in use)
+    int persistent;     // batched calls: 1 one persistent launch, 0 one launch per stage
+    int walk_chunk;     // persistent: walk blocks (256 rays each) per ray-chunk item
+    int wave_pairs;     // leaf tiles (MapDev::wave_pairs, slab_pairs)
+    int slab_pairs;
 };
 
 // Host view of a batched launch: the leaf kernel is launched once per group of
@@ -238,8 +247,31 @@ struct BatchPlan {
 
 constexpr int kLeafKinds = 17;  // variants of the leaf kernel (leaf_kernel_kind)
 int leaf_kernel_kind(const FrameParams &fp);
+__host__ __device__ int voxel_combine_arg(int kind);
 hipError_t launch_integrate_batched(const MapBatch &mb, const BatchPlan &plan, const LaunchShape &shape,
                                     hipStream_t s);
+
+// Persistent batched launch: work items (uint4) taken from a queue in order,
+//   x = map | stage << 16 | leaf-kernel variant << 24,
+//   y, z = first walk block and walk blocks (stage 0), or item index and items
+//          of the stage for the map (grid-stride stages),
+//   w = the counter to wait for | its target << 16, or kPersistNoDep;
+// and a control block of uint32 words, zero at launch:
+//   [0] next item, [1] abort flag, [2 + map * kPersistStages + stage] finished items.
+constexpr int kPersistStages = 6;  // walk, planning, bucketing, leaf kernel, voxel combine, commit
+constexpr uint32_t kPersistEnd = 0xFFFFFFFFu;
+constexpr uint32_t kPersistNoDep = 0xFFFFFFFFu;
+constexpr int kPersistCtlAbort = 1;
+constexpr int kPersistCtlDone = 2;
+struct PersistArgs {
+    const MapDev *mds;
+    const FrameParams *fps;
+    const uint4 *items;
+    uint32_t *ctl;
+    uint32_t nitems;
+};
+int persistent_blocks_per_cu();
+hipError_t launch_integrate_persistent(const PersistArgs &a, int blocks, hipStream_t s);
 
 __host__ __device__ inline unsigned long long pack_leaf(int lx, int ly, int lz)
 {

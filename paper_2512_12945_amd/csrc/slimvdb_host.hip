@@ -67,16 +67,23 @@ struct BatchCtx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<long long> sig;   // what the captured graph was built for
+    int persist_blocks = 0;       // workgroups of the persistent launch (all resident)
 };
 
 constexpr int kDefaultPassFrames = 4;
+constexpr int kMaxWalkChunk = 64;
+
+static LaunchShape default_shape(int cus)
+{
+    return {cus, cus * 16, cus * 8, 1, 4, 0, 0};
+}
 
 struct slim_map {
     slim_map_config cfg;
     int nsem = 0;
     int maxsteps = 0;
     int cus = 256;
-    LaunchShape shape = {256, 4096, 2048};
+    LaunchShape shape = default_shape(256);
     int pass_frames = kDefaultPassFrames;  // frames slim_integrate_sequence integrates in one pass
     BatchCtx *batch = nullptr;
     MapDev md = {};
@@ -304,7 +311,7 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, config->device) == hipSuccess && prop.multiProcessorCount > 0)
         m->cus = prop.multiProcessorCount;
-    m->shape = {m->cus, m->cus * 16, m->cus * 8};
+    m->shape = default_shape(m->cus);
 
     MapDev &md = m->md;
     md.hmask = (uint32_t)(cap - 1);
@@ -312,6 +319,8 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
     md.max_pages = (config->max_voxels + kPageVoxels - 1) / kPageVoxels;
     md.rec_stride = record_stride(m->nsem);
     md.leaf_blocks = m->cus * 8;
+    md.wave_pairs = 0;
+    md.slab_pairs = 0;
     const size_t L = (size_t)config->max_leaves, NP = (size_t)md.max_pages;
     if ((r = dalloc(m, &md.htab, cap)) || (r = dalloc(m, &md.skeys, cap)) ||
         (r = dalloc(m, &md.touched, cap)) || (r = dalloc(m, &md.touched_key, cap)) ||
@@ -998,16 +1007,22 @@ slim_status slim_set_launch_shape(slim_map *m, const slim_launch_shape *shape)
     g_err[0] = 0;
     if (!m) return fail(SLIM_ERR_INVALID, "map is NULL");
     if (!shape) {
-        m->shape = {m->cus, m->cus * 16, m->cus * 8};
+        m->shape = default_shape(m->cus);
         m->pass_frames = kDefaultPassFrames;
         return SLIM_OK;
     }
     if (shape->plan_blocks < 1 || shape->bucket_blocks < 1 || shape->leaf_blocks_per_cu < 1 ||
         shape->plan_blocks > 65536 || shape->bucket_blocks > 65536 ||
         shape->leaf_blocks_per_cu > kMaxLeafBlocksPerCu || shape->pass_frames < 0 ||
-        shape->pass_frames > kPassFrames)
+        shape->pass_frames > kPassFrames || shape->batch_mode < 0 || shape->batch_mode > 2 ||
+        shape->walk_chunk < 0 || shape->walk_chunk > kMaxWalkChunk ||
+        (shape->wave_pairs != 0 && (shape->wave_pairs < 16 || shape->wave_pairs > 256)) ||
+        (shape->slab_pairs != 0 && (shape->slab_pairs < 512 || shape->slab_pairs > 2048)))
         return fail(SLIM_ERR_INVALID, "launch shape out of range");
-    m->shape = {shape->plan_blocks, shape->bucket_blocks, shape->leaf_blocks_per_cu * m->cus};
+    const LaunchShape d = default_shape(m->cus);
+    m->shape = {shape->plan_blocks, shape->bucket_blocks, shape->leaf_blocks_per_cu * m->cus,
+                shape->batch_mode == 0 ? d.persistent : (shape->batch_mode == 1 ? 1 : 0),
+                shape->walk_chunk > 0 ? shape->walk_chunk : d.walk_chunk, shape->wave_pairs, shape->slab_pairs};
     m->pass_frames = shape->pass_frames > 0 ? shape->pass_frames : kDefaultPassFrames;
     return SLIM_OK;
 }
@@ -1042,6 +1057,8 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
         if (r) return r;
         mds[i] = maps[i]->md;
         mds[i].leaf_blocks = m0->shape.leaf_blocks;
+        mds[i].wave_pairs = m0->shape.wave_pairs;
+        mds[i].slab_pairs = m0->shape.slab_pairs;
         start[i + 1] = start[i] + (int)std::max<int64_t>(1, (f.n + kWalkThreads - 1) / kWalkThreads);
         kinds[i] = leaf_kernel_kind(fps[i]);
     }
@@ -1059,10 +1076,60 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
             plan.ngroups++;
         }
     }
-    // descriptor: [MapDev x n][FrameParams x n][walk_start x n+1][subset x n], 16-byte aligned pieces
+    const LaunchShape shape = m0->shape;
+    // persistent launch: the work items of every map, stage after stage; the
+    // planning, bucketing and leaf-tile items of the batch are shared between
+    // the maps in proportion to their walk blocks (so the item list, like the
+    // graph, depends only on the walk grid, the variants and the shape)
+    std::vector<uint4> items;
+    if (shape.persistent) {
+        std::vector<uint32_t> cnt((size_t)nmaps * kPersistStages, 0u);
+        const long long wtot = start[nmaps];
+        const uint32_t leaf_cap = (uint32_t)m0->cus * kMaxLeafBlocksPerCu;
+        auto share = [&](int total, int i, uint32_t cap) {
+            const long long wb = start[i + 1] - start[i];
+            const long long c = ((long long)total * wb + wtot - 1) / wtot;
+            return (uint32_t)std::max<long long>(1, std::min<long long>(c, cap));
+        };
+        for (int i = 0; i < nmaps; ++i) {
+            uint32_t *c = &cnt[(size_t)i * kPersistStages];
+            const int wb = start[i + 1] - start[i];
+            c[0] = (uint32_t)((wb + shape.walk_chunk - 1) / shape.walk_chunk);
+            c[1] = share(shape.plan_blocks, i, 0xFFFFu);
+            c[2] = share(shape.bucket_blocks, i, 0xFFFFu);
+            c[3] = share(shape.leaf_blocks, i, leaf_cap);
+            c[4] = voxel_combine_arg(kinds[i]) != -2 ? share(shape.leaf_blocks, i, 0xFFFFu) : 0u;
+            c[5] = 1;
+            // the commit sums the statistics of this many leaf-tile items
+            mds[i].leaf_blocks = (int)c[3];
+        }
+        for (int st = 0; st < kPersistStages; ++st)
+            for (int i = 0; i < nmaps; ++i) {
+                const uint32_t *c = &cnt[(size_t)i * kPersistStages];
+                int dep = st - 1;
+                while (dep >= 0 && c[dep] == 0) --dep;
+                const uint32_t w = dep < 0 ? kPersistNoDep
+                                           : (uint32_t)(i * kPersistStages + dep) | (c[dep] << 16);
+                const uint32_t x = (uint32_t)i | ((uint32_t)st << 16) | ((uint32_t)kinds[i] << 24);
+                const uint32_t wb = (uint32_t)(start[i + 1] - start[i]);
+                for (uint32_t j = 0; j < c[st]; ++j) {
+                    if (st == 0) {
+                        const uint32_t b0 = j * (uint32_t)shape.walk_chunk;
+                        items.push_back(make_uint4(x, b0, std::min<uint32_t>(shape.walk_chunk, wb - b0), w));
+                    } else {
+                        items.push_back(make_uint4(x, j, c[st], w));
+                    }
+                }
+            }
+    }
+    const uint32_t nitems = (uint32_t)items.size();
+    const size_t nctl = shape.persistent ? (size_t)kPersistCtlDone + (size_t)nmaps * kPersistStages : 0;
+    // descriptor: [MapDev x n][FrameParams x n][walk_start x n+1][subset x n]
+    // [work items][control block, zero], 16-byte aligned pieces
     auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
     const size_t o_fp = al(sizeof(MapDev) * nmaps), o_ws = o_fp + al(sizeof(FrameParams) * nmaps);
-    const size_t o_sub = o_ws + al(sizeof(int) * (nmaps + 1)), bytes = o_sub + al(sizeof(int) * nmaps);
+    const size_t o_sub = o_ws + al(sizeof(int) * (nmaps + 1)), o_it = o_sub + al(sizeof(int) * nmaps);
+    const size_t o_ctl = o_it + al(sizeof(uint4) * nitems), bytes = o_ctl + al(sizeof(uint32_t) * nctl);
 
     if (!m0->batch) m0->batch = new BatchCtx();
     BatchCtx *b = m0->batch;
@@ -1091,6 +1158,8 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
     memcpy(st + o_fp, fps.data(), sizeof(FrameParams) * nmaps);
     memcpy(st + o_ws, start.data(), sizeof(int) * (nmaps + 1));
     memcpy(st + o_sub, subset.data(), sizeof(int) * nmaps);
+    if (nitems) memcpy(st + o_it, items.data(), sizeof(uint4) * nitems);
+    if (nctl) memset(st + o_ctl, 0, sizeof(uint32_t) * nctl);
     char *dv = (char *)b->dev;
     MapBatch mb;
     mb.mds = (const MapDev *)dv;
@@ -1099,16 +1168,29 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
     mb.subset = (const int *)(dv + o_sub);
     mb.nmaps = nmaps;
     mb.nsubset = nmaps;
-    const LaunchShape shape = m0->shape;
+    PersistArgs pa;
+    pa.mds = mb.mds;
+    pa.fps = mb.fps;
+    pa.items = (const uint4 *)(dv + o_it);
+    pa.ctl = (uint32_t *)(dv + o_ctl);
+    pa.nitems = nitems;
+    if (shape.persistent && !b->persist_blocks) b->persist_blocks = persistent_blocks_per_cu() * m0->cus;
+    // the control block is zeroed by the descriptor copy itself (no memset in the graph)
+    auto launch = [&](hipStream_t q) {
+        return shape.persistent ? launch_integrate_persistent(pa, b->persist_blocks, q)
+                                : launch_integrate_batched(mb, plan, shape, q);
+    };
 
     if (!use_graph) {
         HIP_OK(hipMemcpyAsync(b->dev, b->staging, bytes, hipMemcpyHostToDevice, s));
-        HIP_OK(launch_integrate_batched(mb, plan, shape, s));
+        HIP_OK(launch(s));
     } else {
-        // the graph holds grid sizes and the grouping; everything else is read
-        // from the descriptor, which the graph copies in at each replay
+        // the graph holds grid sizes, the grouping and the item count;
+        // everything else is read from the descriptor, which the graph copies
+        // in at each replay
         std::vector<long long> sig = {nmaps, (long long)bytes, shape.plan_blocks, shape.bucket_blocks,
-                                      shape.leaf_blocks};
+                                      shape.leaf_blocks, shape.persistent, shape.walk_chunk, shape.wave_pairs,
+                                      shape.slab_pairs, nitems};
         for (int i = 0; i <= nmaps; ++i) sig.push_back(start[i]);
         for (int i = 0; i < nmaps; ++i) sig.push_back(kinds[i]);
         if (sig != b->sig || !b->exec) {
@@ -1120,7 +1202,7 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
             if (!b->cap_stream) HIP_OK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
             HIP_OK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
             hipError_t e1 = hipMemcpyAsync(b->dev, b->staging, bytes, hipMemcpyHostToDevice, b->cap_stream);
-            hipError_t e2 = launch_integrate_batched(mb, plan, shape, b->cap_stream);
+            hipError_t e2 = launch(b->cap_stream);
             hipGraph_t graph = nullptr;
             hipError_t e3 = hipStreamEndCapture(b->cap_stream, &graph);
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {

@@ -330,17 +330,24 @@ __device__ __forceinline__ uint32_t stage_leaf_cas(const MapDev &md, unsigned lo
     return kNoPos;
 }
 
+// Block-local table of the leaves a walk block's rays touch.
+struct WalkShared {
+    unsigned long long t_key[kWalkTable];
+    uint32_t t_cnt[kWalkTable];   // pairs of this block in the leaf, then their first bucket rank
+    uint32_t t_pos[kWalkTable];   // staging position
+    uint32_t t_slab[kWalkTable];  // x-slabs of the leaf this block touches
+    uint32_t t_list[kWalkTable];  // occupied entries
+    uint32_t t_fresh[kWalkTable]; // entries whose staging insert this block made
+    uint32_t s_n, s_nfresh, s_pair_base, wsum[4];
+};
+
 // One block of the walk: rays blk * blockDim.x + [0, blockDim.x) of a frame.
-__device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const MapDev &md, int blk)
+__device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const MapDev &md, int blk, WalkShared &ws)
 {
-    // block-local table of the leaves this block's rays touch
-    __shared__ unsigned long long t_key[kWalkTable];
-    __shared__ uint32_t t_cnt[kWalkTable];   // pairs of this block in the leaf, then their first bucket rank
-    __shared__ uint32_t t_pos[kWalkTable];   // staging position
-    __shared__ uint32_t t_slab[kWalkTable];  // x-slabs of the leaf this block touches
-    __shared__ uint32_t t_list[kWalkTable];  // occupied entries
-    __shared__ uint32_t t_fresh[kWalkTable]; // entries whose staging insert this block made
-    __shared__ uint32_t s_n, s_nfresh, s_pair_base, wsum[4];
+    unsigned long long *t_key = ws.t_key;
+    uint32_t *t_cnt = ws.t_cnt, *t_pos = ws.t_pos, *t_slab = ws.t_slab, *t_list = ws.t_list, *t_fresh = ws.t_fresh;
+    uint32_t &s_n = ws.s_n, &s_nfresh = ws.s_nfresh, &s_pair_base = ws.s_pair_base;
+    uint32_t *wsum = ws.wsum;
 
     const int tid = threadIdx.x;
     const int i = blk * blockDim.x + tid;
@@ -557,7 +564,8 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
 
 __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit(FrameParams fp, MapDev md)
 {
-    walk_emit_block(fp, md, blockIdx.x);
+    __shared__ WalkShared ws;
+    walk_emit_block(fp, md, blockIdx.x, ws);
 }
 
 // Map of a block of a batched launch (frame of a multi-frame pass): the last i
@@ -575,15 +583,17 @@ __device__ __forceinline__ int batch_map(const int *start, int nmaps, int blk)
 
 __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit_batch(MapBatch mb)
 {
+    __shared__ WalkShared ws;
     const int i = batch_map(mb.walk_start, mb.nmaps, blockIdx.x);
-    walk_emit_block(mb.fps[i], mb.mds[i], blockIdx.x - mb.walk_start[i]);
+    walk_emit_block(mb.fps[i], mb.mds[i], blockIdx.x - mb.walk_start[i], ws);
 }
 
 // The rays of every frame of a multi-frame pass into one staging buffer.
 __global__ __launch_bounds__(kWalkThreads) void k_ray_walk_emit_pass(PassWalk pw, MapDev md)
 {
+    __shared__ WalkShared ws;
     const int f = batch_map(pw.blk_start, pw.nframes, blockIdx.x);
-    walk_emit_block(pw.fp[f], md, blockIdx.x - pw.blk_start[f]);
+    walk_emit_block(pw.fp[f], md, blockIdx.x - pw.blk_start[f], ws);
 }
 
 // Frame (within a multi-frame pass) of sort-key point index p.
@@ -613,8 +623,9 @@ __device__ __forceinline__ void leaf_plan_range(const FrameParams &fp, const Map
     // LDS holds into x-slab items and gives a wave leaves of up to
     // kWaveItemPairs pairs; the accumulating one takes every leaf whole
     const bool acc = accum_path(fp);
-    const uint32_t big_lim = acc ? 0xFFFFFFFFu : (uint32_t)kLeafLdsPairs;
-    const uint32_t small_lim = acc ? (uint32_t)kAccWavePairs : (uint32_t)kWaveItemPairs;
+    const uint32_t slab_cap = (uint32_t)kLeafLdsPairs, wave_cap = acc ? (uint32_t)kAccWavePairs : (uint32_t)kWaveItemPairs;
+    const uint32_t big_lim = acc ? 0xFFFFFFFFu : (md.slab_pairs > 0 ? min((uint32_t)md.slab_pairs, slab_cap) : slab_cap);
+    const uint32_t small_lim = md.wave_pairs > 0 ? min((uint32_t)md.wave_pairs, wave_cap) : wave_cap;
     const uint32_t nt = md.fs->n_touched.v;
     const unsigned long long pused = md.st->pages_used;
     const uint32_t stride = nblk * blockDim.x;
@@ -655,7 +666,7 @@ __device__ __forceinline__ void leaf_plan_range(const FrameParams &fp, const Map
         const bool med = act && !big && !small;
         // the larger workgroup and wave leaves are listed from the front of
         // their arrays, the smaller ones from the back
-        const bool medf = med && npairs > (uint32_t)kLeafLdsPairs / 2, medb = med && !medf;
+        const bool medf = med && npairs > min(big_lim, slab_cap) / 2, medb = med && !medf;
         const bool smallf = small && npairs > small_lim / 4, smallb = small && !smallf;
         // eight reservations with six atomics in flight together (two list
         // counters share each 64-bit word)
@@ -2216,10 +2227,11 @@ __device__ __forceinline__ void voxel_combine_range(const FrameParams &fp, const
 {
     const uint32_t nv = md.fs->n_vox.v;
     const uint32_t nw = blockDim.x >> 6, w = threadIdx.x >> 6;
-    // blocks are dealt to the 8 XCDs round robin: give each XCD a contiguous share
-    const uint32_t per_xcd = (nblk + 7) / 8;
-    const uint32_t vb = (blk % 8) * per_xcd + blk / 8;
-    if (vb >= nblk) return;
+    // blocks are dealt to the 8 XCDs round robin: give each XCD a contiguous
+    // share (XCD r holds the nblk / 8 blocks, plus one if r < nblk % 8, whose
+    // index is r modulo 8; a one-to-one map of [0, nblk) for any nblk)
+    const uint32_t r = blk % 8, q = nblk / 8, m = nblk % 8;
+    const uint32_t vb = r * q + min(r, m) + blk / 8;
     for (uint32_t v = vb * nw + w; v < nv; v += nblk * nw) {
         const uint4 d = md.vox_list[v];
         const uint32_t n = d.y & 0x7FFFFFFFu;
@@ -2254,9 +2266,13 @@ __global__ __launch_bounds__(256) void k_voxel_combine_batch(MapBatch mb)
 // 5. commit (one workgroup)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const MapDev &md)
+struct CommitShared {
+    unsigned long long s_old[256], s_new[256];
+};
+
+__device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const MapDev &md, CommitShared &cs)
 {
-    __shared__ unsigned long long s_old[256], s_new[256];
+    unsigned long long *s_old = cs.s_old, *s_new = cs.s_new;
     DevState *st = md.st;
     // the frame's counters and the map's state are read together with the
     // per-block statistics (one round trip for all of them)
@@ -2342,12 +2358,260 @@ __device__ __forceinline__ void frame_commit_block(const FrameParams &fp, const 
 
 __global__ __launch_bounds__(256) void k_frame_commit(FrameParams fp, MapDev md)
 {
-    frame_commit_block(fp, md);
+    __shared__ CommitShared cs;
+    frame_commit_block(fp, md, cs);
 }
 
 __global__ __launch_bounds__(256) void k_frame_commit_batch(MapBatch mb)
 {
-    frame_commit_block(mb.fps[blockIdx.x], mb.mds[blockIdx.x]);
+    __shared__ CommitShared cs;
+    frame_commit_block(mb.fps[blockIdx.x], mb.mds[blockIdx.x], cs);
+}
+
+// ---------------------------------------------------------------------------
+// 6. the persistent batched launch
+// ---------------------------------------------------------------------------
+//
+// One launch integrates one frame into each of many maps.  Its workgroups stay
+// resident and take work items from an integer queue in order: the ray-chunk
+// items of every map's walk, then every map's planning, bucketing, leaf-tile,
+// voxel-combine and commit items.  An item of a stage starts once all items of
+// the previous stage of the same map have finished (a per-map, per-stage
+// counter), so the stages of different maps overlap and a large frame does
+// not hold up a small one.  Items are taken in queue order and an item only
+// waits for items earlier in the queue, which are held by running workgroups:
+// the queue always drains, whatever the number of workgroups.  Every item runs
+// the same code as the per-stage kernels, so the maps are bitwise the same as
+// after the per-stage launches (and the per-map calls).
+
+// Leaf-kernel variants whose voxels are combined by k_voxel_combine (one wave
+// per voxel), with that kernel's template argument; -2: combined in the leaf kernel.
+__host__ __device__ int voxel_combine_arg(int kind)
+{
+    switch (kind) {
+    case 8: return 0;
+    case 10: return -1;
+    case 11: return 1;
+    case 12: return 2;
+    case 13: return 4;
+    case 14: return 8;
+    case 15: return 16;
+    default: return -2;
+    }
+}
+
+static_assert(kWalkThreads == 256 && kLeafThreads == 256, "persistent items assume 256-thread workgroups");
+
+union PersistShared {
+    WalkShared walk;
+    LeafShared leaf;
+    AccShared<0, 1> acc0;
+    AccShared<8, 1> acc8;
+    AccShared<16, 1> acc16;
+    AccShared<24, 1> acc24;
+    AccShared<32, 1> acc32;
+    CommitShared commit;
+};
+// The launch's LDS, one copy per workgroup, named directly by the stage
+// functions below (a reference passed to a called function would lose its
+// address space).
+static __shared__ PersistShared g_ps;
+
+template <int KMAX>
+__device__ __forceinline__ AccShared<KMAX, 1> &persist_acc_lds()
+{
+    if constexpr (KMAX == 0) return g_ps.acc0;
+    else if constexpr (KMAX == 8) return g_ps.acc8;
+    else if constexpr (KMAX == 16) return g_ps.acc16;
+    else if constexpr (KMAX == 24) return g_ps.acc24;
+    else return g_ps.acc32;
+}
+
+// A waiting workgroup gives up after this many polls (seconds), raises the
+// launch's abort flag and marks its map failed: every later item is then
+// skipped, so the launch always ends.  The queue order makes this unreachable
+// in a correct launch; it is a guard against a broken item list.
+constexpr uint32_t kPersistSpinLimit = 1u << 22;
+
+// Arguments of a called stage function arrive in vector registers; the
+// workgroup's item is the same in every lane, so they are taken back as
+// wave-uniform values on entry.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+template <class T>
+__device__ __forceinline__ const T &uni_ref(const T &r)
+{
+    const unsigned long long p = (unsigned long long)&r;
+    return *(const T *)(((unsigned long long)uni((uint32_t)(p >> 32)) << 32) | uni((uint32_t)p));
+}
+
+// Each stage variant is a function of its own (called, not inlined), so it is
+// register-allocated alone, as in its own kernel.
+__device__ __noinline__ void persist_walk(const FrameParams &fpa, const MapDev &mda, uint32_t b0a, uint32_t nba)
+{
+    const FrameParams &fp = uni_ref(fpa);
+    const MapDev &md = uni_ref(mda);
+    const uint32_t b0 = uni(b0a), b1 = b0 + uni(nba);
+    for (uint32_t b = b0; b < b1; ++b) {
+        walk_emit_block(fp, md, (int)b, g_ps.walk);
+        __syncthreads();
+    }
+}
+
+__device__ __noinline__ void persist_plan(const FrameParams &fp, const MapDev &md, uint32_t j, uint32_t cnt)
+{
+    leaf_plan_range(uni_ref(fp), uni_ref(md), uni(j), uni(cnt));
+}
+
+__device__ __noinline__ void persist_bucket(const FrameParams &fp, const MapDev &md, uint32_t j, uint32_t cnt)
+{
+    pair_bucket_range(uni_ref(fp), uni_ref(md), uni(j), uni(cnt));
+}
+
+template <int KMAX>
+__device__ __noinline__ void persist_acc(const FrameParams &fp, const MapDev &md, uint32_t j, uint32_t cnt)
+{
+    leaf_acc_range<KMAX, 1>(uni_ref(fp), uni_ref(md), persist_acc_lds<KMAX>(), uni(j), uni(cnt));
+}
+
+template <int KMAX, bool WAVE, bool ROWS>
+__device__ __noinline__ void persist_fuse(const FrameParams &fp, const MapDev &md, uint32_t j, uint32_t cnt)
+{
+    leaf_fuse_range<KMAX, WAVE, ROWS>(uni_ref(fp), uni_ref(md), g_ps.leaf, uni(j), uni(cnt));
+}
+
+template <int KMAX>
+__device__ __noinline__ void persist_comb(const FrameParams &fp, const MapDev &md, uint32_t j, uint32_t cnt)
+{
+    voxel_combine_range<KMAX>(uni_ref(fp), uni_ref(md), uni(j), uni(cnt));
+}
+
+__device__ __noinline__ void persist_commit(const FrameParams &fp, const MapDev &md)
+{
+    frame_commit_block(uni_ref(fp), uni_ref(md), g_ps.commit);
+}
+
+__device__ __forceinline__ void persist_leaf(int kind, const FrameParams &fp, const MapDev &md, uint32_t j,
+                                             uint32_t cnt)
+{
+    switch (kind) {
+    case 0: persist_acc<0>(fp, md, j, cnt); break;
+    case 1: persist_acc<8>(fp, md, j, cnt); break;
+    case 2: persist_acc<16>(fp, md, j, cnt); break;
+    case 3: persist_acc<24>(fp, md, j, cnt); break;
+    case 4: persist_acc<32>(fp, md, j, cnt); break;
+    case 5: persist_fuse<8, false, true>(fp, md, j, cnt); break;
+    case 6: persist_fuse<16, false, true>(fp, md, j, cnt); break;
+    case 7: persist_fuse<32, false, true>(fp, md, j, cnt); break;
+    case 16: persist_fuse<24, false, true>(fp, md, j, cnt); break;
+    case 9: persist_fuse<-1, false, false>(fp, md, j, cnt); break;
+    case 10: persist_fuse<-1, true, false>(fp, md, j, cnt); break;
+    case 11: persist_fuse<1, true, false>(fp, md, j, cnt); break;
+    case 12: persist_fuse<2, true, false>(fp, md, j, cnt); break;
+    case 13: persist_fuse<4, true, false>(fp, md, j, cnt); break;
+    case 14: persist_fuse<8, true, false>(fp, md, j, cnt); break;
+    case 15: persist_fuse<16, true, false>(fp, md, j, cnt); break;
+    default: persist_fuse<0, true, false>(fp, md, j, cnt); break;
+    }
+}
+
+__device__ __forceinline__ void persist_combine(int kind, const FrameParams &fp, const MapDev &md, uint32_t j,
+                                                uint32_t cnt)
+{
+    switch (voxel_combine_arg(kind)) {
+    case 0: persist_comb<0>(fp, md, j, cnt); break;
+    case -1: persist_comb<-1>(fp, md, j, cnt); break;
+    case 1: persist_comb<1>(fp, md, j, cnt); break;
+    case 2: persist_comb<2>(fp, md, j, cnt); break;
+    case 4: persist_comb<4>(fp, md, j, cnt); break;
+    case 8: persist_comb<8>(fp, md, j, cnt); break;
+    case 16: persist_comb<16>(fp, md, j, cnt); break;
+    default: break;
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_batch_persistent(PersistArgs a)
+{
+    __shared__ uint4 s_item;
+    __shared__ uint32_t s_skip;
+    // Thread 0 alone talks to the queue, in one place per round: it counts the
+    // item the workgroup has just finished (after the release below), takes
+    // the next one and waits for its dependency.  Keeping that one guarded
+    // region per round, and the item wave-uniform, keeps every barrier of the
+    // loop in uniform control flow.
+    uint32_t finished = kPersistEnd;  // counter of the item the workgroup finished last
+    for (;;) {
+        if (threadIdx.x == 0) {
+            if (finished != kPersistEnd) atomicAdd(&a.ctl[kPersistCtlDone + finished], 1u);
+            const uint32_t it = atomicAdd(&a.ctl[0], 1u);
+            uint4 item = make_uint4(kPersistEnd, 0u, 0u, 0u);
+            uint32_t skip = 0;
+            if (it < a.nitems) {
+                item = a.items[it];
+                if (item.w != kPersistNoDep) {
+                    // wait for every item of the map's previous stage
+                    const uint32_t *done = &a.ctl[kPersistCtlDone + (item.w & 0xFFFFu)];
+                    const uint32_t need = item.w >> 16;
+                    uint32_t polls = 0;
+                    while (__hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        if (++polls > kPersistSpinLimit) {
+                            atomicOr(&a.ctl[kPersistCtlAbort], 1u);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                }
+                skip = __hip_atomic_load(&a.ctl[kPersistCtlAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __threadfence();
+                // after an abort the map's remaining items are skipped and the map is marked failed
+                const DevState *st = a.mds[item.x & 0xFFFFu].st;
+                if (skip && st->status == SLIM_OK) ((DevState *)st)->status = SLIM_ERR_DEVICE;
+            }
+            s_item = item;
+            s_skip = skip;
+        }
+        __syncthreads();
+        // every thread reads the same item: taken as wave-uniform values, so
+        // the loop and its exit stay uniform
+        const uint4 item = make_uint4(__builtin_amdgcn_readfirstlane(s_item.x), __builtin_amdgcn_readfirstlane(s_item.y),
+                                      __builtin_amdgcn_readfirstlane(s_item.z), __builtin_amdgcn_readfirstlane(s_item.w));
+        const uint32_t skip = __builtin_amdgcn_readfirstlane(s_skip);
+        if (item.x == kPersistEnd) break;
+        // acquire (every wave): what the previous stage wrote on other XCDs is visible
+        __threadfence();
+        const uint32_t i = item.x & 0xFFFFu, stage = (item.x >> 16) & 0xFFu;
+        const int kind = (int)(item.x >> 24);
+        const FrameParams &fp = a.fps[i];
+        const MapDev &md = a.mds[i];
+        if (!skip) {
+            switch (stage) {
+            case 0: persist_walk(fp, md, item.y, item.z); break;
+            case 1: persist_plan(fp, md, item.y, item.z); break;
+            case 2: persist_bucket(fp, md, item.y, item.z); break;
+            case 3: persist_leaf(kind, fp, md, item.y, item.z); break;
+            case 4: persist_combine(kind, fp, md, item.y, item.z); break;
+            default: persist_commit(fp, md); break;
+            }
+        }
+        // release: this item's writes reach the device level before thread 0
+        // counts it, at the top of the next round
+        __threadfence();
+        __syncthreads();
+        finished = i * kPersistStages + stage;
+    }
+}
+
+int persistent_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_persistent, 256, 0) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_integrate_persistent(const PersistArgs &a, int blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_persistent, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -2378,22 +2642,6 @@ int leaf_kernel_kind(const FrameParams &fp)
     const bool rows = fp.sem_kind == SLIM_IN_PROB_F32 || fp.sem_kind == SLIM_IN_LOGIT_F32;
     if (rows) return fp.K > 24 ? 7 : (fp.K > 16 ? 16 : (fp.K > 8 ? 6 : 5));
     return fp.K > 24 ? 4 : (fp.K > 16 ? 3 : (fp.K > 8 ? 2 : 1));
-}
-
-// Leaf-kernel variants whose voxels are combined by k_voxel_combine (one wave
-// per voxel), with that kernel's template argument; -2: combined in the leaf kernel.
-static int voxel_combine_arg(int kind)
-{
-    switch (kind) {
-    case 8: return 0;
-    case 10: return -1;
-    case 11: return 1;
-    case 12: return 2;
-    case 13: return 4;
-    case 14: return 8;
-    case 15: return 16;
-    default: return -2;
-    }
 }
 
 static void launch_voxel_combine(int kind, const FrameParams &fp, const MapDev &md, int blocks, hipStream_t s)
@@ -2486,6 +2734,8 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const La
 {
     MapDev md = md_in;
     md.leaf_blocks = shape.leaf_blocks;
+    md.wave_pairs = shape.wave_pairs;
+    md.slab_pairs = shape.slab_pairs;
     const int bw = (fp.n + kWalkThreads - 1) / kWalkThreads;
     auto rec = [&](int e) {
         if (ev) (void)hipEventRecord(ev[e], s);
@@ -2535,6 +2785,8 @@ hipError_t launch_after_walk(const FrameParams &fp, const MapDev &md_in, const L
 {
     MapDev md = md_in;
     md.leaf_blocks = shape.leaf_blocks;
+    md.wave_pairs = shape.wave_pairs;
+    md.slab_pairs = shape.slab_pairs;
     hipLaunchKernelGGL(k_leaf_plan, dim3(shape.plan_blocks), dim3(256), 0, s, fp, md);
     const long long want = ((long long)fp.n * fp.maxsteps + 255) / 256;
     const int bb = (int)std::max<long long>(1, std::min<long long>(want, shape.bucket_blocks));

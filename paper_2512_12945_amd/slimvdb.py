@@ -60,7 +60,9 @@ class Frame(ctypes.Structure):
 
 class LaunchShape(ctypes.Structure):
     _fields_ = [("plan_blocks", ctypes.c_int32), ("bucket_blocks", ctypes.c_int32),
-                ("leaf_blocks_per_cu", ctypes.c_int32), ("pass_frames", ctypes.c_int32)]
+                ("leaf_blocks_per_cu", ctypes.c_int32), ("pass_frames", ctypes.c_int32),
+                ("batch_mode", ctypes.c_int32), ("walk_chunk", ctypes.c_int32),
+                ("wave_pairs", ctypes.c_int32), ("slab_pairs", ctypes.c_int32)]
 
 
 class SlimError(RuntimeError):
@@ -246,17 +248,23 @@ class Map:
                                   _stream(self.device)))
         return dict(D=d[:m], W=w[:m], sem=sem[:m, : self.nsem])
 
-    def set_launch_shape(self, plan_blocks=None, bucket_blocks=None, leaf_blocks_per_cu=None, pass_frames=0):
-        """Grid sizes of the grid-stride kernels and the frames integrate_sequence
-        takes in one pass (0: the default, 1: one at a time); all None / 0
-        restores the defaults, grid sizes left None take their defaults."""
-        if plan_blocks is None and bucket_blocks is None and leaf_blocks_per_cu is None and not pass_frames:
+    def set_launch_shape(self, plan_blocks=None, bucket_blocks=None, leaf_blocks_per_cu=None, pass_frames=0,
+                         batch_mode=0, walk_chunk=0, wave_pairs=0, slab_pairs=0):
+        """Grid sizes of the grid-stride kernels (in a persistent batched launch:
+        items of each stage), the frames integrate_sequence takes in one pass
+        (0: the default, 1: one at a time), the batched form (0 default, 1
+        persistent, 2 one launch per stage), the ray-chunk size in 256-ray
+        blocks and the leaf-tile thresholds (see slim_launch_shape); all None /
+        0 restores the defaults, grid sizes left None take their defaults."""
+        if (plan_blocks is None and bucket_blocks is None and leaf_blocks_per_cu is None and not pass_frames
+                and not batch_mode and not walk_chunk and not wave_pairs and not slab_pairs):
             _check(self._L.slim_set_launch_shape(self.h, None))
         else:
             cus = torch.cuda.get_device_properties(self.device).multi_processor_count
             sh = LaunchShape(cus if plan_blocks is None else plan_blocks,
                              16 * cus if bucket_blocks is None else bucket_blocks,
-                             8 if leaf_blocks_per_cu is None else leaf_blocks_per_cu, int(pass_frames))
+                             8 if leaf_blocks_per_cu is None else leaf_blocks_per_cu, int(pass_frames),
+                             int(batch_mode), int(walk_chunk), int(wave_pairs), int(slab_pairs))
             _check(self._L.slim_set_launch_shape(self.h, ctypes.byref(sh)))
 
     def profile(self, enable=True):

@@ -1,5 +1,6 @@
-"""The launch-shape autotuner picks one of its candidates, caches it by device,
-map mix and point-count bucket, and the chosen shape gives the same maps."""
+"""The launch-shape autotuner picks a shape from its knob values (batched form,
+ray-chunk size, work split, leaf tiles), caches it by device, map mix and
+point-count bucket, and the chosen shape gives the same maps."""
 import json
 
 import numpy as np
@@ -32,13 +33,17 @@ def test_tune_caches_and_keeps_results(tmp_path):
     cache = str(tmp_path / "tune.json")
     shape = autotune.tune(cfgs, frames, reps=2, cache_path=cache)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    assert tuple(shape) in [tuple(c) for c in autotune.candidates(cus)]
+    ax = autotune.axes(cus)
+    assert set(shape) == set(ax)
+    for k, v in shape.items():
+        assert v in ax[k], (k, v)
     rec = json.load(open(cache))
-    assert list(rec.values())[0]["shape"] == list(shape)
-    assert autotune.tune(cfgs, frames, cache_path=cache) == tuple(shape)  # served from the cache
+    assert list(rec.values())[0]["shape"] == shape
+    assert list(rec.values())[0]["shapes_timed"] >= sum(len(v) - 1 for v in ax.values()) + 1
+    assert autotune.tune(cfgs, frames, cache_path=cache) == shape  # served from the cache
     ref = [sv.Map(**c) for c in cfgs]
     alt = [sv.Map(**c) for c in cfgs]
-    alt[0].set_launch_shape(*shape)
+    alt[0].set_launch_shape(**shape)
     sv.integrate_batched(ref, frames, use_graph=True)
     sv.integrate_batched(alt, frames, use_graph=True)
     for a, b in zip(ref, alt):
