@@ -933,119 +933,179 @@ __device__ __forceinline__ void combine_lane(const FrameParams &fp, const MapDev
         if (v < nv) R[v] = make_float4(r[4 * v + 0], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
 }
 
-// One voxel, one wave: lane l owns components l, l + 64, ... of the open-set
-// statistics (L <= 1024) or of the class counts (K <= 1024).
-// Open-set row of observation pid, the V consecutive components lane * V ..
-// of an L = 64 V embedding, read as whole 4- to 16-byte words.
-template <int V>
-__device__ __forceinline__ void load_row(const FrameParams &fp, bool bf, uint32_t pid, int lane, float (&z)[V])
+// Raw words of one lane's share of an open-set row: V / 2 words of bf16
+// pairs, or V floats.
+template <int V, bool BF>
+struct RowWords {
+    static constexpr int W = BF ? V / 2 : V;
+    uint32_t w[W];
+};
+
+template <int V, bool BF>
+__device__ __forceinline__ void load_row_words(const FrameParams &fp, uint32_t pid, int lane, RowWords<V, BF> &r)
 {
-    if (bf) {
-        const uint16_t *row = (const uint16_t *)fp.sem + (size_t)pid * (64 * V) + lane * V;
-        if constexpr (V % 8 == 0) {
+    constexpr int W = RowWords<V, BF>::W;
+    const uint32_t *row = (const uint32_t *)fp.sem + (size_t)pid * (64 * W) + lane * W;
+    if constexpr (W % 4 == 0) {
 #pragma unroll
-            for (int c = 0; c < V / 8; ++c) {
-                const uint4 u = ((const uint4 *)row)[c];
-                const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+        for (int c = 0; c < W / 4; ++c) {
+            const uint4 u = ((const uint4 *)row)[c];
+            r.w[4 * c] = u.x;
+            r.w[4 * c + 1] = u.y;
+            r.w[4 * c + 2] = u.z;
+            r.w[4 * c + 3] = u.w;
+        }
+    } else if constexpr (W == 2) {
+        const uint2 u = *(const uint2 *)row;
+        r.w[0] = u.x;
+        r.w[1] = u.y;
+    } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    z[8 * c + 2 * e] = __uint_as_float(w[e] << 16);
-                    z[8 * c + 2 * e + 1] = __uint_as_float(w[e] & 0xFFFF0000u);
-                }
-            }
-        } else {
+        for (int c = 0; c < W; ++c) r.w[c] = row[c];
+    }
+}
+
+template <int V, bool BF>
+__device__ __forceinline__ void unpack_row(const RowWords<V, BF> &r, float (&z)[V])
+{
+    if constexpr (BF) {
 #pragma unroll
-            for (int e = 0; e < V / 2; ++e) {
-                const uint32_t w = ((const uint32_t *)row)[e];
-                z[2 * e] = __uint_as_float(w << 16);
-                z[2 * e + 1] = __uint_as_float(w & 0xFFFF0000u);
-            }
+        for (int e = 0; e < V / 2; ++e) {
+            z[2 * e] = __uint_as_float(r.w[e] << 16);
+            z[2 * e + 1] = __uint_as_float(r.w[e] & 0xFFFF0000u);
         }
     } else {
-        const float *row = (const float *)fp.sem + (size_t)pid * (64 * V) + lane * V;
-        if constexpr (V % 4 == 0) {
 #pragma unroll
-            for (int c = 0; c < V / 4; ++c) {
-                const float4 f = ((const float4 *)row)[c];
-                z[4 * c] = f.x;
-                z[4 * c + 1] = f.y;
-                z[4 * c + 2] = f.z;
-                z[4 * c + 3] = f.w;
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < V; ++e) z[e] = row[e];
-        }
+        for (int e = 0; e < V; ++e) z[e] = __uint_as_float(r.w[e]);
     }
+}
+
+// Sum over the wave of one 64-bit integer per lane (every lane gets the sum).
+__device__ __forceinline__ long long wave_sum_i64(long long x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int lo = __shfl_xor((int)(unsigned long long)x, o, 64);
+        const int hi = __shfl_xor((int)((unsigned long long)x >> 32), o, 64);
+        x += (long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo);
+    }
+    return x;
 }
 
 // Open set with L = 64 V, one wave per voxel: lane l owns components l V ..
 // l V + V - 1, so one observation's row is one or two wide loads per lane and
-// many observations are in flight at once.  Sums as in combine_wave.
+// many observations are in flight at once.  Sums as in combine_wave: the
+// shifted sums in observation order, the distance sum as exact integers.  The
+// point index of each row is read from its lane as a wave-uniform value, and
+// a batch's rows are all requested before any is unpacked (a batch's slots
+// past the last observation load that observation's row again and add
+// nothing).
+// kl0, vl0: point index and distance of observation `lane` (lanes below
+// min(n, 64)), 0 elsewhere; the caller may have requested them ahead.
+// V consecutive floats of a record (8-byte aligned for even V), read or
+// written as pairs.
 template <int V>
-__device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
-                                                 const float *vals, uint32_t n, long long rec, bool existed)
+__device__ __forceinline__ void rec_load(const float *p, float (&o)[V])
+{
+    if constexpr (V % 2 == 0) {
+#pragma unroll
+        for (int c = 0; c < V / 2; ++c) {
+            const float2 f = ((const float2 *)p)[c];
+            o[2 * c] = f.x;
+            o[2 * c + 1] = f.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) o[i] = p[i];
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void rec_store(float *p, const float (&o)[V])
+{
+    if constexpr (V % 2 == 0) {
+#pragma unroll
+        for (int c = 0; c < V / 2; ++c) ((float2 *)p)[c] = make_float2(o[2 * c], o[2 * c + 1]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i) p[i] = o[i];
+    }
+}
+
+template <int V, bool BF>
+__device__ __forceinline__ void combine_wave_vec_t(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
+                                                   const float *vals, uint32_t n, long long rec, bool existed,
+                                                   uint32_t kl0, float vl0)
 {
     constexpr int B = V >= 16 ? 4 : 8;
     const int lane = lane_id();
-    const bool bf = fp.sem_kind == SLIM_IN_EMB_BF16;
     float *R = md.vox + (size_t)rec * md.rec_stride;
-    // the point indices and distances of up to 64 observations, one per lane,
-    // requested before the first row, and (up to 8 components per lane) the
-    // voxel's record with them
+    // (up to 8 components per lane) the voxel's record is requested with the rows
     constexpr bool early = V <= 8;
-    uint32_t kl = (uint32_t)lane < n ? keys[lane] & kPidMask : 0u;
-    float vl = (uint32_t)lane < n ? vals[lane] : 0.0f;
+    uint32_t kl = kl0;
+    float vl = vl0;
     float *M = R + 2 + lane * V, *Bt = R + 2 + 64 * V + lane * V;
     float m0[early ? V : 1], b0[early ? V : 1];
     float W0 = 0.0f, D0 = 0.0f;
     if constexpr (early) {
         W0 = existed ? R[1] : 0.0f;
         D0 = existed ? R[0] : 0.0f;
+        if (existed) {
+            rec_load<V>(M, m0);
+            rec_load<V>(Bt, b0);
+        } else {
 #pragma unroll
-        for (int i = 0; i < V; ++i) {
-            m0[i] = existed ? M[i] : 0.0f;
-            b0[i] = existed ? Bt[i] : 0.0f;
+            for (int i = 0; i < V; ++i) {
+                m0[i] = 0.0f;
+                b0[i] = 0.0f;
+            }
         }
     }
-    const uint32_t p0 = (uint32_t)__shfl((int)kl, 0, 64);
     float z0[V], s1[V], s2[V];
-    load_row<V>(fp, bf, p0, lane, z0);
+    {
+        RowWords<V, BF> r0;
+        load_row_words<V, BF>(fp, (uint32_t)__builtin_amdgcn_readlane((int)kl, 0), lane, r0);
+        unpack_row<V, BF>(r0, z0);
+    }
 #pragma unroll
     for (int i = 0; i < V; ++i) {
         s1[i] = 0.0f;
         s2[i] = 0.0f;
     }
-    // fixed-point distance sum (Eq. (1)-(2)), from the lanes
+    // fixed-point distance sum (Eq. (1)-(2)): each lane converts its own
+    // observations, one wave-wide sum at the end
     const FixScale fx = fix_scale(fp);
     long long sum_t = 0;
-    // batches of B rows from observation 0 (whose difference is 0); a batch
-    // never crosses a group of 64 observations
+    // batches of B observations from observation 0 (whose difference is 0);
+    // a batch never crosses a group of 64 observations
     for (uint32_t q = 0; q < n; q += B) {
-        if (q > 0 && (q & 63u) == 0) {
-            kl = q + (uint32_t)lane < n ? keys[q + lane] & kPidMask : 0u;
-            vl = q + (uint32_t)lane < n ? vals[q + lane] : 0.0f;
+        if ((q & 63u) == 0) {
+            if (q > 0) {
+                kl = q + (uint32_t)lane < n ? keys[q + lane] & kPidMask : 0u;
+                vl = q + (uint32_t)lane < n ? vals[q + lane] : 0.0f;
+            }
+            if (q + (uint32_t)lane < n) sum_t += fix_q(vl, fx.s);
         }
-        float z[B][V];
+        RowWords<V, BF> raw[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const uint32_t pid = (uint32_t)__shfl((int)kl, (int)((q + b) & 63u), 64);
-            load_row<V>(fp, bf, q + b < n ? pid : p0, lane, z[b]);
-        }
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            const float v = __shfl(vl, (int)((q + b) & 63u), 64);
-            if (q + b < n) sum_t += fix_q(v, fx.s);
+            const uint32_t t = min(q + (uint32_t)b, n - 1u);
+            load_row_words<V, BF>(fp, (uint32_t)__builtin_amdgcn_readlane((int)kl, (int)(t & 63u)), lane, raw[b]);
         }
 #pragma unroll
         for (int b = 0; b < B; ++b)
+            if (q + b > 0 && q + b < n) {
+                float z[V];
+                unpack_row<V, BF>(raw[b], z);
 #pragma unroll
-            for (int i = 0; i < V; ++i) {
-                const float d = z[b][i] - z0[i];  // 0 for observation 0 and the padding (its row again)
-                s1[i] += d;
-                s2[i] += d * d;
+                for (int i = 0; i < V; ++i) {
+                    const float d = z[i] - z0[i];
+                    s1[i] += d;
+                    s2[i] += d * d;
+                }
             }
     }
+    sum_t = wave_sum_i64(sum_t);
     // Eqs. (11)-(14) with lambda = W, nu = W / 2
     const float nf = (float)n;
     if constexpr (!early) {
@@ -1053,11 +1113,13 @@ __device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const Ma
         D0 = existed ? R[0] : 0.0f;
     }
     const float W1 = W0 + nf;
-    const float cross = W0 * nf / W1;
+    const float inv_n = 1.0f / nf, inv_w1 = 1.0f / W1;
+    const float cross = W0 * nf * inv_w1;
+    float mo[V], bo[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-        const float zbar = z0[i] + s1[i] / nf;
-        const float scat = fmaxf(s2[i] - s1[i] * s1[i] / nf, 0.0f);
+        const float zbar = z0[i] + s1[i] * inv_n;
+        const float scat = fmaxf(s2[i] - s1[i] * s1[i] * inv_n, 0.0f);
         float mi, bi;
         if constexpr (early) {
             mi = m0[i];
@@ -1067,13 +1129,38 @@ __device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const Ma
             bi = existed ? Bt[i] : 0.0f;
         }
         const float dm = zbar - mi;
-        Bt[i] = bi + 0.5f * scat + cross * dm * dm * 0.5f;
-        M[i] = (W0 * mi + nf * zbar) / W1;
+        bo[i] = bi + 0.5f * scat + cross * dm * dm * 0.5f;
+        mo[i] = (W0 * mi + nf * zbar) * inv_w1;
     }
+    rec_store<V>(Bt, bo);
+    rec_store<V>(M, mo);
     if (lane == 0) {
         R[0] = tsdf_mean(D0, W0, W1, sum_t, fx.inv);
         R[1] = W1;
     }
+}
+
+template <int V>
+__device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
+                                                 const float *vals, uint32_t n, long long rec, bool existed,
+                                                 uint32_t kl0, float vl0)
+{
+    if constexpr (V >= 2) {
+        if (fp.sem_kind == SLIM_IN_EMB_BF16) {
+            combine_wave_vec_t<V, true>(fp, md, keys, vals, n, rec, existed, kl0, vl0);
+            return;
+        }
+    }
+    combine_wave_vec_t<V, false>(fp, md, keys, vals, n, rec, existed, kl0, vl0);
+}
+
+template <int V>
+__device__ __forceinline__ void combine_wave_vec(const FrameParams &fp, const MapDev &md, const uint32_t *keys,
+                                                 const float *vals, uint32_t n, long long rec, bool existed)
+{
+    const uint32_t lane = (uint32_t)lane_id();
+    combine_wave_vec<V>(fp, md, keys, vals, n, rec, existed, lane < n ? keys[lane] & kPidMask : 0u,
+                        lane < n ? vals[lane] : 0.0f);
 }
 
 constexpr int kWaveComps = 16;
@@ -1135,18 +1222,19 @@ __device__ __forceinline__ void combine_wave(const FrameParams &fp, const MapDev
         // Eqs. (11)-(14) with lambda = W, nu = W / 2
         const float nf = (float)n;
         const float W0 = existed ? R[1] : 0.0f, W1 = W0 + nf;
-        const float cross = W0 * nf / W1;
+        const float inv_n = 1.0f / nf, inv_w1 = 1.0f / W1;
+        const float cross = W0 * nf * inv_w1;
         float *M = R + 2, *B = R + 2 + fp.L;
 #pragma unroll
         for (int j = 0; j < kWaveComps; ++j) {
             const int comp = lane + 64 * j;
             if (comp < C) {
-                const float zbar = z0[j] + s1[j] / nf;
-                const float scat = fmaxf(s2[j] - s1[j] * s1[j] / nf, 0.0f);
+                const float zbar = z0[j] + s1[j] * inv_n;
+                const float scat = fmaxf(s2[j] - s1[j] * s1[j] * inv_n, 0.0f);
                 const float m0 = existed ? M[comp] : 0.0f, b0 = existed ? B[comp] : 0.0f;
                 const float dm = zbar - m0;
                 B[comp] = b0 + 0.5f * scat + cross * dm * dm * 0.5f;
-                M[comp] = (W0 * m0 + nf * zbar) / W1;
+                M[comp] = (W0 * m0 + nf * zbar) * inv_w1;
             }
         }
     } else if (fp.sem_kind == SLIM_IN_LABEL_I32) {
@@ -2232,29 +2320,67 @@ __device__ __forceinline__ void voxel_combine_range(const FrameParams &fp, const
     // index is r modulo 8; a one-to-one map of [0, nblk) for any nblk)
     const uint32_t r = blk % 8, q = nblk / 8, m = nblk % 8;
     const uint32_t vb = r * q + min(r, m) + blk / 8;
-    for (uint32_t v = vb * nw + w; v < nv; v += nblk * nw) {
-        const uint4 d = md.vox_list[v];
-        const uint32_t n = d.y & 0x7FFFFFFFu;
-        const bool existed = (d.y >> 31) != 0u;
-        const uint32_t *keys = md.pair_key + d.z;
-        const float *vals = md.pair_tsdf + d.z;
-        if (KMAX < 0)
-            combine_last_wave(fp, md, keys, vals, n, (long long)d.x, existed);
-        else if (KMAX > 0)
-            combine_wave_vec<(KMAX > 0 ? KMAX : 1)>(fp, md, keys, vals, n, (long long)d.x, existed);
-        else
-            combine_wave(fp, md, keys, vals, n, (long long)d.x, existed);
+    const uint32_t step = nblk * nw;
+    if constexpr (KMAX > 0) {
+        // a wave's voxels one after another, each one's descriptor requested
+        // two voxels ahead and its observations' point indices and distances
+        // one voxel ahead, so that only the rows and the record are waited
+        // for (indices past the end read the wave's first voxel again)
+        const uint32_t lane = (uint32_t)lane_id();
+        const uint32_t v0 = vb * nw + w;
+        if (v0 >= nv) return;
+        uint4 d = md.vox_list[v0];
+        uint32_t kl = lane < (d.y & 0x7FFFFFFFu) ? md.pair_key[d.z + lane] & kPidMask : 0u;
+        float vl = lane < (d.y & 0x7FFFFFFFu) ? md.pair_tsdf[d.z + lane] : 0.0f;
+        uint32_t vn = v0 + step;
+        uint4 dn = md.vox_list[vn < nv ? vn : v0];
+        for (;;) {
+            const bool more = vn < nv;
+            const uint32_t nn = more ? dn.y & 0x7FFFFFFFu : 0u;
+            const uint32_t kn = lane < nn ? md.pair_key[dn.z + lane] & kPidMask : 0u;
+            const float vln = lane < nn ? md.pair_tsdf[dn.z + lane] : 0.0f;
+            const uint32_t vnn = vn + step;
+            const uint4 dnn = md.vox_list[vnn < nv ? vnn : v0];
+            combine_wave_vec<(KMAX > 0 ? KMAX : 1)>(fp, md, md.pair_key + d.z, md.pair_tsdf + d.z,
+                                                    d.y & 0x7FFFFFFFu, (long long)d.x, (d.y >> 31) != 0u, kl, vl);
+            if (!more) break;
+            d = dn;
+            kl = kn;
+            vl = vln;
+            vn = vnn;
+            dn = dnn;
+        }
+    } else {
+        for (uint32_t v = vb * nw + w; v < nv; v += step) {
+            const uint4 d = md.vox_list[v];
+            const uint32_t n = d.y & 0x7FFFFFFFu;
+            const bool existed = (d.y >> 31) != 0u;
+            const uint32_t *keys = md.pair_key + d.z;
+            const float *vals = md.pair_tsdf + d.z;
+            if (KMAX < 0)
+                combine_last_wave(fp, md, keys, vals, n, (long long)d.x, existed);
+            else
+                combine_wave(fp, md, keys, vals, n, (long long)d.x, existed);
+        }
     }
 }
 
+// Workgroups per CU the combine kernels are built for: the vectorised kinds are
+// bound by the latency of their row gathers, so they keep enough waves in
+// flight (register budgets 72, 100, 128, 168 for L = 64, 128, 256, 512).
+__host__ __device__ constexpr int combine_min_blocks(int kmax)
+{
+    return kmax == 1 ? 7 : (kmax == 2 ? 5 : (kmax == 4 ? 4 : (kmax == 8 ? 3 : 1)));
+}
+
 template <int KMAX>
-__global__ __launch_bounds__(256) void k_voxel_combine(FrameParams fp, MapDev md)
+__global__ __launch_bounds__(256, combine_min_blocks(KMAX)) void k_voxel_combine(FrameParams fp, MapDev md)
 {
     voxel_combine_range<KMAX>(fp, md, blockIdx.x, gridDim.x);
 }
 
 template <int KMAX>
-__global__ __launch_bounds__(256) void k_voxel_combine_batch(MapBatch mb)
+__global__ __launch_bounds__(256, combine_min_blocks(KMAX)) void k_voxel_combine_batch(MapBatch mb)
 {
     for (int q = 0; q < mb.nsubset; ++q) {
         const int i = mb.subset[q];
