@@ -331,13 +331,16 @@ __device__ __forceinline__ uint32_t stage_leaf_cas(const MapDev &md, unsigned lo
 }
 
 // Block-local table of the leaves a walk block's rays touch.
+// Kept small enough for three workgroups per CU: slab masks are 8-bit fields,
+// four to a word, and entry lists 16-bit.
+static_assert(kWalkTable <= 65536, "walk-table entries are listed as 16-bit indices");
 struct WalkShared {
     unsigned long long t_key[kWalkTable];
-    uint32_t t_cnt[kWalkTable];   // pairs of this block in the leaf, then their first bucket rank
-    uint32_t t_pos[kWalkTable];   // staging position
-    uint32_t t_slab[kWalkTable];  // x-slabs of the leaf this block touches
-    uint32_t t_list[kWalkTable];  // occupied entries
-    uint32_t t_fresh[kWalkTable]; // entries whose staging insert this block made
+    uint32_t t_cnt[kWalkTable];       // pairs of this block in the leaf, then their first bucket rank
+    uint32_t t_pos[kWalkTable];       // staging position
+    uint32_t t_slab[kWalkTable / 4];  // x-slabs of the leaf this block touches (8 bits per entry)
+    uint16_t t_list[kWalkTable];      // occupied entries
+    uint16_t t_fresh[kWalkTable];     // entries whose staging insert this block made
     uint32_t s_n, s_nfresh, s_pair_base, wsum[4];
 };
 
@@ -345,7 +348,8 @@ struct WalkShared {
 __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const MapDev &md, int blk, WalkShared &ws)
 {
     unsigned long long *t_key = ws.t_key;
-    uint32_t *t_cnt = ws.t_cnt, *t_pos = ws.t_pos, *t_slab = ws.t_slab, *t_list = ws.t_list, *t_fresh = ws.t_fresh;
+    uint32_t *t_cnt = ws.t_cnt, *t_pos = ws.t_pos, *t_slab = ws.t_slab;
+    uint16_t *t_list = ws.t_list, *t_fresh = ws.t_fresh;
     uint32_t &s_n = ws.s_n, &s_nfresh = ws.s_nfresh, &s_pair_base = ws.s_pair_base;
     uint32_t *wsum = ws.wsum;
 
@@ -366,8 +370,8 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
     for (int e = tid; e < kWalkTable; e += blockDim.x) {
         t_key[e] = kEmptyKey;
         t_cnt[e] = 0;
-        t_slab[e] = 0;
     }
+    for (int e = tid; e < kWalkTable / 4; e += blockDim.x) t_slab[e] = 0;
     if (tid == 0) {
         s_n = 0;
         s_nfresh = 0;
@@ -464,7 +468,7 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
                 if (k == kEmptyKey) {
                     k = atomicCAS(&t_key[h], kEmptyKey, key);
                     if (k == kEmptyKey) {
-                        t_list[atomicAdd(&s_n, 1u)] = h;
+                        t_list[atomicAdd(&s_n, 1u)] = (uint16_t)h;
                         k = key;
                     }
                 }
@@ -474,7 +478,7 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
             if (found) {
                 rent[q] = h;
                 rloc[q] = atomicAdd(&t_cnt[h], rlen[q]);
-                atomicOr(&t_slab[h], rslab[q]);
+                atomicOr(&t_slab[h >> 2], rslab[q] << (8u * (h & 3u)));
             } else {
                 atomicOr(&md.fs->frame_err.v, 1u);  // pairs of this run are dropped, frame rejected
             }
@@ -499,8 +503,8 @@ __device__ __forceinline__ void walk_emit_block(const FrameParams &fp, const Map
         t_pos[h] = pos;
         if (pos != kNoPos) {
             t_cnt[h] = atomicAdd(&md.pos_count[pos], t_cnt[h]);
-            atomicOr(&md.pos_slab[pos], t_slab[h]);
-            if (fresh) t_fresh[atomicAdd(&s_nfresh, 1u)] = h;
+            atomicOr(&md.pos_slab[pos], (t_slab[h >> 2] >> (8u * (h & 3u))) & 0xFFu);
+            if (fresh) t_fresh[atomicAdd(&s_nfresh, 1u)] = (uint16_t)h;
         } else {
             atomicOr(&md.fs->frame_err.v, 1u);
         }
