@@ -215,11 +215,16 @@ struct MapDev {
 };
 
 // Device descriptor of a batched launch over several maps (one frame each).
+// Each per-stage launch is shared between its maps: map q of the launch holds
+// blocks first[q] .. first[q + 1] - 1 and runs the stage's grid-stride code
+// with that share as its grid.
 struct MapBatch {
     const MapDev *mds;       // nmaps
     const FrameParams *fps;  // nmaps
     const int *walk_start;   // nmaps + 1: first walk block of each map
     const int *subset;       // the maps one leaf-kernel launch handles
+    const int *plan_first, *bucket_first;  // nmaps + 1 each
+    const int *part_first;   // nsubset + 1: the shares of a leaf-kernel or combine launch
     int nmaps, nsubset;
 };
 
@@ -240,9 +245,12 @@ struct LaunchShape {
 struct BatchPlan {
     int nmaps;
     int walk_blocks;                 // total blocks of the walk kernel
+    int plan_blocks, bucket_blocks;  // grids of planning and bucketing
     int ngroups;
     int group_kind[17];                   // leaf-kernel variant of each group
     int group_begin[17], group_size[17];  // slice of the device subset array
+    int leaf_blocks[17], comb_blocks[17]; // grids of each group's leaf-kernel and combine launches
+    int leaf_part[17], comb_part[17];     // offsets of their shares in the device share arrays
 };
 
 constexpr int kLeafKinds = 17;  // variants of the leaf kernel (leaf_kernel_kind)

@@ -1124,11 +1124,53 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
     }
     const uint32_t nitems = (uint32_t)items.size();
     const size_t nctl = shape.persistent ? (size_t)kPersistCtlDone + (size_t)nmaps * kPersistStages : 0;
+    // per-stage launches: each stage's grid is shared between its maps in
+    // proportion to their walk blocks, at least one block each (map q of a
+    // launch of P blocks over n maps starts at q + floor(W_q (P - n) / W),
+    // W_q the walk blocks of the maps before it)
+    std::vector<int> plan_first, bucket_first, part;
+    if (!shape.persistent) {
+        auto share = [&](const int *maps, int n, int P, std::vector<int> &out) {
+            long long W = 0;
+            for (int q = 0; q < n; ++q) W += start[maps[q] + 1] - start[maps[q]];
+            long long cum = 0;
+            for (int q = 0; q <= n; ++q) {
+                out.push_back(q + (int)(W > 0 ? cum * (P - n) / W : 0));
+                if (q < n) cum += start[maps[q] + 1] - start[maps[q]];
+            }
+        };
+        std::vector<int> all(nmaps);
+        for (int i = 0; i < nmaps; ++i) all[i] = i;
+        plan.plan_blocks = std::max(shape.plan_blocks, nmaps);
+        plan.bucket_blocks = std::max(shape.bucket_blocks, nmaps);
+        share(all.data(), nmaps, plan.plan_blocks, plan_first);
+        share(all.data(), nmaps, plan.bucket_blocks, bucket_first);
+        for (int g = 0; g < plan.ngroups; ++g) {
+            const int *gm = subset.data() + plan.group_begin[g];
+            const int gs = plan.group_size[g];
+            plan.leaf_blocks[g] = std::max(shape.leaf_blocks, gs);
+            plan.leaf_part[g] = (int)part.size();
+            share(gm, gs, plan.leaf_blocks[g], part);
+            // the commit sums the statistics of the map's share of leaf blocks
+            for (int q = 0; q < gs; ++q)
+                mds[gm[q]].leaf_blocks = part[plan.leaf_part[g] + q + 1] - part[plan.leaf_part[g] + q];
+            plan.comb_part[g] = (int)part.size();
+            plan.comb_blocks[g] = 0;
+            if (voxel_combine_arg(plan.group_kind[g]) != -2) {
+                plan.comb_blocks[g] = std::max(shape.leaf_blocks, gs);
+                share(gm, gs, plan.comb_blocks[g], part);
+            }
+        }
+    }
     // descriptor: [MapDev x n][FrameParams x n][walk_start x n+1][subset x n]
-    // [work items][control block, zero], 16-byte aligned pieces
+    // [plan shares][bucket shares][leaf and combine shares][work items]
+    // [control block, zero], 16-byte aligned pieces
     auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
     const size_t o_fp = al(sizeof(MapDev) * nmaps), o_ws = o_fp + al(sizeof(FrameParams) * nmaps);
-    const size_t o_sub = o_ws + al(sizeof(int) * (nmaps + 1)), o_it = o_sub + al(sizeof(int) * nmaps);
+    const size_t o_sub = o_ws + al(sizeof(int) * (nmaps + 1)), o_pf = o_sub + al(sizeof(int) * nmaps);
+    const size_t o_bf = o_pf + al(sizeof(int) * plan_first.size());
+    const size_t o_pt = o_bf + al(sizeof(int) * bucket_first.size());
+    const size_t o_it = o_pt + al(sizeof(int) * part.size());
     const size_t o_ctl = o_it + al(sizeof(uint4) * nitems), bytes = o_ctl + al(sizeof(uint32_t) * nctl);
 
     if (!m0->batch) m0->batch = new BatchCtx();
@@ -1158,6 +1200,9 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
     memcpy(st + o_fp, fps.data(), sizeof(FrameParams) * nmaps);
     memcpy(st + o_ws, start.data(), sizeof(int) * (nmaps + 1));
     memcpy(st + o_sub, subset.data(), sizeof(int) * nmaps);
+    if (!plan_first.empty()) memcpy(st + o_pf, plan_first.data(), sizeof(int) * plan_first.size());
+    if (!bucket_first.empty()) memcpy(st + o_bf, bucket_first.data(), sizeof(int) * bucket_first.size());
+    if (!part.empty()) memcpy(st + o_pt, part.data(), sizeof(int) * part.size());
     if (nitems) memcpy(st + o_it, items.data(), sizeof(uint4) * nitems);
     if (nctl) memset(st + o_ctl, 0, sizeof(uint32_t) * nctl);
     char *dv = (char *)b->dev;
@@ -1166,6 +1211,9 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
     mb.fps = (const FrameParams *)(dv + o_fp);
     mb.walk_start = (const int *)(dv + o_ws);
     mb.subset = (const int *)(dv + o_sub);
+    mb.plan_first = (const int *)(dv + o_pf);
+    mb.bucket_first = (const int *)(dv + o_bf);
+    mb.part_first = (const int *)(dv + o_pt);
     mb.nmaps = nmaps;
     mb.nsubset = nmaps;
     PersistArgs pa;

@@ -749,7 +749,8 @@ __global__ __launch_bounds__(256) void k_leaf_plan(FrameParams fp, MapDev md)
 
 __global__ __launch_bounds__(256) void k_leaf_plan_batch(MapBatch mb)
 {
-    for (int i = 0; i < mb.nmaps; ++i) leaf_plan_range(mb.fps[i], mb.mds[i], blockIdx.x, gridDim.x);
+    const int i = batch_map(mb.plan_first, mb.nmaps, blockIdx.x);
+    leaf_plan_range(mb.fps[i], mb.mds[i], blockIdx.x - mb.plan_first[i], mb.plan_first[i + 1] - mb.plan_first[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -762,13 +763,29 @@ __device__ __forceinline__ void pair_bucket_range(const FrameParams &fp, const M
     const uint32_t P = min(md.fs->pairs.v, md.pair_cap);
     const uint32_t stride = nblk * blockDim.x;
     const bool labels = fp.K > 0 && fp.sem_kind == SLIM_IN_LABEL_I32;
-    for (uint32_t i = blk * blockDim.x + threadIdx.x; i < P; i += stride) {
-        const uint4 pq = md.pairs[i];  // (staging position, rank, key, distance bits)
-        if (pq.x == kNoPos) continue;
-        const uint32_t dst = (uint32_t)md.pos_plan[pq.x].z + pq.y;
-        md.srt_kv[dst] = make_uint2(pq.z, pq.w);
-        // the leaf kernel's small items find the label beside the pair
-        if (labels) md.srt_lab[dst] = point_label(fp, pq.z & kPidMask);
+    // four pairs per thread and round, each step's loads issued together
+    constexpr int U = 4;
+    for (uint32_t i0 = blk * blockDim.x + threadIdx.x; i0 < P; i0 += U * stride) {
+        uint4 pq[U];  // (staging position, rank, key, distance bits)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * stride;
+            pq[u] = i < P ? md.pairs[i] : make_uint4(kNoPos, 0u, 0u, 0u);
+        }
+        uint32_t dst[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) dst[u] = pq[u].x != kNoPos ? (uint32_t)md.pos_plan[pq[u].x].z + pq[u].y : 0u;
+        int32_t lab[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            lab[u] = labels && pq[u].x != kNoPos ? point_label(fp, pq[u].z & kPidMask) : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (pq[u].x == kNoPos) continue;
+            md.srt_kv[dst[u]] = make_uint2(pq[u].z, pq[u].w);
+            // the leaf kernel's small items find the label beside the pair
+            if (labels) md.srt_lab[dst[u]] = lab[u];
+        }
     }
 }
 
@@ -779,7 +796,9 @@ __global__ __launch_bounds__(256) void k_pair_bucket(FrameParams fp, MapDev md)
 
 __global__ __launch_bounds__(256) void k_pair_bucket_batch(MapBatch mb)
 {
-    for (int i = 0; i < mb.nmaps; ++i) pair_bucket_range(mb.fps[i], mb.mds[i], blockIdx.x, gridDim.x);
+    const int i = batch_map(mb.bucket_first, mb.nmaps, blockIdx.x);
+    pair_bucket_range(mb.fps[i], mb.mds[i], blockIdx.x - mb.bucket_first[i],
+                      mb.bucket_first[i + 1] - mb.bucket_first[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1007,20 +1026,25 @@ __device__ __forceinline__ long long wave_sum_i64(long long x)
 // kl0, vl0: point index and distance of observation `lane` (lanes below
 // min(n, 64)), 0 elsewhere; the caller may have requested them ahead.
 // V consecutive floats of a record (8-byte aligned for even V), read or
-// written as pairs.
+// written as pairs.  A record is read and written once per frame while the
+// rows of the voxel's observations are read again by the neighbouring voxels:
+// the record accesses are marked streaming (non-temporal), so that they do not
+// push the rows out of L2.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
 template <int V>
 __device__ __forceinline__ void rec_load(const float *p, float (&o)[V])
 {
     if constexpr (V % 2 == 0) {
 #pragma unroll
         for (int c = 0; c < V / 2; ++c) {
-            const float2 f = ((const float2 *)p)[c];
+            const f32x2_t f = __builtin_nontemporal_load((const f32x2_t *)p + c);
             o[2 * c] = f.x;
             o[2 * c + 1] = f.y;
         }
     } else {
 #pragma unroll
-        for (int i = 0; i < V; ++i) o[i] = p[i];
+        for (int i = 0; i < V; ++i) o[i] = __builtin_nontemporal_load(p + i);
     }
 }
 
@@ -1029,10 +1053,15 @@ __device__ __forceinline__ void rec_store(float *p, const float (&o)[V])
 {
     if constexpr (V % 2 == 0) {
 #pragma unroll
-        for (int c = 0; c < V / 2; ++c) ((float2 *)p)[c] = make_float2(o[2 * c], o[2 * c + 1]);
+        for (int c = 0; c < V / 2; ++c) {
+            f32x2_t f;
+            f.x = o[2 * c];
+            f.y = o[2 * c + 1];
+            __builtin_nontemporal_store(f, (f32x2_t *)p + c);
+        }
     } else {
 #pragma unroll
-        for (int i = 0; i < V; ++i) p[i] = o[i];
+        for (int i = 0; i < V; ++i) __builtin_nontemporal_store(o[i], p + i);
     }
 }
 
@@ -1921,15 +1950,15 @@ __global__ __launch_bounds__(kLeafThreads, WAVE ? 1 : 3) void k_leaf_fuse(FrameP
     leaf_fuse_range<KMAX, WAVE, ROWS>(fp, md, sh, blockIdx.x, gridDim.x);
 }
 
-// The maps mb.subset[0 .. nsubset) of a batch, all of this kernel's kind.
+// The maps mb.subset[0 .. nsubset) of a batch, all of this kernel's kind, each
+// on its share of the grid.
 template <int KMAX, bool WAVE, bool ROWS>
 __global__ __launch_bounds__(kLeafThreads) void k_leaf_fuse_batch(MapBatch mb)
 {
     __shared__ LeafShared sh;
-    for (int q = 0; q < mb.nsubset; ++q) {
-        const int i = mb.subset[q];
-        leaf_fuse_range<KMAX, WAVE, ROWS>(mb.fps[i], mb.mds[i], sh, blockIdx.x, gridDim.x);
-    }
+    const int q = batch_map(mb.part_first, mb.nsubset, blockIdx.x), i = mb.subset[q];
+    leaf_fuse_range<KMAX, WAVE, ROWS>(mb.fps[i], mb.mds[i], sh, blockIdx.x - mb.part_first[q],
+                                      mb.part_first[q + 1] - mb.part_first[q]);
 }
 
 
@@ -2297,15 +2326,15 @@ __global__ __launch_bounds__(kLeafThreads, 3) void k_leaf_acc(FrameParams fp, Ma
     leaf_acc_range<KMAX, FR>(fp, md, sh, blockIdx.x, gridDim.x);
 }
 
-// The maps mb.subset[0 .. nsubset) of a batch (one frame each), all of this kernel's kind.
+// The maps mb.subset[0 .. nsubset) of a batch (one frame each), all of this
+// kernel's kind, each on its share of the grid.
 template <int KMAX>
 __global__ __launch_bounds__(kLeafThreads, 3) void k_leaf_acc_batch(MapBatch mb)
 {
     __shared__ AccShared<KMAX, 1> sh;
-    for (int q = 0; q < mb.nsubset; ++q) {
-        const int i = mb.subset[q];
-        leaf_acc_range<KMAX, 1>(mb.fps[i], mb.mds[i], sh, blockIdx.x, gridDim.x);
-    }
+    const int q = batch_map(mb.part_first, mb.nsubset, blockIdx.x), i = mb.subset[q];
+    leaf_acc_range<KMAX, 1>(mb.fps[i], mb.mds[i], sh, blockIdx.x - mb.part_first[q],
+                            mb.part_first[q + 1] - mb.part_first[q]);
 }
 
 // One wave per voxel descriptor of the frame (open set, wide class counts,
@@ -2386,10 +2415,9 @@ __global__ __launch_bounds__(256, combine_min_blocks(KMAX)) void k_voxel_combine
 template <int KMAX>
 __global__ __launch_bounds__(256, combine_min_blocks(KMAX)) void k_voxel_combine_batch(MapBatch mb)
 {
-    for (int q = 0; q < mb.nsubset; ++q) {
-        const int i = mb.subset[q];
-        voxel_combine_range<KMAX>(mb.fps[i], mb.mds[i], blockIdx.x, gridDim.x);
-    }
+    const int q = batch_map(mb.part_first, mb.nsubset, blockIdx.x), i = mb.subset[q];
+    voxel_combine_range<KMAX>(mb.fps[i], mb.mds[i], blockIdx.x - mb.part_first[q],
+                              mb.part_first[q + 1] - mb.part_first[q]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2660,7 +2688,7 @@ __device__ __forceinline__ void persist_combine(int kind, const FrameParams &fp,
     }
 }
 
-__global__ __launch_bounds__(256, 2) void k_batch_persistent(PersistArgs a)
+__global__ __launch_bounds__(256, 3) void k_batch_persistent(PersistArgs a)
 {
     __shared__ uint4 s_item;
     __shared__ uint32_t s_skip;
@@ -2932,14 +2960,16 @@ hipError_t launch_integrate_batched(const MapBatch &mb, const BatchPlan &plan, c
                                     hipStream_t s)
 {
     hipLaunchKernelGGL(k_ray_walk_emit_batch, dim3(std::max(plan.walk_blocks, 1)), dim3(kWalkThreads), 0, s, mb);
-    hipLaunchKernelGGL(k_leaf_plan_batch, dim3(shape.plan_blocks), dim3(256), 0, s, mb);
-    hipLaunchKernelGGL(k_pair_bucket_batch, dim3(shape.bucket_blocks), dim3(256), 0, s, mb);
+    hipLaunchKernelGGL(k_leaf_plan_batch, dim3(plan.plan_blocks), dim3(256), 0, s, mb);
+    hipLaunchKernelGGL(k_pair_bucket_batch, dim3(plan.bucket_blocks), dim3(256), 0, s, mb);
     for (int g = 0; g < plan.ngroups; ++g) {
         MapBatch sub = mb;
         sub.subset = mb.subset + plan.group_begin[g];
         sub.nsubset = plan.group_size[g];
-        launch_leaf_batch(plan.group_kind[g], sub, shape.leaf_blocks, s);
-        launch_voxel_combine_batch(plan.group_kind[g], sub, shape.leaf_blocks, s);
+        sub.part_first = mb.part_first + plan.leaf_part[g];
+        launch_leaf_batch(plan.group_kind[g], sub, plan.leaf_blocks[g], s);
+        sub.part_first = mb.part_first + plan.comb_part[g];
+        if (plan.comb_blocks[g] > 0) launch_voxel_combine_batch(plan.group_kind[g], sub, plan.comb_blocks[g], s);
     }
     hipLaunchKernelGGL(k_frame_commit_batch, dim3(plan.nmaps), dim3(256), 0, s, mb);
     return hipGetLastError();
