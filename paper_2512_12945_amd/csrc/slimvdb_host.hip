@@ -507,8 +507,10 @@ slim_status ensure_buffer1(slim_map *m, hipStream_t s)
         (r = dalloc(m, &md.items_small, cap)) || (r = dalloc(m, &md.fs, 1)))
         return r;
     HIP_OK(hipStreamCreateWithFlags(&m->wstream, hipStreamNonBlocking));
+    // these events only order work between the map's two streams on the GPU:
+    // device-scope release, no system-scope cache writeback at each record
     for (hipEvent_t *e : {&m->ev_in, &m->ev_free[0], &m->ev_free[1], &m->ev_walk[0], &m->ev_walk[1]})
-        HIP_OK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(e, hipEventDisableTiming | hipEventReleaseToDevice));
     HIP_OK(launch_reset_staging(md, s));
     m->md1 = md;
     m->pair_cap1 = 0;
@@ -1275,7 +1277,9 @@ slim_status slim_profile_enable(slim_map *m, int32_t enable)
     DeviceGuard g(m->cfg.device);
     if (enable && m->ev.empty()) {
         m->ev.resize((size_t)kProfRing * 2 * kNumProfiled);
-        for (auto &e : m->ev) HIP_OK(hipEventCreate(&e));
+        // device-scope release: the stage brackets time the kernels, not
+        // system-scope cache writebacks
+        for (auto &e : m->ev) HIP_OK(hipEventCreateWithFlags(&e, hipEventReleaseToDevice));
     }
     m->prof = enable != 0;
     return SLIM_OK;
