@@ -1587,6 +1587,30 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
         }
     }
     __syncthreads();
+    if (WAVE && ok && lead) {
+        // the leaf's item that inserts it also lists all its touched voxels for
+        // the wave combine, in offset order at consecutive entries, so that the
+        // voxels of one leaf (which share observations) are combined at the
+        // same time; every item of the leaf has its histogram, so the voxel's
+        // sorted pairs start at bucket position bin0[o] whichever item sorts them
+        if (tid == 0) {
+            uint32_t t = 0;
+            for (int q = 0; q < kMaskWords; ++q) t += __popc(sh.touch[q]);
+            sh.chunk_end = atomicAdd(&md.fs->n_vox.v, t);  // (free until the runs below)
+        }
+        __syncthreads();
+        const uint32_t vbase = sh.chunk_end;
+        for (uint32_t o = tid; o < (uint32_t)kLeafVoxels; o += blockDim.x) {
+            const uint32_t n_o = sh.hist[o];
+            if (!n_o) continue;
+            // rank of o among the leaf's touched offsets
+            uint32_t r = __popc(sh.touch[o >> 5] & ((1u << (o & 31)) - 1u));
+            for (uint32_t w32 = 0; w32 < (o >> 5); ++w32) r += __popc(sh.touch[w32]);
+            const uint32_t rec = (uint32_t)sh.pages[o >> 6] * kPageVoxels + (o & (kPageVoxels - 1));
+            const uint32_t existed = (sh.occ0[o >> 5] >> (o & 31)) & 1u;
+            md.vox_list[vbase + r] = make_uint4(rec, n_o | (existed << 31), bstart + sh.bin0[o], 0u);
+        }
+    }
     const uint32_t lo_all = sh.bin0[ob], hi_all = oe < (uint32_t)kLeafVoxels ? sh.bin0[oe] : n;
     const bool small = whole_small || (slab >= 0 && hi_all - lo_all <= (uint32_t)kLeafLdsPairs);
     if (tid == 0) {
@@ -1690,38 +1714,12 @@ __device__ __forceinline__ void fuse_item(const FrameParams &fp, const MapDev &m
         __syncthreads();
         if (ok && WAVE) {
             // wave combines run in their own kernel over every voxel of the frame:
-            // the sorted pairs go to the pair buffers at their bucket positions,
-            // and each touched voxel of the run gets a descriptor
+            // the sorted pairs go to the pair buffers at their bucket positions
             if (fits)
                 for (uint32_t t = tid; t < hi - lo; t += blockDim.x) {
                     md.pair_key[bstart + lo + t] = sh.a_key[t];
                     md.pair_tsdf[bstart + lo + t] = sh.a_val[t];
                 }
-            uint32_t cnt = 0;
-            for (uint32_t w32 = o0 >> 5; w32 <= ((o1 - 1) >> 5); ++w32) {
-                uint32_t bits = sh.touch[w32];
-                if ((w32 << 5) < o0) bits &= ~0u << (o0 & 31);
-                if (((w32 + 1) << 5) > o1) bits &= (o1 & 31) ? ((1u << (o1 & 31)) - 1u) : ~0u;
-                cnt += __popc(bits);
-            }
-            if (tid == 0) sh.chunk_end = atomicAdd(&md.fs->n_vox.v, cnt);
-            __syncthreads();
-            const uint32_t vbase = sh.chunk_end;
-            for (uint32_t o = o0 + tid; o < o1; o += blockDim.x) {
-                const uint32_t n_o = sh.hist[o];
-                if (!n_o) continue;
-                // rank of o among the touched offsets of [o0, o1)
-                uint32_t r = 0;
-                for (uint32_t w32 = o0 >> 5; w32 <= (o >> 5); ++w32) {
-                    uint32_t bits = sh.touch[w32];
-                    if ((w32 << 5) < o0) bits &= ~0u << (o0 & 31);
-                    if (w32 == (o >> 5)) bits &= (1u << (o & 31)) - 1u;
-                    r += __popc(bits);
-                }
-                const uint32_t rec = (uint32_t)sh.pages[o >> 6] * kPageVoxels + (o & (kPageVoxels - 1));
-                const uint32_t existed = (sh.occ0[o >> 5] >> (o & 31)) & 1u;
-                md.vox_list[vbase + r] = make_uint4(rec, n_o | (existed << 31), bstart + sh.bin0[o], 0u);
-            }
         } else if (ok) {
             // sorted pairs of bin o sit at keys[bin0[o] - base]
             const uint32_t *ck = fits ? sh.a_key : md.pair_key + bstart;
