@@ -238,6 +238,7 @@ struct LaunchShape {
     int walk_chunk;     // persistent: walk blocks (256 rays each) per ray-chunk item
     int wave_pairs;     // leaf tiles (MapDev::wave_pairs, slab_pairs)
     int slab_pairs;
+    int cus;            // compute units of the map's GPU
 };
 
 // Host view of a batched launch: the leaf kernel is launched once per group of
@@ -256,6 +257,7 @@ struct BatchPlan {
 constexpr int kLeafKinds = 17;  // variants of the leaf kernel (leaf_kernel_kind)
 int leaf_kernel_kind(const FrameParams &fp);
 __host__ __device__ int voxel_combine_arg(int kind);
+int combine_blocks(int kind, const LaunchShape &shape);
 hipError_t launch_integrate_batched(const MapBatch &mb, const BatchPlan &plan, const LaunchShape &shape,
                                     hipStream_t s);
 

@@ -75,7 +75,7 @@ constexpr int kMaxWalkChunk = 64;
 
 static LaunchShape default_shape(int cus)
 {
-    return {cus, cus * 16, cus * 8, 1, 4, 0, 0};
+    return {cus, cus * 16, cus * 8, 1, 4, 0, 0, cus};
 }
 
 struct slim_map {
@@ -1024,7 +1024,8 @@ slim_status slim_set_launch_shape(slim_map *m, const slim_launch_shape *shape)
     const LaunchShape d = default_shape(m->cus);
     m->shape = {shape->plan_blocks, shape->bucket_blocks, shape->leaf_blocks_per_cu * m->cus,
                 shape->batch_mode == 0 ? d.persistent : (shape->batch_mode == 1 ? 1 : 0),
-                shape->walk_chunk > 0 ? shape->walk_chunk : d.walk_chunk, shape->wave_pairs, shape->slab_pairs};
+                shape->walk_chunk > 0 ? shape->walk_chunk : d.walk_chunk, shape->wave_pairs, shape->slab_pairs,
+                m->cus};
     m->pass_frames = shape->pass_frames > 0 ? shape->pass_frames : kDefaultPassFrames;
     return SLIM_OK;
 }
@@ -1100,7 +1101,7 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
             c[1] = share(shape.plan_blocks, i, 0xFFFFu);
             c[2] = share(shape.bucket_blocks, i, 0xFFFFu);
             c[3] = share(shape.leaf_blocks, i, leaf_cap);
-            c[4] = voxel_combine_arg(kinds[i]) != -2 ? share(shape.leaf_blocks, i, 0xFFFFu) : 0u;
+            c[4] = voxel_combine_arg(kinds[i]) != -2 ? share(combine_blocks(kinds[i], shape), i, 0xFFFFu) : 0u;
             c[5] = 1;
             // the commit sums the statistics of this many leaf-tile items
             mds[i].leaf_blocks = (int)c[3];
@@ -1159,7 +1160,7 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
             plan.comb_part[g] = (int)part.size();
             plan.comb_blocks[g] = 0;
             if (voxel_combine_arg(plan.group_kind[g]) != -2) {
-                plan.comb_blocks[g] = std::max(shape.leaf_blocks, gs);
+                plan.comb_blocks[g] = std::max(combine_blocks(plan.group_kind[g], shape), gs);
                 share(gm, gs, plan.comb_blocks[g], part);
             }
         }

@@ -2800,6 +2800,16 @@ int leaf_kernel_kind(const FrameParams &fp)
     return fp.K > 24 ? 4 : (fp.K > 16 ? 3 : (fp.K > 8 ? 2 : 1));
 }
 
+// Grid of the wave combine.  Its blocks take equal static shares of the
+// voxels, so the kinds built for 3 or 4 workgroups per CU (L = 256, 512 as
+// whole words) run two rounds of what the CUs hold at once, the others the leaf
+// kernel's grid.
+int combine_blocks(int kind, const LaunchShape &shape)
+{
+    const int k = voxel_combine_arg(kind);
+    return (k == 4 || k == 8) ? 2 * combine_min_blocks(k) * shape.cus : shape.leaf_blocks;
+}
+
 static void launch_voxel_combine(int kind, const FrameParams &fp, const MapDev &md, int blocks, hipStream_t s)
 {
     const dim3 gl(blocks), bl(256);
@@ -2917,7 +2927,7 @@ hipError_t launch_integrate(const FrameParams &fp, const MapDev &md_in, const La
     launch_leaf(kind, fp, md, shape.leaf_blocks, s);
     rec(7);
     rec(8);
-    launch_voxel_combine(kind, fp, md, shape.leaf_blocks, s);
+    launch_voxel_combine(kind, fp, md, combine_blocks(kind, shape), s);
     rec(9);
     rec(10);
     hipLaunchKernelGGL(k_frame_commit, dim3(1), dim3(256), 0, s, fp, md);
@@ -2949,7 +2959,7 @@ hipError_t launch_after_walk(const FrameParams &fp, const MapDev &md_in, const L
     hipLaunchKernelGGL(k_pair_bucket, dim3(bb), dim3(256), 0, s, fp, md);
     const int kind = leaf_kernel_kind(fp);
     launch_leaf(kind, fp, md, shape.leaf_blocks, s);
-    launch_voxel_combine(kind, fp, md, shape.leaf_blocks, s);
+    launch_voxel_combine(kind, fp, md, combine_blocks(kind, shape), s);
     hipLaunchKernelGGL(k_frame_commit, dim3(1), dim3(256), 0, s, fp, md);
     return hipGetLastError();
 }
