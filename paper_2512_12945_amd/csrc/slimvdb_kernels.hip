@@ -2396,6 +2396,63 @@ __device__ __forceinline__ void voxel_combine_range(const FrameParams &fp, const
     }
 }
 
+// The wave combine of the maps mb.subset[0 .. nsubset) of a batch in one
+// launch: their voxel lists are taken as one list, map after map, and the
+// whole grid strides over it as voxel_combine_range does over one map's, so
+// that the work spreads evenly whatever the maps' sizes.
+constexpr int kMaxBatchMaps = 1024;
+template <int KMAX>
+__device__ __forceinline__ void voxel_combine_maps(const MapBatch &mb, uint32_t blk, uint32_t nblk)
+{
+    __shared__ uint32_t pre[kMaxBatchMaps + 1];  // first voxel of each map in the joint list, then the total
+    __shared__ uint32_t wsum[4];
+    const int ns = min(mb.nsubset, kMaxBatchMaps), tid = threadIdx.x;
+    uint32_t c[4], t = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int q = tid * 4 + u;
+        c[u] = q < ns ? mb.mds[mb.subset[q]].fs->n_vox.v : 0u;
+        t += c[u];
+    }
+    const uint32_t incl = wave_incl_scan(t);
+    if (lane_id() == 63) wsum[tid >> 6] = incl;
+    __syncthreads();
+    uint32_t run = incl - t;
+    for (int w = 0; w < (tid >> 6); ++w) run += wsum[w];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int q = tid * 4 + u;
+        if (q < ns) pre[q] = run;
+        run += c[u];
+    }
+    if (tid == 0) pre[ns] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    const uint32_t nv = pre[ns];
+    const uint32_t nw = blockDim.x >> 6, w = tid >> 6;
+    // the XCD deal of voxel_combine_range
+    const uint32_t r = blk % 8, qb = nblk / 8, m = nblk % 8;
+    const uint32_t vb = r * qb + min(r, m) + blk / 8;
+    const uint32_t step = nblk * nw;
+    int q = 0;
+    for (uint32_t v = vb * nw + w; v < nv; v += step) {
+        while (pre[q + 1] <= v) ++q;  // the map of joint voxel v (pre[ns] = nv > v)
+        const int i = mb.subset[q];
+        const MapDev &md = mb.mds[i];
+        const FrameParams &fp = mb.fps[i];
+        const uint4 d = md.vox_list[v - pre[q]];
+        const uint32_t n = d.y & 0x7FFFFFFFu;
+        const bool existed = (d.y >> 31) != 0u;
+        const uint32_t *keys = md.pair_key + d.z;
+        const float *vals = md.pair_tsdf + d.z;
+        if constexpr (KMAX > 0)
+            combine_wave_vec<(KMAX > 0 ? KMAX : 1)>(fp, md, keys, vals, n, (long long)d.x, existed);
+        else if constexpr (KMAX < 0)
+            combine_last_wave(fp, md, keys, vals, n, (long long)d.x, existed);
+        else
+            combine_wave(fp, md, keys, vals, n, (long long)d.x, existed);
+    }
+}
+
 // Workgroups per CU the combine kernels are built for: the vectorised kinds are
 // bound by the latency of their row gathers, so they keep enough waves in
 // flight (register budgets 72, 100, 128, 168 for L = 64, 128, 256, 512).
@@ -2413,9 +2470,7 @@ __global__ __launch_bounds__(256, combine_min_blocks(KMAX)) void k_voxel_combine
 template <int KMAX>
 __global__ __launch_bounds__(256, combine_min_blocks(KMAX)) void k_voxel_combine_batch(MapBatch mb)
 {
-    const int q = batch_map(mb.part_first, mb.nsubset, blockIdx.x), i = mb.subset[q];
-    voxel_combine_range<KMAX>(mb.fps[i], mb.mds[i], blockIdx.x - mb.part_first[q],
-                              mb.part_first[q + 1] - mb.part_first[q]);
+    voxel_combine_maps<KMAX>(mb, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
