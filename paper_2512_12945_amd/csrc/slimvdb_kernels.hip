@@ -1070,7 +1070,11 @@ __device__ __forceinline__ void combine_wave_vec_t(const FrameParams &fp, const 
                                                    const float *vals, uint32_t n, long long rec, bool existed,
                                                    uint32_t kl0, float vl0)
 {
-    constexpr int B = V >= 16 ? 4 : 8;
+    // observations per batch of rows: fewer for L = 256 (few observations per
+    // voxel), whose kernel runs more waves instead; a batch never crosses a
+    // group of 64 observations (the lanes' point indices are reloaded there)
+    constexpr int B = V >= 16 || V == 4 ? 4 : 8;
+    static_assert(64 % B == 0, "batches tile the 64-observation groups");
     const int lane = lane_id();
     float *R = md.vox + (size_t)rec * md.rec_stride;
     // (up to 8 components per lane) the voxel's record is requested with the rows
@@ -2352,8 +2356,8 @@ __device__ __forceinline__ void voxel_combine_range(const FrameParams &fp, const
     const uint32_t r = blk % 8, q = nblk / 8, m = nblk % 8;
     const uint32_t vb = r * q + min(r, m) + blk / 8;
     const uint32_t step = nblk * nw;
-    if constexpr (KMAX > 0) {
-        // a wave's voxels one after another, each one's descriptor requested
+    if constexpr (KMAX >= 8) {
+        // L >= 512: a wave's voxels one after another, each one's descriptor requested
         // two voxels ahead and its observations' point indices and distances
         // one voxel ahead, so that only the rows and the record are waited
         // for (indices past the end read the wave's first voxel again)
@@ -2382,13 +2386,18 @@ __device__ __forceinline__ void voxel_combine_range(const FrameParams &fp, const
             dn = dnn;
         }
     } else {
+        // the other kinds one voxel at a time: for L <= 256 (few observations
+        // per voxel) requesting ahead gains nothing and costs the registers
+        // of more waves
         for (uint32_t v = vb * nw + w; v < nv; v += step) {
             const uint4 d = md.vox_list[v];
             const uint32_t n = d.y & 0x7FFFFFFFu;
             const bool existed = (d.y >> 31) != 0u;
             const uint32_t *keys = md.pair_key + d.z;
             const float *vals = md.pair_tsdf + d.z;
-            if (KMAX < 0)
+            if constexpr (KMAX > 0)
+                combine_wave_vec<(KMAX > 0 ? KMAX : 1)>(fp, md, keys, vals, n, (long long)d.x, existed);
+            else if constexpr (KMAX < 0)
                 combine_last_wave(fp, md, keys, vals, n, (long long)d.x, existed);
             else
                 combine_wave(fp, md, keys, vals, n, (long long)d.x, existed);
@@ -2454,11 +2463,11 @@ __device__ __forceinline__ void voxel_combine_maps(const MapBatch &mb, uint32_t 
 }
 
 // Workgroups per CU the combine kernels are built for: the vectorised kinds are
-// bound by the latency of their row gathers, so they keep enough waves in
-// flight (register budgets 72, 100, 128, 168 for L = 64, 128, 256, 512).
+// bound by the latency of their row and record accesses, so they keep enough
+// waves in flight (register budgets 72, 100, 72, 168 for L = 64, 128, 256, 512).
 __host__ __device__ constexpr int combine_min_blocks(int kmax)
 {
-    return kmax == 1 ? 7 : (kmax == 2 ? 5 : (kmax == 4 ? 4 : (kmax == 8 ? 3 : 1)));
+    return kmax == 1 ? 7 : (kmax == 2 ? 5 : (kmax == 4 ? 7 : (kmax == 8 ? 3 : 1)));
 }
 
 template <int KMAX>
@@ -2856,7 +2865,7 @@ int leaf_kernel_kind(const FrameParams &fp)
 }
 
 // Grid of the wave combine.  Its blocks take equal static shares of the
-// voxels, so the kinds built for 3 or 4 workgroups per CU (L = 256, 512 as
+// voxels, so the kinds built for 3 or 7 workgroups per CU (L = 512, 256 as
 // whole words) run two rounds of what the CUs hold at once, the others the leaf
 // kernel's grid.
 int combine_blocks(int kind, const LaunchShape &shape)
