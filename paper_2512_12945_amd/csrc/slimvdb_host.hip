@@ -1101,7 +1101,7 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
             c[1] = share(shape.plan_blocks, i, 0xFFFFu);
             c[2] = share(shape.bucket_blocks, i, 0xFFFFu);
             c[3] = share(shape.leaf_blocks, i, leaf_cap);
-            c[4] = voxel_combine_arg(kinds[i]) != -2 ? share(combine_blocks(kinds[i], shape), i, 0xFFFFu) : 0u;
+            c[4] = voxel_combine_arg(kinds[i]) != -2 ? share(shape.leaf_blocks, i, 0xFFFFu) : 0u;
             c[5] = 1;
             // the commit sums the statistics of this many leaf-tile items
             mds[i].leaf_blocks = (int)c[3];
