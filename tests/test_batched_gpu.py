@@ -103,3 +103,45 @@ def test_launch_shape_does_not_change_results(workload, shape):
         m.integrate(f["points"], f["pose"], f["sem"], f["kind"])
     for i in range(len(w)):
         _same(extract_np(ref[i]), extract_np(alt[i]))
+
+
+@pytest.mark.parametrize("L", [256, 512])
+def test_joint_combine_list_over_maps_of_one_kind(L):
+    """Several maps of one vectorised wave-combine kind in one batched call:
+    the combine takes their voxel lists as one.  A map whose frame has no
+    valid point (no voxel) sits between the others.  Bitwise equal to one
+    call per map, on first frames and on frames into existing voxels, eager
+    and from a graph."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sv.load()
+    sc = synth.StreetScene(seed=2, beams=128)
+    rng = np.random.default_rng(L)
+    frames = []
+    for j in range(4):
+        t = int(rng.integers(0, 100))
+        sw = sc.sweep(t, nrays=int(rng.integers(3_000, 12_000)))
+        pts = sw["points"].copy()
+        if j == 1:
+            pts[:] = np.nan  # every point rejected: the map lists no voxel
+        emb = synth.primitive_embeddings(sc, sw["prim"], L, 7 + j, t)
+        frames.append(dict(points=cuda(pts), pose=sw["pose"], sem=cuda(emb), kind=sv.IN_EMB_BF16))
+
+    def maps():
+        return [sv.Map(0.1, 0.3, 0.0, 50.0, sv.SEM_OPEN, 0, L, 0, 1 << 14, 1 << 21) for _ in frames]
+
+    seq, bat, gra = maps(), maps(), maps()
+    for rep in range(2):
+        for m, f in zip(seq, frames):
+            m.integrate(f["points"], f["pose"], f["sem"], f["kind"])
+        sv.integrate_batched(bat, frames, use_graph=False)
+        sv.integrate_batched(gra, frames, use_graph=True)
+        torch.cuda.synchronize()
+        for i in range(len(frames)):
+            a, b, c = seq[i].stats(), bat[i].stats(), gra[i].stats()
+            assert a == b == c, (rep, i, a, b, c)
+            ea = extract_np(seq[i])
+            _same(ea, extract_np(bat[i]))
+            _same(ea, extract_np(gra[i]))
+        _say(f"L={L} rep {rep}: voxels per map {[s.stats()['voxels'] for s in seq]}")
+    assert seq[1].stats()["voxels"] == 0 and min(seq[i].stats()["voxels"] for i in (0, 2, 3)) > 0
