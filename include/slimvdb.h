@@ -304,8 +304,8 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
  * statistics afterwards are the same as after count calls of slim_integrate /
  * slim_integrate_rays (bit for bit).  Geometry-only and label maps (int32
  * labels, at most 32 classes, Bayesian mode) take consecutive frames in
- * multi-frame passes (up to slim_launch_shape.pass_frames and at most 4,
- * default 4; the last frame alone): one ray walk over all their rays, one
+ * multi-frame passes (up to slim_launch_shape.pass_frames, at most 8,
+ * default 8; the last frame alone): one ray walk over all their rays, one
  * plan, bucketing, leaf kernel and commit, each voxel applying its frames'
  * observations frame by frame, Eq. (1)-(2) and Eq. (6) as for a frame alone.  This form returns after
  * the GPU has finished the call's work: a pass that exceeds the map's
@@ -323,7 +323,7 @@ slim_status slim_integrate_sequence(slim_map *map, const slim_frame *frames_host
 /* Grid sizes of the grid-stride kernels of integration: leaf planning and pair
  * bucketing blocks, and leaf-kernel blocks per compute unit (1 .. 32); and
  * pass_frames, the most frames slim_integrate_sequence takes in one pass
- * (0: the default 4, 1: one at a time, at most 8; passes take at most 4).
+ * (0: the default 8, 1: one at a time, at most 8).
  * batch_mode picks the form of slim_integrate_batched: 1 one persistent launch
  * whose workgroups take ray-chunk, planning, bucketing, leaf-tile, combine and
  * commit items of every map from a queue, 2 one launch per stage, 0 the

@@ -28,7 +28,7 @@ constexpr int kLeafThreads = 256;
 constexpr int kLeafBatch = 8;                // loads in flight per thread in the leaf kernel
 constexpr int kLeafLdsPairs = kLeafBatch * kLeafThreads;  // pairs a leaf holds in LDS at once
 constexpr int kNumProfiled = 6;  // timed stages: walk, plan, bucketing, leaf kernel, voxel combine, commit
-constexpr int kAccFrames = 4;        // frames of a pass the accumulating leaf kernel takes
+constexpr int kAccFrames = 8;        // frames of a pass the accumulating leaf kernel takes
 constexpr int kAccWavePairs = 128;   // accumulated leaves with at most this many pairs are one wave's work
 constexpr int kPassFrames = 8;               // most frames integrated in one pass
 constexpr int kMaxLeafBlocksPerCu = 32;

@@ -70,7 +70,7 @@ struct BatchCtx {
     int persist_blocks = 0;       // workgroups of the persistent launch (all resident)
 };
 
-constexpr int kDefaultPassFrames = 4;
+constexpr int kDefaultPassFrames = 8;
 constexpr int kMaxWalkChunk = 64;
 
 static LaunchShape default_shape(int cus)

@@ -2909,13 +2909,14 @@ static void launch_leaf(int kind, const FrameParams &fp, const MapDev &md, int b
     const dim3 gl(blocks), bl(kLeafThreads);
     if (kind <= 4) {
         // accumulating kernel with one set of accumulators per frame of the pass
-        const int fr = fp.nsub <= 1 ? 1 : (fp.nsub == 2 ? 2 : 4);
+        const int fr = fp.nsub <= 1 ? 1 : (fp.nsub == 2 ? 2 : (fp.nsub <= 4 ? 4 : 8));
         const int kmax = kind * 8;
 #define SLIM_ACC(K, F) \
     if (kmax == K && fr == F) hipLaunchKernelGGL((k_leaf_acc<K, F>), gl, bl, 0, s, fp, md);
         SLIM_ACC(0, 1) SLIM_ACC(0, 2) SLIM_ACC(0, 4) SLIM_ACC(8, 1) SLIM_ACC(8, 2) SLIM_ACC(8, 4)
         SLIM_ACC(16, 1) SLIM_ACC(16, 2) SLIM_ACC(16, 4) SLIM_ACC(24, 1) SLIM_ACC(24, 2) SLIM_ACC(24, 4)
-        SLIM_ACC(32, 1) SLIM_ACC(32, 2) SLIM_ACC(32, 4)
+        SLIM_ACC(32, 1) SLIM_ACC(32, 2) SLIM_ACC(32, 4) SLIM_ACC(0, 8) SLIM_ACC(8, 8) SLIM_ACC(16, 8)
+        SLIM_ACC(24, 8) SLIM_ACC(32, 8)
 #undef SLIM_ACC
         return;
     }
