@@ -99,7 +99,7 @@ def _stats_status(m):
         return m.stats(), e.code
 
 
-@pytest.mark.parametrize("pass_frames", [1, 2, 3, 8])
+@pytest.mark.parametrize("pass_frames", [1, 2, 3, 5, 8])
 def test_sequence_pass_sizes(sweeps, pass_frames):
     # geometry and label maps take consecutive frames in multi-frame passes:
     # every pass size gives the per-frame map and the last frame's statistics
