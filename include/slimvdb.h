@@ -321,7 +321,7 @@ slim_status slim_integrate_batched(slim_map *const *maps, int32_t nmaps, const s
 slim_status slim_integrate_sequence(slim_map *map, const slim_frame *frames_host, int32_t count, void *stream);
 
 /* Grid sizes of the grid-stride kernels of integration: leaf planning and pair
- * bucketing blocks, and leaf-kernel blocks per compute unit (1 .. 32); and
+ * bucketing blocks, and leaf-kernel blocks per compute unit (1 .. 32; default 16); and
  * pass_frames, the most frames slim_integrate_sequence takes in one pass
  * (0: the default 8, 1: one at a time, at most 8).
  * batch_mode picks the form of slim_integrate_batched: 1 one persistent launch

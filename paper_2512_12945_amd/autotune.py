@@ -40,7 +40,7 @@ def axes(cus):
     return {
         "batch_mode": [1, 2],
         "walk_chunk": [4, 1, 2, 8, 16],
-        "leaf_blocks_per_cu": [8, 2, 4, 16, 32],
+        "leaf_blocks_per_cu": [16, 2, 4, 8, 32],
         "bucket_blocks": [16 * cus, 2 * cus, 4 * cus, 32 * cus],
         "plan_blocks": [cus, max(cus // 2, 1), 2 * cus],
         "wave_pairs": [0, 32, 64, 128],
@@ -57,7 +57,7 @@ def key_of(cfgs, frames):
     mix = sorted((c["sem_mode"], c.get("num_classes", 0), c.get("embed_dim", 0)) for c in cfgs)
     n = [int((f.get("points") if f.get("points") is not None else f["ranges"]).shape[0]) for f in frames]
     bucket = int(round(math.log2(max(sum(n) / max(len(n), 1), 1))))
-    return f"v2|{getattr(props, 'gcnArchName', props.name)}|{len(cfgs)}|{mix}|{bucket}"
+    return f"v3|{getattr(props, 'gcnArchName', props.name)}|{len(cfgs)}|{mix}|{bucket}"
 
 
 def _load(path):

@@ -75,7 +75,7 @@ constexpr int kMaxWalkChunk = 64;
 
 static LaunchShape default_shape(int cus)
 {
-    return {cus, cus * 16, cus * 8, 1, 4, 0, 0, cus};
+    return {cus, cus * 16, cus * 16, 1, 4, 0, 0, cus};
 }
 
 struct slim_map {
@@ -318,7 +318,7 @@ slim_status slim_map_create(const slim_map_config *config, slim_map **out)
     md.max_leaves = config->max_leaves;
     md.max_pages = (config->max_voxels + kPageVoxels - 1) / kPageVoxels;
     md.rec_stride = record_stride(m->nsem);
-    md.leaf_blocks = m->cus * 8;
+    md.leaf_blocks = m->cus * 16;
     md.wave_pairs = 0;
     md.slab_pairs = 0;
     const size_t L = (size_t)config->max_leaves, NP = (size_t)md.max_pages;

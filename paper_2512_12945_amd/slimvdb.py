@@ -263,7 +263,7 @@ class Map:
             cus = torch.cuda.get_device_properties(self.device).multi_processor_count
             sh = LaunchShape(cus if plan_blocks is None else plan_blocks,
                              16 * cus if bucket_blocks is None else bucket_blocks,
-                             8 if leaf_blocks_per_cu is None else leaf_blocks_per_cu, int(pass_frames),
+                             16 if leaf_blocks_per_cu is None else leaf_blocks_per_cu, int(pass_frames),
                              int(batch_mode), int(walk_chunk), int(wave_pairs), int(slab_pairs))
             _check(self._L.slim_set_launch_shape(self.h, ctypes.byref(sh)))
 
